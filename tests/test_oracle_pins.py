@@ -1,0 +1,239 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Every test here is CPU-only ("not gpu").  The oracle is checked against:
+  * the closed-form spectrum 2 - 2cos(j*pi/(n+1)) of tridiag(-1,2,-1), for
+    every shift of a grid including shifts 1e-9 away from eigenvalues, through
+    the hierarchical path both with fill-in (eta = 0.5: neighbouring leaves
+    are near, second neighbours admissible) and without (eta = 1: the
+    generalized HSS path);
+  * LAPACK dense inertia of the assembled H^2 matrix A~ and of the exact
+    kernel matrix A on the cube workload;
+  * an independent cyclic Jacobi eigensolver;
+  * Algorithm 1's error bound and step count, on the closed form at n = 2^20;
+  * mutation checks: a plausible mistake planted in the oracle must fail one
+    of these pins.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import factor as OF
+from oracle.bisect import bisect_kth, expected_steps, gershgorin, kth_eigs
+from oracle.build import H2, estimate_norm, pivoted_rows_id
+from oracle.dense import dense_inertia, jacobi_eigvalsh, tridiag_eigs, tridiag_inertia
+from oracle.kernels import Kernel
+from paper_2311_08618_amd import workloads as W
+
+
+def _tridiag_h2(n, leaf, eta):
+    return H2(W.line_points(n), Kernel(4, 2.0, 1.0), leaf, eta, 1e-12, cap=n)
+
+
+def _shift_grid_near_eigs(lam, count=25, seed=3):
+    rng = np.random.default_rng(seed)
+    # generic shifts (an exactly singular pivot block is a breakdown, not a count)
+    sig = list(np.linspace(-0.2, 4.2, count) + 1e-3 * math.sqrt(2.0))
+    for j in rng.integers(0, len(lam), 8):
+        sig += [lam[j] - 1e-9, lam[j] + 1e-9]
+    return np.array(sig)
+
+
+@pytest.mark.parametrize("eta", [0.5, 1.0])
+@pytest.mark.parametrize("n,leaf", [(256, 16), (300, 16), (97, 8)])
+def test_tridiag_closed_form_every_shift(n, leaf, eta):
+    H = _tridiag_h2(n, leaf, eta)
+    lam = tridiag_eigs(n)
+    for s in _shift_grid_near_eigs(lam):
+        assert OF.inertia(H, s) == tridiag_inertia(n, s) == int(np.sum(lam < s)), s
+
+
+def test_tridiag_fill_in_path_is_exercised():
+    """With eta = 0.5 the far field is exactly zero (r = 0 at every leaf) and
+    every rank the factorization keeps comes from fill-in recompression."""
+    H = _tridiag_h2(256, 16, 0.5)
+    assert max(H.r[H.tree.L]) == 0
+    st = {}
+    OF.inertia(H, 1.3, st)
+    assert max(st["t"][0]) >= 1
+    H1 = _tridiag_h2(256, 16, 1.0)
+    assert all(len(v) == 1 for v in H1.tree.near[H1.tree.L])   # HSS: only diagonal blocks dense
+    assert max(H1.r[H1.tree.L]) == 2
+
+
+def test_tridiag_closed_form_inertia_helper():
+    for n in (1, 2, 7, 64, 1000):
+        lam = tridiag_eigs(n)
+        for s in np.linspace(-1, 5, 61) + 1e-7 * math.pi:
+            assert tridiag_inertia(n, s) == int(np.sum(lam < s))
+
+
+def test_jacobi_against_closed_form_and_lapack():
+    n = 40
+    A = 2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    assert np.max(np.abs(jacobi_eigvalsh(A) - tridiag_eigs(n))) < 1e-12
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((30, 30))
+    B = B + B.T
+    assert np.max(np.abs(jacobi_eigvalsh(B) - np.linalg.eigvalsh(B))) < 1e-11
+
+
+@pytest.fixture(scope="module")
+def cube_h2():
+    X = W.cube_points(1024, 0)
+    k = Kernel(0, 1e3)
+    H = H2(X, k, 64, 1.0, 1e-8)
+    Ah = H.dense()
+    A = k.dense(X)
+    return H, A, Ah, np.linalg.eigvalsh(Ah), np.linalg.eigvalsh(A)
+
+
+def test_construction_error_and_orthonormality(cube_h2):
+    H, A, Ah, _, _ = cube_h2
+    assert np.linalg.norm(A - Ah, 2) <= 10 * H.eps * H.normA
+    for l in range(H.tree.L + 1):
+        for Q in H.Q[l]:
+            if Q.size:
+                assert np.max(np.abs(Q.T @ Q - np.eye(Q.shape[0]))) < 1e-13
+    # normA estimate (mean row sum) is a lower bound of ||A||_2 within a few %
+    nrm = np.linalg.norm(A, 2)
+    assert 0.9 * nrm <= H.normA <= nrm * (1 + 1e-12)
+
+
+def test_cube_inertia_matches_dense(cube_h2):
+    H, A, Ah, ev_h, ev_a = cube_h2
+    w = 1e3 * H.tau
+    sig = np.quantile(ev_h, np.linspace(0.0, 1.0, 21))
+    sig = np.concatenate([sig + 0.37 * w, [ev_h[0] - 1.0, ev_h[-1] + 1.0]])
+    checked = 0
+    for s in sig:
+        nu = OF.inertia(H, s)
+        lo, hi = int(np.sum(ev_h < s - w)), int(np.sum(ev_h < s + w))
+        assert lo <= nu <= hi
+        if lo == hi:
+            assert nu == dense_inertia(Ah, s) == int(np.sum(ev_a < s))
+            checked += 1
+    assert checked >= 3
+    assert OF.inertia(H, ev_h[0] - 1.0) == 0
+    assert OF.inertia(H, ev_h[-1] + 1.0) == H.tree.n
+
+
+def test_cube_inertia_monotone(cube_h2):
+    H = cube_h2[0]
+    sig = np.linspace(900.0, 1100.0, 9)
+    nus = [OF.inertia(H, s) for s in sig]
+    assert all(a <= b for a, b in zip(nus, nus[1:]))
+
+
+def test_kth_eig_cube_vs_lapack(cube_h2):
+    H, A, Ah, ev_h, ev_a = cube_h2
+    tol = 1e-3
+    ks = [1, 512]
+    lam = kth_eigs(H, ks, tol)
+    for k, l in zip(ks, lam):
+        assert abs(l - ev_a[k - 1]) <= tol / 2 + 10 * H.eps * H.normA
+
+
+def test_bisection_closed_form_large_n():
+    n = 1 << 20
+    lam = tridiag_eigs(n)
+    for k in (1, 7, n // 3, n // 2, n):
+        tol = 1e-9
+        a, b = -0.5, 4.5
+        est, (ak, bk), steps = bisect_kth(lambda mu: tridiag_inertia(n, mu), k, a, b, tol)
+        assert abs(est - lam[k - 1]) < tol / 2
+        assert ak <= lam[k - 1] <= bk and bk - ak < tol
+        assert steps == expected_steps(b - a, tol) == math.floor(math.log2((b - a) / tol)) + 1
+
+
+def test_bisection_cache_narrows_and_agrees():
+    n = 1000
+    lam = tridiag_eigs(n)
+    nu = lambda mu: tridiag_inertia(n, mu)
+    cache = []
+    tol = 1e-10
+    first = [bisect_kth(nu, k, -0.5, 4.5, tol, cache) for k in (500,)][0]
+    later = bisect_kth(nu, 501, -0.5, 4.5, tol, cache)
+    fresh = bisect_kth(nu, 501, -0.5, 4.5, tol, None)
+    assert later[2] < fresh[2]
+    assert abs(later[0] - lam[500]) < tol / 2 and abs(first[0] - lam[499]) < tol / 2
+
+
+def test_paper_circle_accuracy():
+    """Sec. 5.1: regularised Laplace kernel on points of the unit circle,
+    eps_H2 = 1e-2 * eps_ev, eps_ev = 1e-8: every eigenvalue error stays below
+    eps_ev / 2 (n = 1024 in the paper; 512 here to keep the CPU suite short)."""
+    n = 512
+    X = W.circle_points(n)
+    k = Kernel(3, 1.0 / 1e-3, 1e-3)
+    tol = 1e-8
+    # eps_H2 is an absolute bound in the paper; tau = eps * normA, so scale eps
+    eps = 1e-2 * tol / estimate_norm(X, k)
+    H = H2(X, k, 32, 1.0, eps, cap=n)
+    ev = np.linalg.eigvalsh(k.dense(X))
+    ks = [1, n // 4, n // 2, n]
+    lam = kth_eigs(H, ks, tol, ab=(0.0, 2048.0 * 2))
+    for kk, l in zip(ks, lam):
+        assert abs(l - ev[kk - 1]) < tol / 2, (kk, l, ev[kk - 1])
+
+
+def test_gershgorin_contains_spectrum():
+    X = W.cube_points(300, 2)
+    k = Kernel(1, 1e3)
+    lo, hi = gershgorin(X, k)
+    ev = np.linalg.eigvalsh(k.dense(X))
+    assert lo <= ev[0] and ev[-1] <= hi
+
+
+def test_row_id_reproduces_low_rank():
+    rng = np.random.default_rng(0)
+    M = rng.standard_normal((40, 6)) @ rng.standard_normal((6, 90))
+    s, X = pivoted_rows_id(M, 1e-10)
+    assert len(s) == 6
+    assert np.allclose(X[s], np.eye(6))
+    assert np.linalg.norm(M - X @ M[s]) < 1e-8 * np.linalg.norm(M)
+
+
+# ---------------------------------------------------------------- mutations
+def _mutant_no_recompression(monkeypatch):
+    real_svd = np.linalg.svd
+
+    def fake_svd(a, full_matrices=True, compute_uv=True):
+        U, s, Vt = real_svd(a, full_matrices=full_matrices)
+        return U, np.zeros_like(s), Vt
+    monkeypatch.setattr(OF.np.linalg, "svd", fake_svd)
+
+
+def test_mutation_dropped_recompression_is_caught(monkeypatch):
+    """Dropping the fill-in recompression (Sec. 3.4) must break the closed-form pin."""
+    H = _tridiag_h2(256, 16, 0.5)
+    lam = tridiag_eigs(256)
+    _mutant_no_recompression(monkeypatch)
+    bad = sum(OF.inertia(H, s) != int(np.sum(lam < s)) for s in np.linspace(0.05, 3.95, 20))
+    assert bad > 0
+
+
+def test_mutation_wrong_schur_sign_is_caught(monkeypatch):
+    """A sign error in the Schur complement (Eq. blr2-diag-schur) must break a pin."""
+    H = _tridiag_h2(128, 16, 1.0)
+    lam = tridiag_eigs(128)
+    real_solve = np.linalg.solve
+    monkeypatch.setattr(OF.np.linalg, "solve", lambda a, b: -real_solve(a, b))
+    bad = sum(OF.inertia(H, s) != int(np.sum(lam < s)) for s in np.linspace(0.05, 3.95, 20))
+    assert bad > 0
+
+
+def test_mutation_transposed_transfer_is_caught(monkeypatch):
+    """Using E^T instead of E in the merge (Sec. 3.3) must break a pin."""
+    X = W.cube_points(512, 1)
+    k = Kernel(0, 1e3)
+    H = H2(X, k, 32, 1.0, 1e-8)
+    ev = np.linalg.eigvalsh(k.dense(X))
+    sig = np.quantile(ev, [0.3, 0.5, 0.7, 0.9])
+    good = [OF.inertia(H, s) for s in sig]
+    for l in range(H.tree.L):
+        H.Q[l] = [q.T.copy() for q in H.Q[l]]
+    bad = [OF.inertia(H, s) for s in sig]
+    truth = [int(np.sum(ev < s)) for s in sig]
+    assert good == truth
+    assert bad != truth
