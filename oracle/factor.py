@@ -15,10 +15,12 @@ For every cluster i, in colour-major / index-minor order:
   (i)   recompression (Sec. 3.4 displaymath): the products to concatenate are
         the R_i rows of every fill-in product that landed in row i of a
         non-near block, one product per (eliminated neighbour, block), plus
-        the R_i rows of the fill-in carried up from the level below.  Their
-        left singular vectors with singular value > tau join the skeleton:
-        the redundant coordinates are rotated by W = [U_perp | U_t] and the
-        last t of them become skeleton coordinates.  The redundant rows of the
+        the R_i rows of the fill-in carried up from the level below.  A
+        rank-revealing (column-pivoted) QR of the concatenation, truncated at
+        remaining norm <= tau, gives t directions that join the skeleton: the
+        redundant coordinates are rotated by W = [Q_perp | Q_t] (Q_t an
+        orthonormal basis of the kept directions) and the last t of them
+        become skeleton coordinates.  The redundant rows of the
         non-near blocks of row i are then dropped (the truncation).
   (ii)  pivot block P = S_ii^{RR}; its inertia is added to nu (Eq.
         blr2-diag-ldl; Sylvester's law, Sec. 2 and Sec. 4).  The oracle takes
@@ -44,6 +46,41 @@ parent level, and the embedding of the transfer matrix after rank growth.
 from __future__ import annotations
 
 import numpy as np
+
+
+def rrqr_directions(X: np.ndarray, tol: float):
+    """Rank-revealing QR of the concatenation X (R_i x ncol), Sec. 3.4.
+
+    Column-pivoted Householder QR of X^T: the pivots are coordinates of the
+    redundant part, chosen by largest remaining norm (recomputed at every
+    step, first index on ties), stopping when the largest remaining norm is
+    <= tol.  With X^T P = Q R, X ~= P R^T Q^T, so the kept directions are
+    the first t columns of P R^T.  Returns (t, P R^T[:, :t])."""
+    A = np.array(X.T, dtype=np.float64, copy=True)     # ncol x R_i
+    n, m = A.shape
+    perm = np.arange(m)
+    t = 0
+    for k in range(min(n, m)):
+        nrm = np.sqrt(np.sum(A[k:, k:] * A[k:, k:], axis=0))
+        j = int(np.argmax(nrm))
+        if not nrm[j] > tol:
+            break
+        j += k
+        if j != k:
+            A[:, [k, j]] = A[:, [j, k]]
+            perm[[k, j]] = perm[[j, k]]
+        x = A[k:, k].copy()
+        alpha = -np.copysign(np.linalg.norm(x), x[0] if x[0] != 0 else 1.0)
+        v = x
+        v[0] -= alpha
+        vn = np.dot(v, v)
+        if vn > 0:
+            A[k:, k:] -= np.outer(v, (2.0 / vn) * (v @ A[k:, k:]))
+        t = k + 1
+    Rt = np.triu(A[:t, :]).T                           # m x t, rows in pivoted order
+    At = np.zeros((m, t))
+    At[perm, :] = Rt
+    return t, At
 
 
 def _rotate(i, W, R_i, S, F, nbS, nbF):
@@ -93,10 +130,10 @@ def inertia(H, sigma: float, stats: dict | None = None) -> int:
             if Ri > 0:
                 if pending[i]:
                     Xc = np.concatenate(pending[i], axis=1)
-                    U, sv, _ = np.linalg.svd(Xc, full_matrices=True)
-                    t = int(np.sum(sv > tau))
+                    t, At = rrqr_directions(Xc, tau)
                     if t > 0:
-                        W = np.concatenate([U[:, t:], U[:, :t]], axis=1)
+                        Qc, _ = np.linalg.qr(At, mode="complete")
+                        W = np.concatenate([Qc[:, t:], Qc[:, :t]], axis=1)
                         _rotate(i, W, Ri, S, F, T.near[l][i], sorted(fnb[i]))
                         Ri -= t
                         R[i] = Ri

@@ -196,12 +196,7 @@ def test_row_id_reproduces_low_rank():
 
 # ---------------------------------------------------------------- mutations
 def _mutant_no_recompression(monkeypatch):
-    real_svd = np.linalg.svd
-
-    def fake_svd(a, full_matrices=True, compute_uv=True):
-        U, s, Vt = real_svd(a, full_matrices=full_matrices)
-        return U, np.zeros_like(s), Vt
-    monkeypatch.setattr(OF.np.linalg, "svd", fake_svd)
+    monkeypatch.setattr(OF, "rrqr_directions", lambda X, tol: (0, np.zeros((X.shape[0], 0))))
 
 
 def test_mutation_dropped_recompression_is_caught(monkeypatch):
@@ -237,3 +232,15 @@ def test_mutation_transposed_transfer_is_caught(monkeypatch):
     truth = [int(np.sum(ev < s)) for s in sig]
     assert good == truth
     assert bad != truth
+
+
+def test_rrqr_directions_span_and_bound():
+    """Recompression's rank-revealing QR: an exactly rank-5 concatenation keeps
+    5 directions spanning its column space; the dropped part is below tol."""
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((30, 5)) @ rng.standard_normal((5, 200))
+    X += 1e-12 * rng.standard_normal(X.shape)
+    t, At = OF.rrqr_directions(X, 1e-8)
+    assert t == 5
+    Q, _ = np.linalg.qr(At)
+    assert np.linalg.norm(X - Q @ (Q.T @ X)) < 1e-9
