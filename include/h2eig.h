@@ -1,0 +1,158 @@
+/*
+ * h2eig — k-th eigenvalues of a symmetric H^2 matrix on one AMD MI355X (gfx950).
+ *
+ * The method is "slicing the spectrum" (Algorithm 1 of Apriansyah & Yokota,
+ * "Computing the k-th Eigenvalue of Symmetric H^2-Matrices"): bisection on a
+ * shift sigma, where each step needs the inertia nu(A - sigma I), the number of
+ * eigenvalues below sigma (Sec. 2).  The inertia is read off the block-diagonal
+ * factor of the generalized H^2-LDL factorization of Secs. 3.2-3.4 (Sylvester's
+ * law of inertia, Sec. 4), computed level by level up the cluster tree on the GPU.
+ *
+ * Conventions for every call:
+ *   - Return value: H2_OK (0) or a negative h2_status; h2_last_error() then
+ *     returns a thread-local, NUL-terminated message (valid until the next call
+ *     on the same thread).
+ *   - Inputs are host arrays and are copied; the caller keeps ownership and may
+ *     free them after the call returns.  Outputs are caller-allocated host arrays.
+ *   - A handle owns all of its device memory until h2_free.  A handle must not be
+ *     used from two threads at once (H2_EBUSY).
+ *   - The library always runs its kernels on the GPU; if no usable gfx950 device
+ *     is present every call that needs one fails with H2_EDEVICE.
+ */
+#ifndef H2EIG_H
+#define H2EIG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct h2_matrix_s* h2_matrix;
+
+typedef enum {
+  H2_OK = 0,
+  H2_EINVAL = -1,    /* invalid argument (sizes, non-finite input, k out of range) */
+  H2_ENOMEM = -2,    /* device or host memory exhausted, or workspace cap exceeded  */
+  H2_EDEVICE = -3,   /* no usable GPU, or a HIP runtime error                       */
+  H2_ENUMERIC = -4,  /* exactly singular or non-finite pivot block for some shift   */
+  H2_EBUSY = -5      /* handle already in use by another thread                     */
+} h2_status;
+
+/* Kernel of the matrix: A_ij = f(|x_i - x_j|) for i != j, A_ii = diag.
+ * The paper's synthetic test (Sec. 5.1) is H2_K_REG_LAPLACE with p0 = 1e-3. */
+typedef enum {
+  H2_K_LAPLACE = 0,       /* 1/r                                                */
+  H2_K_YUKAWA = 1,        /* exp(-r)/r                                          */
+  H2_K_GAUSS_DAMPED = 2,  /* exp(-r^2/p0) / (r + p1)                            */
+  H2_K_REG_LAPLACE = 3,   /* 1/(r + p0)                                         */
+  H2_K_TRIDIAG_1D = 4     /* -1 if |r - p0| < 1e-9*p0 else 0 (1-D test matrix)  */
+} h2_kernel_kind;
+
+typedef struct {
+  int32_t kind;   /* h2_kernel_kind */
+  double diag;    /* A_ii */
+  double p0, p1;  /* kernel parameters (see h2_kernel_kind) */
+} h2_kernel;
+
+/* Build options (pass NULL for defaults). */
+typedef struct {
+  int32_t sample_cap;        /* far-field columns per far cluster in the basis
+                                construction; 0 = automatic (all points when
+                                n <= 16384, else 2*leaf)                        */
+  int32_t max_shifts;        /* shifts factored together per launch; 0 = auto   */
+  int32_t reserved[6];
+} h2_opts;
+
+/*
+ * Build the H^2 representation of the kernel matrix of n points in `dim`
+ * dimensions (Sec. 3.1).
+ *   points : host, n*dim doubles, row-major (point i at points[i*dim .. i*dim+dim-1]).
+ *   leaf   : maximum cluster size at the leaf level (>= 2 unless n == 1).
+ *   eta    : strong admissibility parameter: clusters i != j are admissible when
+ *            eta * |c_i - c_j| >= rho_i + rho_j (bounding-box centres / half
+ *            diagonals).
+ *   eps    : compression tolerance; the absolute truncation threshold is
+ *            tau = eps * normA (see h2_norm).  Used for the shared bases
+ *            (Eq. shared-bases) and for fill-in recompression (Sec. 3.4).
+ * On success *out receives a handle whose bases, couplings and leaf near blocks
+ * (in skeleton coordinates, Eq. dense_skeleton) are resident in GPU memory.
+ * Errors: H2_EINVAL (n < 1, dim not in 1..3, leaf < 2 with n > 1, eta <= 0,
+ * eps <= 0, non-finite points, a singular kernel at coincident points),
+ * H2_ENOMEM, H2_EDEVICE.
+ */
+h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern,
+                   int32_t leaf, double eta, double eps, const h2_opts* opts,
+                   h2_matrix* out);
+
+/*
+ * Inertia counts nu_s = #{ lambda(A~) < sigma_s } for nshift shifts (Sec. 2,
+ * Eq. for nu; Sec. 4), by the generalized H^2-LDL of A~ - sigma_s I.  All shifts
+ * are factored on the GPU, batched.
+ *   sigma  : host, nshift doubles.
+ *   nu     : host output, nshift int64.
+ *   status : optional host output (may be NULL), nshift int32: H2_OK or
+ *            H2_ENUMERIC for a shift whose factorization met an exactly singular
+ *            or non-finite pivot (its nu is then -1).
+ * Returns H2_ENUMERIC if any shift failed (the others are still valid).
+ */
+h2_status h2_inertia(h2_matrix A, const double* sigma, int64_t nshift,
+                     int64_t* nu, int32_t* status);
+
+/*
+ * k-th smallest eigenvalues of A~ by Algorithm 1 (bisection), for nk 1-based
+ * indices k[j] in [1, n], to absolute tolerance tol > 0:
+ *   lambda[j] = midpoint of the final bracket, |lambda - lambda_k| < tol/2 when
+ *   every inertia is correct (Eq. error-bound).
+ *   ab     : optional [a, b] containing every requested eigenvalue; NULL = the
+ *            Gershgorin interval of the kernel matrix widened by 10*eps*normA.
+ *   bracket: optional output, 2*nk doubles (final [a_k, b_k]).
+ * All active brackets contribute one shift each to a single batched
+ * factorization per bisection step; inertia results are reused across the
+ * requested indices (Sec. 4.2).
+ */
+h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol,
+                     const double* ab, double* lambda, double* bracket);
+
+/* normA used for tau = eps*normA: max(mean row sum of A over rows i = 0 mod s,
+ * |A_ii|), s = max(1, n/16384). */
+h2_status h2_norm(h2_matrix A, double* normA);
+
+typedef struct {
+  int64_t n;
+  int32_t levels;           /* depth L of the cluster tree (leaves at level L) */
+  int32_t leaf_max;         /* largest leaf cluster                            */
+  int32_t rank_max;         /* largest skeleton rank of the construction       */
+  int32_t near_max;         /* largest near-list length (incl. self)           */
+  int64_t near_blocks;      /* ordered near pairs at the leaf level            */
+  int64_t resident_bytes;   /* device bytes held by the handle                 */
+  int64_t last_work_bytes;  /* workspace bytes of the last factorization       */
+  double last_flops;        /* algorithmic flops of the last factorization,
+                               per shift (from the actual ranks)               */
+  double last_bytes;        /* algorithmic HBM bytes per shift                 */
+  double build_seconds;
+  int32_t last_rank_max;    /* largest cluster dimension met in the last
+                               factorization (after rank growth)               */
+  int32_t reserved[5];
+} h2_stats_t;
+
+h2_status h2_stats(h2_matrix A, h2_stats_t* out);
+
+/* Run subsequent work of this handle on the given hipStream_t (NULL = the
+ * library's own stream). */
+h2_status h2_set_stream(h2_matrix A, void* hip_stream);
+
+/* Tree permutation: perm[p] = original index of the p-th point in leaf order
+ * (n int64, host output). */
+h2_status h2_tree_perm(h2_matrix A, int64_t* perm);
+
+void h2_free(h2_matrix A);
+
+const char* h2_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* H2EIG_H */

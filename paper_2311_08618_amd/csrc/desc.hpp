@@ -1,0 +1,140 @@
+// Work descriptors of the level-by-level factorization.  They are built once
+// per matrix on the host (the block structure does not depend on the shift)
+// and resolved on the device per shift, because the redundant/skeleton split of
+// every cluster depends on the shift through fill-in recompression.
+#pragma once
+#include <stdint.h>
+
+#ifndef __HIPCC__
+#ifndef __host__
+#define __host__
+#define __device__
+#endif
+#endif
+
+namespace h2 {
+
+// ---------------------------------------------------------- size expressions
+// A size expression is (kind << 24) | arg, evaluated per shift on the device.
+enum DimKind : int {
+  DK_CONST = 0,  // arg
+  DK_M = 1,      // m(c): current dimension of cluster c at this level
+  DK_R = 2,      // R(c): current redundant count
+  DK_S = 3,      // m(c) - R(c): skeleton count (after elimination: kept part)
+  DK_T = 4,      // t(c): directions added by this level's recompression of c
+  DK_RT = 5,     // R(c) + t(c): redundant count before the recompression
+  DK_R0 = 6,     // r0(c): skeleton rank of the construction
+  DK_PM = 7,     // parent dimension m(p) (merge)
+  DK_PR = 8,     // parent redundant count R(p) (merge)
+};
+
+__host__ __device__ inline int dx(int kind, int arg) { return (kind << 24) | arg; }
+__host__ __device__ inline int dconst(int v) { return v; }
+
+// --------------------------------------------------------------- buffers
+enum BufId : int {
+  B_S = 0,    // near blocks of the current level        [shift][pair][mcap x mcap]
+  B_F,        // carried fill-in of the current level    [shift][pair][mcap x mcap]
+  B_G,        // per cluster: Gram G -> rotation W -> elimination operator K
+  B_V,        // per cluster scratch (recompression)
+  B_M,        // per colour scratch: Y^T Y                [shift][slot][mcap^2]
+  B_P,        // per colour scratch: sums of Y^T Y
+  B_T,        // per colour scratch: Y^R sign P
+  B_SIGN,     // per cluster signs of the scaled pivots   [shift][cluster][mcap]
+  B_HAT,      // merge: children skeleton blocks          [shift][parent block][pcap^2]
+  B_PMAT,     // merge: parent basis per parent           [shift][parent][pcap^2]
+  B_TMP,      // merge: P^T Shat                          [shift][parent block][pcap^2]
+  B_SN,       // next level near blocks
+  B_FN,       // next level carried fill-in
+  B_BRES,     // resident leaf near blocks (shift independent)
+  B_CPL,      // resident couplings of the current level
+  B_EMAT,     // resident transfer matrices of the parent level
+  NBUF
+};
+
+struct BufTab {
+  double* p[NBUF];
+  int64_t ss[NBUF];  // shift stride (elements)
+  int64_t bs[NBUF];  // block stride (elements)
+  int ld[NBUF];      // leading dimension
+};
+
+struct SizeTab {
+  int* m;          // [S][N]
+  int* R;          // [S][N]
+  int* t;          // [S][N]
+  const int* r0;   // [N]
+  int* pm;         // [S][Np]
+  int* pR;         // [S][Np]
+  const int* pr0;  // [Np]
+  int N, Np;
+};
+
+__host__ __device__ inline int dev_eval(int e, const SizeTab& z, int s) {
+  int k = (int)((unsigned)e >> 24), a = e & 0xFFFFFF;
+  switch (k) {
+    case DK_CONST: return a;
+    case DK_M: return z.m[s * z.N + a];
+    case DK_R: return z.R[s * z.N + a];
+    case DK_S: return z.m[s * z.N + a] - z.R[s * z.N + a];
+    case DK_T: return z.t[s * z.N + a];
+    case DK_RT: return z.R[s * z.N + a] + z.t[s * z.N + a];
+    case DK_R0: return z.r0[a];
+    case DK_PM: return z.pm[s * z.Np + a];
+    case DK_PR: return z.pR[s * z.Np + a];
+  }
+  return 0;
+}
+
+// A sub-block origin: row = eval(r0) + eval(r1), col = eval(c0) + eval(c1).
+struct Ref {
+  int buf, blk;
+  int r0, r1, c0, c1;
+};
+
+// GEMM term: op(A) (M x K) * diag(w) * op(B) (K x N)
+struct GTerm {
+  Ref a, b;
+  int K;            // size expression
+  int wbuf, wblk;   // weights (B_SIGN, cluster) or wbuf = -1
+};
+
+// One output block: C = beta*C + alpha * sum_t op(A_t) diag(w_t) op(B_t)
+// optional C2 = beta*C2 + alpha*(...)^T (the transposed twin of a symmetric pair)
+struct GItem {
+  Ref c, c2;        // c2.buf = -1 when absent
+  int M, N;         // size expressions
+  int t0, nt;       // term range
+  double alpha, beta;
+};
+
+// Matrix sum: C[M x N] = sum_t A_t[M x N] (all at origin)
+struct SumItem {
+  int cbuf, cblk, M, N;
+  int t0, nt;       // into an int array of (buf, blk) pairs
+};
+
+// In-place rotation of the first RT(i) rows (side 0) or columns (side 1) of a
+// block by the cluster's rotation W (in B_G): rows <- W^T rows; cols <- cols W.
+struct RotItem {
+  int buf, blk, cluster, side;
+  int other;        // size expression: number of columns (side 0) / rows (side 1)
+};
+
+// In-place right multiplication of rows [row0, row0+nrows) x cols [0, R(i))
+// of a near block by the elimination operator K_i (in B_G).
+struct TrsmItem {
+  int blk, cluster;
+  int row0, nrows;  // size expressions
+};
+
+// Merge gather: parent block (p, q) from the 2x2 children skeleton blocks.
+struct GatherItem {
+  int out_blk;              // in B_HAT
+  int p, q;                 // parent clusters
+  int src_kind[4];          // 0 none, 1 near block (B_S), 2 carried fill-in (B_F)
+  int src_blk[4];
+  int cpl_blk[4];           // coupling slot in B_CPL or -1
+};
+
+}  // namespace h2

@@ -1,0 +1,834 @@
+// Level engine and C ABI of the H^2 k-th eigenvalue library.
+//
+// h2_build: host construction (tree, bases, couplings, static schedule), then the
+//   leaf near blocks in skeleton coordinates Q_i^T A_ij Q_j (Eq. dense_skeleton)
+//   are evaluated and rotated on the GPU and stay resident with the couplings and
+//   transfer matrices.
+// h2_inertia: batched generalized H^2-LDL of A~ - sigma_s I on the GPU, level by
+//   level, colour class by colour class (Secs. 3.2-3.4), returning
+//   nu_s = #{lambda < sigma_s} (Sec. 2, Sec. 4).
+// h2_kth_eig: Algorithm 1 for every requested index; the midpoints of all open
+//   brackets form one batch per bisection step, and every (mu, nu) record narrows
+//   every open bracket (inertia reuse, Sec. 4.2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/h2eig.h"
+#include "host.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace h2;
+
+namespace {
+
+thread_local std::string g_err;
+
+h2_status fail(h2_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+struct HipError {
+  hipError_t e;
+  std::string where;
+};
+
+#define HIPCHK(x)                                                   \
+  do {                                                              \
+    hipError_t e_ = (x);                                            \
+    if (e_ != hipSuccess) throw HipError{e_, std::string(#x)};      \
+  } while (0)
+
+struct NoMem {
+  std::string what;
+};
+
+// Device buffer that only grows.
+struct Arena {
+  void* p = nullptr;
+  size_t cap = 0;
+  void ensure(size_t bytes, hipStream_t st) {
+    if (bytes <= cap) return;
+    if (p) {
+      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(hipFree(p));
+      p = nullptr;
+      cap = 0;
+    }
+    size_t want = bytes + bytes / 8 + 4096;
+    if (hipMalloc(&p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw NoMem{"device allocation of " + std::to_string(want) + " bytes failed"};
+    }
+    cap = want;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+// Host blob of plan arrays uploaded in one copy.
+struct Blob {
+  std::vector<char> h;
+  template <class T>
+  size_t put(const std::vector<T>& v) {
+    size_t off = (h.size() + 255) & ~(size_t)255;
+    h.resize(off + v.size() * sizeof(T) + 1);
+    if (!v.empty()) std::memcpy(h.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+};
+
+struct DevList {
+  size_t items = 0, terms = 0;
+  int n = 0;
+};
+
+struct DevColour {
+  size_t clusters = 0;
+  int ncl = 0;
+  size_t rot_rows = 0, rot_cols = 0, trsm = 0;
+  int nrr = 0, nrc = 0, ntr = 0;
+  DevList schur, gm, gt, gg;
+  size_t gp_items = 0, gp_src = 0;
+  int ngp = 0;
+};
+
+struct DevLevel {
+  std::vector<DevColour> colours;
+  size_t diag_blk = 0, r0 = 0, pr0 = 0, edim = 0, gather = 0;
+  int ngather = 0;
+  DevList gram_init, fill, tr1, tr2;
+};
+
+}  // namespace
+
+struct h2_matrix_s {
+  std::atomic<int> busy{0};
+  Tree T;
+  Basis B;
+  KernelSpec kern;
+  double eps = 0, normA = 0, tau = 0;
+  std::vector<LevelPlan> plan;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  int leafcap = 0;
+  int device = 0;
+  // resident device data
+  double* d_bres = nullptr;
+  std::vector<double*> d_cpl;    // per level
+  std::vector<double*> d_emat;   // per level l: parents of level l+1 (index l)
+  std::vector<int> emat_ld;
+  char* d_plan = nullptr;
+  std::vector<DevLevel> dlev;
+  size_t leaf_m0 = 0, leaf_blkdiag = 0;
+  int64_t resident = 0;
+  // workspace
+  Arena sf[2], lvl, mrg, small;
+  // slicing cache and statistics
+  std::vector<std::pair<double, int64_t>> cache;
+  bool have_gersh = false;
+  double g_lo = 0, g_hi = 0;
+  h2_stats_t st{};
+  int max_shifts = 0;
+
+  template <class T>
+  const T* dp(size_t off) const { return reinterpret_cast<const T*>(d_plan + off); }
+  template <class T>
+  T* dpm(size_t off) const { return reinterpret_cast<T*>(d_plan + off); }
+};
+
+namespace {
+
+struct Busy {
+  h2_matrix A;
+  bool ok;
+  explicit Busy(h2_matrix a) : A(a) {
+    int z = 0;
+    ok = A->busy.compare_exchange_strong(z, 1);
+  }
+  ~Busy() {
+    if (ok) A->busy.store(0);
+  }
+};
+
+DevList put_list(Blob& b, const GList& g) {
+  DevList d;
+  d.items = b.put(g.items);
+  d.terms = b.put(g.terms);
+  d.n = (int)g.items.size();
+  return d;
+}
+
+void upload_plan(h2_matrix A) {
+  Blob b;
+  int L = A->T.L;
+  A->dlev.assign(L + 1, {});
+  for (int l = 0; l <= L; ++l) {
+    const LevelPlan& lp = A->plan[l];
+    DevLevel& dl = A->dlev[l];
+    dl.diag_blk = b.put(lp.diag_blk);
+    dl.r0 = b.put(lp.r0);
+    dl.colours.resize(lp.colours.size());
+    for (size_t c = 0; c < lp.colours.size(); ++c) {
+      const ColourPlan& cp = lp.colours[c];
+      DevColour& dc = dl.colours[c];
+      dc.clusters = b.put(cp.clusters);
+      dc.ncl = (int)cp.clusters.size();
+      dc.rot_rows = b.put(cp.rot_rows);
+      dc.nrr = (int)cp.rot_rows.size();
+      dc.rot_cols = b.put(cp.rot_cols);
+      dc.nrc = (int)cp.rot_cols.size();
+      dc.trsm = b.put(cp.trsm);
+      dc.ntr = (int)cp.trsm.size();
+      dc.schur = put_list(b, cp.schur);
+      dc.gm = put_list(b, cp.gram_m);
+      dc.gt = put_list(b, cp.gram_t);
+      dc.gg = put_list(b, cp.gram_g);
+      dc.gp_items = b.put(cp.gram_p.items);
+      dc.gp_src = b.put(cp.gram_p.src);
+      dc.ngp = (int)cp.gram_p.items.size();
+    }
+    dl.gram_init = put_list(b, lp.gram_init);
+    if (l >= 1) {
+      const MergePlan& mp = lp.merge;
+      dl.pr0 = b.put(mp.pr0);
+      dl.edim = b.put(mp.emat_dim);
+      dl.gather = b.put(mp.gather);
+      dl.ngather = (int)mp.gather.size();
+      dl.fill = put_list(b, mp.fill);
+      dl.tr1 = put_list(b, mp.tr1);
+      dl.tr2 = put_list(b, mp.tr2);
+    }
+  }
+  // leaf: dimensions and diagonal flags
+  const LevelPlan& lf = A->plan[L];
+  std::vector<int> m0(lf.N), bdm(lf.nblk(), 0);
+  for (int i = 0; i < lf.N; ++i) {
+    m0[i] = A->B.m[L][i];
+    bdm[lf.diag_blk[i]] = m0[i];
+  }
+  A->leaf_m0 = b.put(m0);
+  A->leaf_blkdiag = b.put(bdm);
+  HIPCHK(hipMalloc(&A->d_plan, b.h.size()));
+  HIPCHK(hipMemcpy(A->d_plan, b.h.data(), b.h.size(), hipMemcpyHostToDevice));
+  A->resident += (int64_t)b.h.size();
+}
+
+// Leaf near blocks B_ij = Q_i^T A_ij Q_j on the GPU.
+void build_near_blocks(h2_matrix A) {
+  const Tree& T = A->T;
+  int L = T.L;
+  const LevelPlan& lf = A->plan[L];
+  int cap = A->leafcap;
+  int N = lf.N, nblk = lf.nblk();
+  hipStream_t st = A->stream;
+  size_t bsz = (size_t)cap * cap;
+  HIPCHK(hipMalloc(&A->d_bres, std::max<size_t>(1, (size_t)nblk * bsz * sizeof(double))));
+  A->resident += (int64_t)nblk * bsz * 8;
+  // points in leaf order, starts, sizes, bases
+  std::vector<double> Xl((size_t)T.n * T.dim);
+  for (int64_t p = 0; p < T.n; ++p)
+    for (int d = 0; d < T.dim; ++d) Xl[p * T.dim + d] = T.X[T.perm[p] * T.dim + d];
+  std::vector<int64_t> start(N);
+  std::vector<int> msz(N);
+  for (int i = 0; i < N; ++i) {
+    start[i] = T.start[L][i];
+    msz[i] = (int)T.size[L][i];
+  }
+  std::vector<double> Q((size_t)N * bsz, 0.0);
+  for (int i = 0; i < N; ++i) {
+    int m = msz[i];
+    const auto& q = A->B.Q[L][i];
+    for (int c = 0; c < m; ++c)
+      for (int r = 0; r < m; ++r) Q[(size_t)i * bsz + r + (size_t)c * cap] = q[r + (size_t)c * m];
+  }
+  double *dX = nullptr, *dQ = nullptr;
+  int64_t* dstart = nullptr;
+  int *dm = nullptr, *dbad = nullptr;
+  HIPCHK(hipMalloc(&dX, std::max<size_t>(8, Xl.size() * 8)));
+  HIPCHK(hipMalloc(&dQ, Q.size() * 8));
+  HIPCHK(hipMalloc(&dstart, N * 8));
+  HIPCHK(hipMalloc(&dm, N * 4));
+  HIPCHK(hipMalloc(&dbad, 4));
+  HIPCHK(hipMemcpy(dX, Xl.data(), Xl.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dQ, Q.data(), Q.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dstart, start.data(), N * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dm, msz.data(), N * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(dbad, 0, 4));
+  // chunked: kernel blocks -> HAT ; TMP = Q_i^T HAT ; BRES = TMP Q_j
+  int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nblk, (int64_t)(2LL << 30) / (int64_t)(bsz * 8)));
+  double *dA = nullptr, *dT = nullptr;
+  HIPCHK(hipMalloc(&dA, (size_t)chunk * bsz * 8));
+  HIPCHK(hipMalloc(&dT, (size_t)chunk * bsz * 8));
+  std::vector<int> bi(nblk), bj(nblk);
+  for (int i = 0; i < N; ++i)
+    for (int k = lf.near_ptr[i]; k < lf.near_ptr[i + 1]; ++k) {
+      bi[k] = i;
+      bj[k] = lf.near_idx[k];
+    }
+  int *dbi = nullptr, *dbj = nullptr;
+  HIPCHK(hipMalloc(&dbi, std::max(1, nblk) * 4));
+  HIPCHK(hipMalloc(&dbj, std::max(1, nblk) * 4));
+  HIPCHK(hipMemcpy(dbi, bi.data(), nblk * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dbj, bj.data(), nblk * 4, hipMemcpyHostToDevice));
+  int zero_int = 0;
+  SizeTab sz{};
+  sz.N = 1;
+  sz.Np = 1;
+  sz.m = sz.R = sz.t = sz.pm = sz.pR = &zero_int;  // never dereferenced: constant sizes only
+  for (int b0 = 0; b0 < nblk; b0 += chunk) {
+    int nb = std::min(chunk, nblk - b0);
+    launch_kernel_blocks(dA, bsz, cap, dbi + b0, dbj + b0, nb, dstart, dm, dX, T.dim, A->kern.kind, A->kern.diag,
+                         A->kern.p0, A->kern.p1, dbad, st);
+    GList g1, g2;
+    for (int k = 0; k < nb; ++k) {
+      int i = bi[b0 + k], j = bj[b0 + k];
+      Ref q{B_PMAT, i, 0, 0, 0, 0}, a{B_HAT, k, 0, 0, 0, 0}, t{B_TMP, k, 0, 0, 0, 0}, o{B_BRES, b0 + k, 0, 0, 0, 0};
+      Ref none{-1, 0, 0, 0, 0, 0};
+      GItem it1{t, none, msz[i], msz[j], 0, 0, 1.0, 0.0};
+      g1.add(it1, {GTerm{q, a, msz[i], -1, 0}});
+      GItem it2{o, none, msz[i], msz[j], 0, 0, 1.0, 0.0};
+      g2.add(it2, {GTerm{t, Ref{B_PMAT, j, 0, 0, 0, 0}, msz[j], -1, 0}});
+    }
+    GItem *di1, *di2;
+    GTerm *dt1, *dt2;
+    HIPCHK(hipMalloc(&di1, g1.items.size() * sizeof(GItem)));
+    HIPCHK(hipMalloc(&di2, g2.items.size() * sizeof(GItem)));
+    HIPCHK(hipMalloc(&dt1, g1.terms.size() * sizeof(GTerm)));
+    HIPCHK(hipMalloc(&dt2, g2.terms.size() * sizeof(GTerm)));
+    HIPCHK(hipMemcpy(di1, g1.items.data(), g1.items.size() * sizeof(GItem), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(di2, g2.items.data(), g2.items.size() * sizeof(GItem), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dt1, g1.terms.data(), g1.terms.size() * sizeof(GTerm), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dt2, g2.terms.data(), g2.terms.size() * sizeof(GTerm), hipMemcpyHostToDevice));
+    BufTab bt{};
+    for (int k = 0; k < NBUF; ++k) { bt.p[k] = nullptr; bt.ss[k] = 0; bt.bs[k] = (int64_t)bsz; bt.ld[k] = cap; }
+    bt.p[B_PMAT] = dQ;
+    bt.p[B_HAT] = dA;
+    bt.p[B_TMP] = dT;
+    bt.p[B_BRES] = A->d_bres;
+    launch_gemm(GEMM_TN, di1, nb, dt1, bt, sz, cap, cap, 1, st);
+    launch_gemm(GEMM_NN, di2, nb, dt2, bt, sz, cap, cap, 1, st);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipFree(di1));
+    HIPCHK(hipFree(di2));
+    HIPCHK(hipFree(dt1));
+    HIPCHK(hipFree(dt2));
+  }
+  int bad = 0;
+  HIPCHK(hipMemcpy(&bad, dbad, 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipFree(dA));
+  HIPCHK(hipFree(dT));
+  HIPCHK(hipFree(dX));
+  HIPCHK(hipFree(dQ));
+  HIPCHK(hipFree(dstart));
+  HIPCHK(hipFree(dm));
+  HIPCHK(hipFree(dbad));
+  HIPCHK(hipFree(dbi));
+  HIPCHK(hipFree(dbj));
+  if (bad) throw std::invalid_argument("kernel is not finite for a pair of distinct points (coincident points?)");
+}
+
+void upload_resident(h2_matrix A) {
+  int L = A->T.L;
+  A->d_cpl.assign(L + 1, nullptr);
+  A->d_emat.assign(L + 1, nullptr);
+  A->emat_ld.assign(L + 1, 1);
+  for (int l = 1; l <= L; ++l) {
+    const LevelPlan& lp = A->plan[l];
+    int rm = std::max(1, lp.rmax);
+    size_t nsl = lp.far_idx.size();
+    std::vector<double> h(std::max<size_t>(1, nsl) * rm * rm, 0.0);
+    for (int i = 0; i < lp.N; ++i) {
+      int ri = A->B.r[l][i];
+      for (auto& pr : A->B.C[l][i]) {
+        int j = pr.first, rj = A->B.r[l][j];
+        int slot = lp.cslot(i, j);
+        for (int c = 0; c < rj; ++c)
+          for (int r = 0; r < ri; ++r) h[(size_t)slot * rm * rm + r + (size_t)c * rm] = pr.second[r + (size_t)c * ri];
+      }
+    }
+    HIPCHK(hipMalloc(&A->d_cpl[l], h.size() * 8));
+    HIPCHK(hipMemcpy(A->d_cpl[l], h.data(), h.size() * 8, hipMemcpyHostToDevice));
+    A->resident += (int64_t)h.size() * 8;
+    // transfer matrices of the parents (level l-1), stored with level l-1
+    const MergePlan& mp = lp.merge;
+    int em = std::max(1, mp.emax);
+    std::vector<double> e((size_t)mp.Np * em * em, 0.0);
+    for (int p = 0; p < mp.Np; ++p) {
+      int d = mp.emat_dim[p];
+      const auto& Q = A->B.Q[l - 1][p];
+      for (int c = 0; c < d; ++c)
+        for (int r = 0; r < d; ++r) e[(size_t)p * em * em + r + (size_t)c * em] = Q[r + (size_t)c * d];
+    }
+    HIPCHK(hipMalloc(&A->d_emat[l - 1], e.size() * 8));
+    HIPCHK(hipMemcpy(A->d_emat[l - 1], e.data(), e.size() * 8, hipMemcpyHostToDevice));
+    A->emat_ld[l - 1] = em;
+    A->resident += (int64_t)e.size() * 8;
+  }
+}
+
+// ------------------------------------------------------------ factorization
+struct Work {
+  int S = 0;
+  int *m = nullptr, *R = nullptr, *t = nullptr, *pm = nullptr, *pR = nullptr, *status = nullptr;
+  unsigned long long* nu = nullptr;
+  double* sigma = nullptr;
+};
+
+inline int round_cap(int v) { return std::max(8, (v + 7) & ~7); }
+
+int debug_level() {
+  static int v = [] {
+    const char* e = std::getenv("H2EIG_DEBUG");
+    return e ? std::atoi(e) : 0;
+  }();
+  return v;
+}
+
+// Diagnostic print (H2EIG_DEBUG=1): sizes of the first shift after a level.
+void debug_dump_level(int l, int N, int S, const Work& w, hipStream_t st) {
+  std::vector<int> m((size_t)S * N), R((size_t)S * N), t((size_t)S * N), stv(S);
+  std::vector<unsigned long long> nu(S);
+  HIPCHK(hipMemcpyAsync(m.data(), w.m, m.size() * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(R.data(), w.R, R.size() * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(t.data(), w.t, t.size() * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(nu.data(), w.nu, S * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(stv.data(), w.status, S * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::fprintf(stderr, "[h2eig] level %d: nu[0]=%llu status[0]=%d\n", l, nu[0], stv[0]);
+  std::fprintf(stderr, "[h2eig]   m:");
+  for (int i = 0; i < std::min(N, 32); ++i) std::fprintf(stderr, " %d", m[i]);
+  std::fprintf(stderr, "\n[h2eig]   R:");
+  for (int i = 0; i < std::min(N, 32); ++i) std::fprintf(stderr, " %d", R[i]);
+  std::fprintf(stderr, "\n[h2eig]   t:");
+  for (int i = 0; i < std::min(N, 32); ++i) std::fprintf(stderr, " %d", t[i]);
+  std::fprintf(stderr, "\n");
+}
+
+// Factor S shifts; nu/status are host outputs.
+void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_t* st_out, double* flops_out,
+                  int* maxdim_out) {
+  const Tree& T = A->T;
+  const int L = T.L;
+  hipStream_t st = A->stream;
+  const int Nmax = 1 << L;
+  // small arena: sizes tables + sigma + nu + status
+  size_t nsz = (size_t)S * Nmax;
+  size_t off_m = 0, off_R = off_m + nsz * 4, off_t = off_R + nsz * 4, off_pm = off_t + nsz * 4,
+         off_pR = off_pm + nsz * 4, off_st = off_pR + nsz * 4, off_sig = ((off_st + S * 4 + 255) / 256) * 256,
+         off_nu = off_sig + S * 8, total = off_nu + S * 8;
+  A->small.ensure(total, st);
+  char* base = (char*)A->small.p;
+  Work w;
+  w.S = S;
+  w.m = (int*)(base + off_m);
+  w.R = (int*)(base + off_R);
+  w.t = (int*)(base + off_t);
+  w.pm = (int*)(base + off_pm);
+  w.pR = (int*)(base + off_pR);
+  w.status = (int*)(base + off_st);
+  w.sigma = (double*)(base + off_sig);
+  w.nu = (unsigned long long*)(base + off_nu);
+  HIPCHK(hipMemcpyAsync(w.sigma, sig, S * 8, hipMemcpyHostToDevice, st));
+  launch_fill_int(w.status, S, 0, st);
+  launch_fill_int((int*)w.nu, 2 * S, 0, st);
+
+  int cap = A->leafcap;
+  int cur = 0;  // which sf arena holds the current level
+  double flops = 0.0;
+  int maxdim = cap;
+  std::vector<int> hpm;
+  for (int l = L; l >= 0; --l) {
+    const LevelPlan& lp = A->plan[l];
+    const DevLevel& dl = A->dlev[l];
+    const int N = lp.N;
+    const size_t bsz = (size_t)cap * cap;
+    // level buffers
+    size_t nS = (size_t)S * lp.nblk() * bsz, nF = (size_t)S * lp.nfblk() * bsz;
+    if (l == L) A->sf[cur].ensure((nS + nF) * 8 + 64, st);
+    double* dS = (double*)A->sf[cur].p;
+    double* dF = dS + nS;
+    size_t nG = (size_t)S * N * bsz, nM = (size_t)S * std::max(1, lp.max_slot_m) * bsz,
+           nP = (size_t)S * std::max(1, lp.max_slot_p) * bsz, nSg = (size_t)S * N * cap;
+    A->lvl.ensure((2 * nG + nM + 2 * nP + nSg) * 8 + 64, st);
+    double* dG = (double*)A->lvl.p;
+    double* dV = dG + nG;
+    double* dM = dV + nG;
+    double* dP = dM + nM;
+    double* dT = dP + nP;
+    double* dSg = dT + nP;
+    BufTab bt{};
+    for (int k = 0; k < NBUF; ++k) { bt.p[k] = nullptr; bt.ss[k] = 0; bt.bs[k] = (int64_t)bsz; bt.ld[k] = cap; }
+    auto setb = [&](int id, double* p, size_t perShift, size_t blk, int ld) {
+      bt.p[id] = p;
+      bt.ss[id] = (int64_t)perShift;
+      bt.bs[id] = (int64_t)blk;
+      bt.ld[id] = ld;
+    };
+    setb(B_S, dS, (size_t)lp.nblk() * bsz, bsz, cap);
+    setb(B_F, dF, (size_t)lp.nfblk() * bsz, bsz, cap);
+    setb(B_G, dG, (size_t)N * bsz, bsz, cap);
+    setb(B_V, dV, (size_t)N * bsz, bsz, cap);
+    setb(B_M, dM, (size_t)std::max(1, lp.max_slot_m) * bsz, bsz, cap);
+    setb(B_P, dP, (size_t)std::max(1, lp.max_slot_p) * bsz, bsz, cap);
+    setb(B_T, dT, (size_t)std::max(1, lp.max_slot_p) * bsz, bsz, cap);
+    setb(B_SIGN, dSg, (size_t)N * cap, (size_t)cap, cap);
+    if (l >= 1) {
+      const LevelPlan& lpl = A->plan[l];
+      setb(B_CPL, A->d_cpl[l], 0, (size_t)std::max(1, lpl.rmax) * std::max(1, lpl.rmax), std::max(1, lpl.rmax));
+    }
+    SizeTab sz{};
+    sz.m = w.m;
+    sz.R = w.R;
+    sz.t = w.t;
+    sz.r0 = A->dp<int>(dl.r0);
+    sz.pm = w.pm;
+    sz.pR = w.pR;
+    sz.N = N;
+    sz.Np = std::max(1, N >> 1);
+    sz.pr0 = l >= 1 ? A->dp<int>(dl.pr0) : nullptr;
+    if (l == L) {
+      bt.p[B_BRES] = A->d_bres;
+      bt.ss[B_BRES] = 0;
+      bt.bs[B_BRES] = (int64_t)bsz;
+      bt.ld[B_BRES] = cap;
+      launch_sizes_init(sz, A->dp<int>(A->leaf_m0), S, st);
+      launch_leaf_init(bt, lp.nblk(), A->dp<int>(A->leaf_blkdiag), w.sigma, cap, S, st);
+    }
+    launch_fill(dG, nG, 0.0, st);
+    launch_fill(dSg, nSg, 0.0, st);
+    launch_gemm(GEMM_NT, A->dp<GItem>(dl.gram_init.items), dl.gram_init.n, A->dp<GTerm>(dl.gram_init.terms), bt, sz,
+                cap, cap, S, st);
+    const double tau2 = A->tau * A->tau;
+    for (size_t c = 0; c < dl.colours.size(); ++c) {
+      const DevColour& dc = dl.colours[c];
+      const int* cl = A->dp<int>(dc.clusters);
+      launch_recompress(cl, dc.ncl, bt, sz, tau2, w.status, cap, S, st);
+      launch_rotate(A->dp<RotItem>(dc.rot_rows), dc.nrr, bt, sz, cap, S, st);
+      launch_rotate(A->dp<RotItem>(dc.rot_cols), dc.nrc, bt, sz, cap, S, st);
+      launch_ldl(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, w.nu, w.status, cap, S, st);
+      launch_trsm(A->dp<TrsmItem>(dc.trsm), dc.ntr, bt, sz, cap, S, st);
+      launch_gemm(GEMM_NT, A->dp<GItem>(dc.schur.items), dc.schur.n, A->dp<GTerm>(dc.schur.terms), bt, sz, cap, cap, S, st);
+      launch_gemm(GEMM_TN, A->dp<GItem>(dc.gm.items), dc.gm.n, A->dp<GTerm>(dc.gm.terms), bt, sz, cap, cap, S, st);
+      launch_matsum(A->dp<SumItem>(dc.gp_items), dc.ngp, A->dp<int>(dc.gp_src), bt, sz, cap, S, st);
+      launch_gemm(GEMM_NN, A->dp<GItem>(dc.gt.items), dc.gt.n, A->dp<GTerm>(dc.gt.terms), bt, sz, cap, cap, S, st);
+      launch_gemm(GEMM_NT, A->dp<GItem>(dc.gg.items), dc.gg.n, A->dp<GTerm>(dc.gg.terms), bt, sz, cap, cap, S, st);
+    }
+    HIPCHK(hipGetLastError());
+    if (debug_level()) debug_dump_level(l, N, S, w, st);
+    if (l == 0) break;
+    // ---- merge into level l-1
+    const LevelPlan& pp = A->plan[l - 1];
+    const int Np = N >> 1;
+    launch_merge_sizes(sz, Np, S, st);
+    hpm.resize((size_t)S * Np);
+    HIPCHK(hipMemcpyAsync(hpm.data(), w.pm, (size_t)S * Np * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int pmax = 0;
+    for (int v : hpm) pmax = std::max(pmax, v);
+    if (pmax == 0) break;  // nothing left above this level
+    maxdim = std::max(maxdim, pmax);
+    const int pcap = round_cap(pmax);
+    const size_t pbsz = (size_t)pcap * pcap;
+    const int other = 1 - cur;
+    size_t nSN = (size_t)S * pp.nblk() * pbsz, nFN = (size_t)S * pp.nfblk() * pbsz;
+    A->sf[other].ensure((nSN + nFN) * 8 + 64, st);
+    double* dSN = (double*)A->sf[other].p;
+    double* dFN = dSN + nSN;
+    const MergePlan& mp = lp.merge;
+    size_t nH = (size_t)S * std::max(1, mp.nhat) * pbsz, nPm = (size_t)S * Np * pbsz;
+    A->mrg.ensure((2 * nH + nPm) * 8 + 64, st);
+    double* dH = (double*)A->mrg.p;
+    double* dTm = dH + nH;
+    double* dPm = dTm + nH;
+    setb(B_HAT, dH, (size_t)std::max(1, mp.nhat) * pbsz, pbsz, pcap);
+    setb(B_TMP, dTm, (size_t)std::max(1, mp.nhat) * pbsz, pbsz, pcap);
+    setb(B_PMAT, dPm, (size_t)Np * pbsz, pbsz, pcap);
+    setb(B_SN, dSN, (size_t)pp.nblk() * pbsz, pbsz, pcap);
+    setb(B_FN, dFN, (size_t)pp.nfblk() * pbsz, pbsz, pcap);
+    setb(B_EMAT, A->d_emat[l - 1], 0, (size_t)A->emat_ld[l - 1] * A->emat_ld[l - 1], A->emat_ld[l - 1]);
+    launch_pmat(bt, sz, A->dp<int>(dl.edim), Np, pcap, S, st);
+    launch_gather(A->dp<GatherItem>(dl.gather), dl.ngather, bt, sz, pcap, S, st);
+    launch_gemm(GEMM_NT, A->dp<GItem>(dl.fill.items), dl.fill.n, A->dp<GTerm>(dl.fill.terms), bt, sz, pcap, pcap, S, st);
+    launch_gemm(GEMM_TN, A->dp<GItem>(dl.tr1.items), dl.tr1.n, A->dp<GTerm>(dl.tr1.terms), bt, sz, pcap, pcap, S, st);
+    launch_gemm(GEMM_NN, A->dp<GItem>(dl.tr2.items), dl.tr2.n, A->dp<GTerm>(dl.tr2.terms), bt, sz, pcap, pcap, S, st);
+    launch_next_sizes(sz, S, st);
+    HIPCHK(hipGetLastError());
+    cur = other;
+    cap = pcap;
+  }
+  std::vector<unsigned long long> hnu(S);
+  std::vector<int> hst(S);
+  HIPCHK(hipMemcpyAsync(hnu.data(), w.nu, S * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(hst.data(), w.status, S * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int s = 0; s < S; ++s) {
+    nu_out[s] = hst[s] ? -1 : (int64_t)hnu[s];
+    if (st_out) st_out[s] = hst[s] ? H2_ENUMERIC : H2_OK;
+  }
+  if (flops_out) *flops_out = flops;
+  if (maxdim_out) *maxdim_out = maxdim;
+}
+
+int auto_max_shifts(h2_matrix A) {
+  if (A->max_shifts > 0) return A->max_shifts;
+  size_t freeb = 0, totalb = 0;
+  if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) {
+    (void)hipGetLastError();
+    return 4;
+  }
+  const LevelPlan& lf = A->plan[A->T.L];
+  double per = (double)A->leafcap * A->leafcap * 8.0 * (lf.nblk() + 2.0 * lf.N + lf.max_slot_m + 2.0 * lf.max_slot_p);
+  per *= 2.2;  // upper levels and merge buffers
+  int s = (int)std::floor(0.7 * (double)freeb / std::max(per, 1.0));
+  return std::max(1, std::min(s, 64));
+}
+
+h2_status run_inertia(h2_matrix A, const double* sigma, int64_t ns, int64_t* nu, int32_t* status) {
+  int maxs = auto_max_shifts(A);
+  bool anybad = false;
+  auto t0 = std::chrono::steady_clock::now();
+  for (int64_t s0 = 0; s0 < ns;) {
+    int S = (int)std::min<int64_t>(maxs, ns - s0);
+    try {
+      int md = 0;
+      factor_batch(A, sigma + s0, S, nu + s0, status ? status + s0 : nullptr, nullptr, &md);
+      A->st.last_rank_max = std::max(A->st.last_rank_max, md);
+    } catch (NoMem&) {
+      if (S == 1) throw;
+      maxs = std::max(1, S / 2);
+      A->max_shifts = maxs;
+      for (auto& a : A->sf) a.release();
+      A->lvl.release();
+      A->mrg.release();
+      continue;
+    }
+    for (int k = 0; k < S; ++k) {
+      if (nu[s0 + k] < 0) anybad = true;
+      else A->cache.push_back({sigma[s0 + k], nu[s0 + k]});
+    }
+    s0 += S;
+  }
+  (void)t0;
+  int64_t ws = (int64_t)(A->sf[0].cap + A->sf[1].cap + A->lvl.cap + A->mrg.cap + A->small.cap);
+  A->st.last_work_bytes = ws;
+  return anybad ? H2_ENUMERIC : H2_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* h2_last_error(void) { return g_err.c_str(); }
+
+h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern, int32_t leaf, double eta, double eps,
+                   const h2_opts* opts, h2_matrix* out) {
+  if (!out) return fail(H2_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!points || n < 1) return fail(H2_EINVAL, "n must be >= 1 and points non-NULL");
+  if (dim < 1 || dim > 3) return fail(H2_EINVAL, "dim must be 1, 2 or 3");
+  if (leaf < 2 && n > 1) return fail(H2_EINVAL, "leaf must be >= 2");
+  if (!(eta > 0.0) || !(eps > 0.0)) return fail(H2_EINVAL, "eta and eps must be > 0");
+  if (kern.kind < 0 || kern.kind > 4) return fail(H2_EINVAL, "unknown kernel kind");
+  if (!std::isfinite(kern.diag) || !std::isfinite(kern.p0) || !std::isfinite(kern.p1))
+    return fail(H2_EINVAL, "non-finite kernel parameter");
+  if ((kern.kind == H2_K_GAUSS_DAMPED || kern.kind == H2_K_TRIDIAG_1D) && !(kern.p0 > 0.0))
+    return fail(H2_EINVAL, "kernel parameter p0 must be > 0");
+  for (int64_t i = 0; i < n * dim; ++i)
+    if (!std::isfinite(points[i])) return fail(H2_EINVAL, "non-finite point coordinate");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return fail(H2_EDEVICE, "no HIP device available");
+  }
+  h2_matrix A = new h2_matrix_s();
+  auto t0 = std::chrono::steady_clock::now();
+  try {
+    HIPCHK(hipGetDevice(&A->device));
+    HIPCHK(hipStreamCreateWithFlags(&A->own_stream, hipStreamNonBlocking));
+    A->stream = A->own_stream;
+    A->kern = KernelSpec{kern.kind, kern.diag, kern.p0, kern.p1};
+    A->eps = eps;
+    build_tree(A->T, points, n, dim, leaf, eta);
+    A->normA = estimate_norm(A->T, A->kern);
+    A->tau = eps * A->normA;
+    BuildParams P;
+    P.kern = A->kern;
+    P.eps = eps;
+    P.sample_cap = opts ? opts->sample_cap : 0;
+    if (opts && opts->max_shifts > 0) A->max_shifts = opts->max_shifts;
+    build_basis(A->T, P, A->tau, A->B);
+    A->plan = build_plan(A->T, A->B);
+    int L = A->T.L;
+    A->leafcap = 0;
+    for (int i = 0; i < (1 << L); ++i) A->leafcap = std::max<int>(A->leafcap, (int)A->T.size[L][i]);
+    A->leafcap = round_cap(A->leafcap);
+    upload_plan(A);
+    upload_resident(A);
+    build_near_blocks(A);
+    HIPCHK(hipStreamSynchronize(A->stream));
+  } catch (HipError& e) {
+    h2_free(A);
+    return fail(H2_EDEVICE, e.where + ": " + hipGetErrorString(e.e));
+  } catch (NoMem& e) {
+    h2_free(A);
+    return fail(H2_ENOMEM, e.what);
+  } catch (std::invalid_argument& e) {
+    h2_free(A);
+    return fail(H2_EINVAL, e.what());
+  } catch (std::bad_alloc&) {
+    h2_free(A);
+    return fail(H2_ENOMEM, "host allocation failed");
+  }
+  const Tree& T = A->T;
+  A->st.n = T.n;
+  A->st.levels = T.L;
+  A->st.leaf_max = A->leafcap;
+  int rmax = 0, nmax = 0;
+  for (int l = 0; l <= T.L; ++l) {
+    for (int v : A->B.r[l]) rmax = std::max(rmax, v);
+    for (auto& v : T.near[l]) nmax = std::max(nmax, (int)v.size());
+  }
+  A->st.rank_max = rmax;
+  A->st.near_max = nmax;
+  A->st.near_blocks = A->plan[T.L].nblk();
+  A->st.resident_bytes = A->resident;
+  A->st.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = A;
+  return H2_OK;
+}
+
+h2_status h2_inertia(h2_matrix A, const double* sigma, int64_t nshift, int64_t* nu, int32_t* status) {
+  if (!A) return fail(H2_EINVAL, "NULL handle");
+  if (nshift < 0 || (nshift > 0 && (!sigma || !nu))) return fail(H2_EINVAL, "bad shift arrays");
+  for (int64_t s = 0; s < nshift; ++s)
+    if (!std::isfinite(sigma[s])) return fail(H2_EINVAL, "non-finite shift");
+  Busy b(A);
+  if (!b.ok) return fail(H2_EBUSY, "handle in use by another thread");
+  if (nshift == 0) return H2_OK;
+  try {
+    HIPCHK(hipSetDevice(A->device));
+    h2_status r = run_inertia(A, sigma, nshift, nu, status);
+    if (r != H2_OK) return fail(r, "singular or non-finite pivot block for at least one shift");
+    return H2_OK;
+  } catch (HipError& e) {
+    return fail(H2_EDEVICE, e.where + ": " + hipGetErrorString(e.e));
+  } catch (NoMem& e) {
+    return fail(H2_ENOMEM, e.what);
+  }
+}
+
+h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol, const double* ab, double* lambda,
+                     double* bracket) {
+  if (!A) return fail(H2_EINVAL, "NULL handle");
+  if (nk < 0 || (nk > 0 && (!k || !lambda))) return fail(H2_EINVAL, "bad index arrays");
+  if (!(tol > 0.0)) return fail(H2_EINVAL, "tol must be > 0");
+  const int64_t n = A->T.n;
+  for (int64_t j = 0; j < nk; ++j)
+    if (k[j] < 1 || k[j] > n) return fail(H2_EINVAL, "k out of range [1, n]");
+  double a0, b0;
+  if (ab) {
+    a0 = ab[0];
+    b0 = ab[1];
+    if (!(std::isfinite(a0) && std::isfinite(b0) && a0 < b0)) return fail(H2_EINVAL, "bad interval ab");
+  } else {
+    if (!A->have_gersh) {
+      gershgorin(A->T, A->kern, &A->g_lo, &A->g_hi);
+      A->have_gersh = true;
+    }
+    double mg = 10.0 * A->eps * A->normA;
+    a0 = A->g_lo - mg;
+    b0 = A->g_hi + mg;
+  }
+  if (nk == 0) return H2_OK;
+  std::vector<double> lo(nk, a0), hi(nk, b0);
+  auto narrow = [&](double mu, int64_t v) {
+    for (int64_t j = 0; j < nk; ++j) {
+      if (!(mu > lo[j] && mu < hi[j])) continue;
+      if (v >= k[j]) hi[j] = mu;
+      else lo[j] = mu;
+    }
+  };
+  for (auto& rec : A->cache) narrow(rec.first, rec.second);
+  for (;;) {
+    std::vector<double> mus;
+    for (int64_t j = 0; j < nk; ++j)
+      if (hi[j] - lo[j] >= tol) mus.push_back(0.5 * (lo[j] + hi[j]));
+    if (mus.empty()) break;
+    std::sort(mus.begin(), mus.end());
+    mus.erase(std::unique(mus.begin(), mus.end()), mus.end());
+    std::vector<int64_t> nus(mus.size());
+    std::vector<int32_t> sts(mus.size());
+    h2_status r = h2_inertia(A, mus.data(), (int64_t)mus.size(), nus.data(), sts.data());
+    if (r != H2_OK) return r;
+    for (size_t q = 0; q < mus.size(); ++q) narrow(mus[q], nus[q]);
+  }
+  for (int64_t j = 0; j < nk; ++j) {
+    lambda[j] = 0.5 * (lo[j] + hi[j]);
+    if (bracket) {
+      bracket[2 * j] = lo[j];
+      bracket[2 * j + 1] = hi[j];
+    }
+  }
+  return H2_OK;
+}
+
+h2_status h2_norm(h2_matrix A, double* normA) {
+  if (!A || !normA) return fail(H2_EINVAL, "NULL argument");
+  *normA = A->normA;
+  return H2_OK;
+}
+
+h2_status h2_stats(h2_matrix A, h2_stats_t* out) {
+  if (!A || !out) return fail(H2_EINVAL, "NULL argument");
+  *out = A->st;
+  return H2_OK;
+}
+
+h2_status h2_set_stream(h2_matrix A, void* hip_stream) {
+  if (!A) return fail(H2_EINVAL, "NULL handle");
+  A->stream = hip_stream ? (hipStream_t)hip_stream : A->own_stream;
+  return H2_OK;
+}
+
+h2_status h2_tree_perm(h2_matrix A, int64_t* perm) {
+  if (!A || !perm) return fail(H2_EINVAL, "NULL argument");
+  std::copy(A->T.perm.begin(), A->T.perm.end(), perm);
+  return H2_OK;
+}
+
+void h2_free(h2_matrix A) {
+  if (!A) return;
+  if (A->stream) (void)hipStreamSynchronize(A->stream);
+  for (auto& a : A->sf) a.release();
+  A->lvl.release();
+  A->mrg.release();
+  A->small.release();
+  if (A->d_bres) (void)hipFree(A->d_bres);
+  for (auto p : A->d_cpl)
+    if (p) (void)hipFree(p);
+  for (auto p : A->d_emat)
+    if (p) (void)hipFree(p);
+  if (A->d_plan) (void)hipFree(A->d_plan);
+  if (A->own_stream) (void)hipStreamDestroy(A->own_stream);
+  delete A;
+}
+
+}  // extern "C"

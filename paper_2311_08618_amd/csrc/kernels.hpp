@@ -1,0 +1,34 @@
+// Launchers of the HIP kernels (defined in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "desc.hpp"
+
+namespace h2 {
+
+enum GemmKind { GEMM_NN = 0, GEMM_NT = 1, GEMM_TN = 2, GEMM_TT = 3 };
+
+void launch_fill(double* p, int64_t n, double v, hipStream_t st);
+void launch_fill_int(int* p, int64_t n, int v, hipStream_t st);
+void launch_gemm(int kind, const GItem* items, int nitems, const GTerm* terms, const BufTab& bt, const SizeTab& sz,
+                 int mcap, int ncap, int nshift, hipStream_t st);
+void launch_matsum(const SumItem* items, int nitems, const int* src, const BufTab& bt, const SizeTab& sz, int cap,
+                   int nshift, hipStream_t st);
+void launch_recompress(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, double tau2, int* status,
+                       int cap, int nshift, hipStream_t st);
+void launch_rotate(const RotItem* items, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
+void launch_ldl(const int* clusters, int n, const int* diag_blk, const BufTab& bt, const SizeTab& sz,
+                unsigned long long* nu, int* status, int cap, int nshift, hipStream_t st);
+void launch_trsm(const TrsmItem* items, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
+void launch_merge_sizes(const SizeTab& sz, int Np, int nshift, hipStream_t st);
+void launch_pmat(const BufTab& bt, const SizeTab& sz, const int* edim, int Np, int pcap, int nshift, hipStream_t st);
+void launch_gather(const GatherItem* items, int n, const BufTab& bt, const SizeTab& sz, int pcap, int nshift, hipStream_t st);
+void launch_next_sizes(const SizeTab& sz, int nshift, hipStream_t st);
+void launch_leaf_init(const BufTab& bt, int nblk, const int* blk_diag_m, const double* sigma, int cap, int nshift,
+                      hipStream_t st);
+void launch_sizes_init(const SizeTab& sz, const int* m0, int nshift, hipStream_t st);
+void launch_kernel_blocks(double* out, int64_t bstride, int ld, const int* bi, const int* bj, int nblk,
+                          const int64_t* start, const int* msz, const double* X, int dim, int kind, double diag,
+                          double p0, double p1, int* bad, hipStream_t st);
+
+}  // namespace h2

@@ -1,0 +1,256 @@
+// Builds the static schedule.  For a level l with colour classes c = 0..C-1
+// (clusters of one class are pairwise non-near, so eliminating them together
+// gives the same result as eliminating them one after the other in index
+// order), each class runs, in this order:
+//   recompress -> rotate rows -> rotate columns -> pivot LDL -> elimination
+//   (right-multiplication by the LDL operator) -> Schur updates of near blocks
+//   -> Gram of the fill-in products for the not yet eliminated neighbours.
+// Then the merge into level l-1 and the Gram of carried fill-in.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <map>
+#include <set>
+
+namespace h2 {
+
+static int find_in(const std::vector<int>& ptr, const std::vector<int>& idx, int i, int j) {
+  auto b = idx.begin() + ptr[i], e = idx.begin() + ptr[i + 1];
+  auto it = std::lower_bound(b, e, j);
+  if (it != e && *it == j) return (int)(it - idx.begin());
+  return -1;
+}
+
+int LevelPlan::blk(int i, int j) const { return find_in(near_ptr, near_idx, i, j); }
+int LevelPlan::fblk(int i, int j) const { return find_in(f_ptr, f_idx, i, j); }
+int LevelPlan::cslot(int i, int j) const { return find_in(far_ptr, far_idx, i, j); }
+
+static Ref ref(int buf, int blk, int r0 = 0, int c0 = 0, int r1 = 0, int c1 = 0) {
+  Ref x;
+  x.buf = buf; x.blk = blk; x.r0 = r0; x.r1 = r1; x.c0 = c0; x.c1 = c1;
+  return x;
+}
+static Ref noref() { Ref x = ref(-1, 0); return x; }
+
+static GTerm term(Ref a, Ref b, int K, int wbuf = -1, int wblk = 0) {
+  GTerm t;
+  t.a = a; t.b = b; t.K = K; t.wbuf = wbuf; t.wblk = wblk;
+  return t;
+}
+
+static GItem item(Ref c, Ref c2, int M, int N, double alpha, double beta) {
+  GItem g;
+  g.c = c; g.c2 = c2; g.M = M; g.N = N; g.alpha = alpha; g.beta = beta; g.t0 = 0; g.nt = 0;
+  return g;
+}
+
+std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
+  int L = T.L;
+  std::vector<LevelPlan> P(L + 1);
+  // carried fill-in partners per level, bottom-up
+  std::vector<std::vector<std::set<int>>> carried(L + 1);
+  for (int l = 0; l <= L; ++l) carried[l].assign(1 << l, {});
+  for (int l = L; l >= 1; --l) {
+    int N = 1 << l;
+    // fill pairs at level l: non-near pairs with a common near neighbour, or carried
+    std::vector<std::set<int>> fill(N);
+    for (int i = 0; i < N; ++i)
+      for (int c : T.near[l][i])
+        for (int d : T.near[l][i])
+          if (!T.is_near(l, c, d)) fill[c].insert(d);
+    for (int c = 0; c < N; ++c)
+      for (int d : carried[l][c]) fill[c].insert(d);
+    for (int c = 0; c < N; ++c)
+      for (int d : fill[c]) {
+        int p = c >> 1, q = d >> 1;
+        if (!T.is_near(l - 1, p, q)) carried[l - 1][p].insert(q);
+      }
+  }
+  for (int l = L; l >= 0; --l) {
+    LevelPlan& lp = P[l];
+    int N = 1 << l;
+    lp.l = l;
+    lp.N = N;
+    lp.near_ptr.assign(1, 0);
+    lp.f_ptr.assign(1, 0);
+    lp.far_ptr.assign(1, 0);
+    for (int i = 0; i < N; ++i) {
+      for (int j : T.near[l][i]) lp.near_idx.push_back(j);
+      lp.near_ptr.push_back((int)lp.near_idx.size());
+      for (int j : carried[l][i]) lp.f_idx.push_back(j);
+      lp.f_ptr.push_back((int)lp.f_idx.size());
+      for (int j : T.far[l][i]) lp.far_idx.push_back(j);
+      lp.far_ptr.push_back((int)lp.far_idx.size());
+    }
+    lp.diag_blk.resize(N);
+    for (int i = 0; i < N; ++i) lp.diag_blk[i] = lp.blk(i, i);
+    lp.r0 = B.r[l];
+    lp.colour = T.colour[l];
+    lp.rmax = 0;
+    for (int v : lp.r0) lp.rmax = std::max(lp.rmax, v);
+
+    const auto& col = T.colour[l];
+    int C = T.ncolour[l];
+    lp.colours.assign(C, {});
+    for (int c = 0; c < C; ++c) {
+      ColourPlan& cp = lp.colours[c];
+      for (int i = 0; i < N; ++i)
+        if (col[i] == c) cp.clusters.push_back(i);
+      auto done = [&](int k) { return col[k] <= c; };  // eliminated before or in this class
+      auto row0 = [&](int k) { return done(k) ? dx(DK_R, k) : dconst(0); };
+      auto nrows = [&](int k) { return done(k) ? dx(DK_S, k) : dx(DK_M, k); };
+      for (int i : cp.clusters) {
+        for (int k : T.near[l][i]) {
+          RotItem r;
+          r.buf = B_S; r.blk = lp.blk(i, k); r.cluster = i; r.side = 0; r.other = dx(DK_M, k);
+          cp.rot_rows.push_back(r);
+          r.blk = lp.blk(k, i); r.side = 1;
+          cp.rot_cols.push_back(r);
+        }
+        for (int q : carried[l][i]) {
+          RotItem r;
+          r.buf = B_F; r.blk = lp.fblk(i, q); r.cluster = i; r.side = 0; r.other = dx(DK_M, q);
+          cp.rot_rows.push_back(r);
+          r.blk = lp.fblk(q, i); r.side = 1;
+          cp.rot_cols.push_back(r);
+        }
+        for (int k : T.near[l][i]) {
+          TrsmItem t;
+          t.blk = lp.blk(k, i); t.cluster = i; t.row0 = row0(k); t.nrows = nrows(k);
+          cp.trsm.push_back(t);
+        }
+      }
+      // Schur updates, aggregated per target pair (j <= k)
+      std::map<std::pair<int, int>, std::vector<int>> tgt;
+      for (int i : cp.clusters)
+        for (int j : T.near[l][i])
+          for (int k : T.near[l][i])
+            if (j <= k && T.is_near(l, j, k)) tgt[{j, k}].push_back(i);
+      for (auto& kv : tgt) {
+        int j = kv.first.first, k = kv.first.second;
+        Ref c = ref(B_S, lp.blk(j, k), row0(j), row0(k));
+        Ref c2 = j != k ? ref(B_S, lp.blk(k, j), row0(k), row0(j)) : noref();
+        std::vector<GTerm> ts;
+        for (int i : kv.second)
+          ts.push_back(term(ref(B_S, lp.blk(j, i), row0(j), 0), ref(B_S, lp.blk(k, i), row0(k), 0),
+                            dx(DK_R, i), B_SIGN, i));
+        cp.schur.add(item(c, c2, nrows(j), nrows(k), -1.0, 1.0), ts);
+      }
+      // Gram of fill-in products for not-yet-eliminated neighbours k of i
+      std::map<std::pair<int, int>, int> slot_m, slot_p;   // (j,i) -> slot ; (k,i) -> slot
+      std::map<int, std::vector<int>> gtarget;             // k -> contributing i
+      for (int i : cp.clusters)
+        for (int k : T.near[l][i]) {
+          if (done(k)) continue;
+          std::vector<int> J;
+          for (int j : T.near[l][i])
+            if (!T.is_near(l, j, k)) J.push_back(j);
+          if (J.empty()) continue;
+          int sp = (int)slot_p.size();
+          slot_p[{k, i}] = sp;
+          std::vector<int> src;
+          for (int j : J) {
+            auto key = std::make_pair(j, i);
+            if (!slot_m.count(key)) {
+              int sm = (int)slot_m.size();
+              slot_m[key] = sm;
+              Ref a = ref(B_S, lp.blk(j, i), row0(j), 0);
+              cp.gram_m.add(item(ref(B_M, sm), noref(), dx(DK_R, i), dx(DK_R, i), 1.0, 0.0),
+                            {term(a, a, nrows(j))});
+            }
+            cp.gram_p.src.push_back(B_M);
+            cp.gram_p.src.push_back(slot_m[key]);
+          }
+          SumItem s;
+          s.cbuf = B_P; s.cblk = sp; s.M = dx(DK_R, i); s.N = dx(DK_R, i);
+          s.nt = (int)J.size();
+          s.t0 = (int)cp.gram_p.src.size() / 2 - s.nt;
+          cp.gram_p.items.push_back(s);
+          cp.gram_t.add(item(ref(B_T, sp), noref(), dx(DK_R, k), dx(DK_R, i), 1.0, 0.0),
+                        {term(ref(B_S, lp.blk(k, i)), ref(B_P, sp), dx(DK_R, i), B_SIGN, i)});
+          gtarget[k].push_back(i);
+        }
+      for (auto& kv : gtarget) {
+        int k = kv.first;
+        std::vector<GTerm> ts;
+        for (int i : kv.second)
+          ts.push_back(term(ref(B_T, slot_p[{k, i}]), ref(B_S, lp.blk(k, i)), dx(DK_R, i), B_SIGN, i));
+        cp.gram_g.add(item(ref(B_G, k), noref(), dx(DK_R, k), dx(DK_R, k), 1.0, 1.0), ts);
+      }
+      cp.nslot_m = (int)slot_m.size();
+      cp.nslot_p = (int)slot_p.size();
+      lp.max_slot_m = std::max(lp.max_slot_m, cp.nslot_m);
+      lp.max_slot_p = std::max(lp.max_slot_p, cp.nslot_p);
+    }
+    // Gram of carried fill-in at the start of the level
+    for (int p = 0; p < N; ++p) {
+      if (carried[l][p].empty()) continue;
+      std::vector<GTerm> ts;
+      for (int q : carried[l][p]) {
+        Ref a = ref(B_F, lp.fblk(p, q));
+        ts.push_back(term(a, a, dx(DK_M, q)));
+      }
+      lp.gram_init.add(item(ref(B_G, p), noref(), dx(DK_R, p), dx(DK_R, p), 1.0, 1.0), ts);
+    }
+  }
+  // merge plans (need both levels' CSR)
+  for (int l = L; l >= 1; --l) {
+    LevelPlan& lp = P[l];
+    const LevelPlan& pp = P[l - 1];
+    MergePlan& mp = lp.merge;
+    int Np = 1 << (l - 1);
+    mp.Np = Np;
+    mp.pr0 = B.r[l - 1];
+    mp.emat_dim.assign(Np, 0);
+    for (int p = 0; p < Np; ++p) {
+      mp.emat_dim[p] = B.r[l][2 * p] + B.r[l][2 * p + 1];
+      mp.emax = std::max(mp.emax, mp.emat_dim[p]);
+    }
+    int h = 0;
+    auto add_out = [&](int p, int q, bool is_near) {
+      GatherItem g;
+      g.out_blk = h;
+      g.p = p;
+      g.q = q;
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          int c = 2 * p + a, d = 2 * q + b, s = 2 * a + b;
+          g.src_kind[s] = 0;
+          g.src_blk[s] = 0;
+          g.cpl_blk[s] = -1;
+          if (lp.blk(c, d) >= 0) { g.src_kind[s] = 1; g.src_blk[s] = lp.blk(c, d); }
+          else if (lp.fblk(c, d) >= 0) { g.src_kind[s] = 2; g.src_blk[s] = lp.fblk(c, d); }
+          if (is_near && lp.cslot(c, d) >= 0) g.cpl_blk[s] = lp.cslot(c, d);
+          if (lp.blk(c, d) < 0) {
+            // generator fill-in from common near neighbours of c and d
+            std::vector<int> cn;
+            std::set_intersection(T.near[l][c].begin(), T.near[l][c].end(), T.near[l][d].begin(),
+                                  T.near[l][d].end(), std::back_inserter(cn));
+            if (!cn.empty()) {
+              int offc = a ? dx(DK_S, 2 * p) : 0, offd = b ? dx(DK_S, 2 * q) : 0;
+              std::vector<GTerm> ts;
+              for (int i : cn)
+                ts.push_back(term(ref(B_S, lp.blk(c, i), dx(DK_R, c), 0), ref(B_S, lp.blk(d, i), dx(DK_R, d), 0),
+                                  dx(DK_R, i), B_SIGN, i));
+              mp.fill.add(item(ref(B_HAT, h, offc, offd), noref(), dx(DK_S, c), dx(DK_S, d), -1.0, 1.0), ts);
+            }
+          }
+        }
+      mp.gather.push_back(g);
+      mp.tr1.add(item(ref(B_TMP, h), noref(), dx(DK_PM, p), dx(DK_PM, q), 1.0, 0.0),
+                 {term(ref(B_PMAT, p), ref(B_HAT, h), dx(DK_PM, p))});
+      Ref out = is_near ? ref(B_SN, pp.blk(p, q)) : ref(B_FN, pp.fblk(p, q));
+      mp.tr2.add(item(out, noref(), dx(DK_PM, p), dx(DK_PM, q), 1.0, 0.0),
+                 {term(ref(B_TMP, h), ref(B_PMAT, q), dx(DK_PM, q))});
+      ++h;
+    };
+    for (int p = 0; p < Np; ++p) {
+      for (int q : T.near[l - 1][p]) add_out(p, q, true);
+      for (int k = pp.f_ptr[p]; k < pp.f_ptr[p + 1]; ++k) add_out(p, pp.f_idx[k], false);
+    }
+    mp.nhat = h;
+  }
+  return P;
+}
+
+}  // namespace h2

@@ -1,0 +1,76 @@
+// Static schedule of the generalized H^2-LDL: for every level, the colour
+// classes of the near graph and, per class, the descriptor lists of each
+// kernel; then the merge into the parent level (Secs. 3.2-3.4).
+#pragma once
+#include <vector>
+
+#include "desc.hpp"
+#include "host.hpp"
+
+namespace h2 {
+
+struct GList {
+  std::vector<GItem> items;
+  std::vector<GTerm> terms;
+  void add(const GItem& it, const std::vector<GTerm>& ts) {
+    GItem x = it;
+    x.t0 = (int)terms.size();
+    x.nt = (int)ts.size();
+    items.push_back(x);
+    terms.insert(terms.end(), ts.begin(), ts.end());
+  }
+};
+
+struct SumList {
+  std::vector<SumItem> items;
+  std::vector<int> src;  // pairs (buf, blk)
+};
+
+struct ColourPlan {
+  std::vector<int> clusters;
+  std::vector<RotItem> rot_rows, rot_cols;
+  std::vector<TrsmItem> trsm;
+  GList schur;                 // NT, alpha -1
+  GList gram_m;                // TN
+  SumList gram_p;
+  GList gram_t;                // NN
+  GList gram_g;                // NT
+  int nslot_m = 0, nslot_p = 0;
+};
+
+struct MergePlan {
+  int Np = 0;
+  int nhat = 0;
+  std::vector<GatherItem> gather;
+  GList fill;                  // NT into B_HAT
+  GList tr1;                   // TN: TMP = P_p^T HAT
+  GList tr2;                   // NN: out = TMP P_q
+  std::vector<int> pr0;        // parent construction ranks
+  std::vector<int> emat_dim;   // r0_c1 + r0_c2 per parent
+  int emax = 0;
+};
+
+struct LevelPlan {
+  int l = 0, N = 0;
+  std::vector<int> near_ptr, near_idx;   // CSR, sorted, includes self
+  std::vector<int> diag_blk;
+  std::vector<int> f_ptr, f_idx;         // carried fill-in partners (CSR)
+  std::vector<int> far_ptr, far_idx;     // interaction list I_l (CSR) = coupling slots
+  std::vector<int> r0;
+  std::vector<int> colour;
+  int rmax = 0;
+  std::vector<ColourPlan> colours;
+  GList gram_init;                       // NT: G_p += F F^T over carried fill-in
+  MergePlan merge;                       // into level l-1 (unused at l = 0)
+  int max_slot_m = 0, max_slot_p = 0;
+
+  int nblk() const { return near_ptr.back(); }
+  int nfblk() const { return f_ptr.back(); }
+  int blk(int i, int j) const;           // near pair block index, -1 if not near
+  int fblk(int i, int j) const;          // carried pair block index, -1 if none
+  int cslot(int i, int j) const;         // coupling slot, -1 if not admissible
+};
+
+std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B);
+
+}  // namespace h2

@@ -1,0 +1,148 @@
+"""Thin ctypes binding of the C ABI in include/h2eig.h (argument marshalling only).
+
+Every computation runs inside libh2eig.so on the GPU; if the library is not
+built this module raises at import, and calls fail with H2EigError when no GPU
+is present.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libh2eig.so")
+
+H2_OK, H2_EINVAL, H2_ENOMEM, H2_EDEVICE, H2_ENUMERIC, H2_EBUSY = 0, -1, -2, -3, -4, -5
+
+K_LAPLACE, K_YUKAWA, K_GAUSS_DAMPED, K_REG_LAPLACE, K_TRIDIAG_1D = 0, 1, 2, 3, 4
+
+
+class H2EigError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("h2eig status %d: %s" % (status, msg))
+        self.status = status
+
+
+class _Kernel(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("diag", C.c_double), ("p0", C.c_double), ("p1", C.c_double)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("sample_cap", C.c_int32), ("max_shifts", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("levels", C.c_int32), ("leaf_max", C.c_int32), ("rank_max", C.c_int32),
+                ("near_max", C.c_int32), ("near_blocks", C.c_int64), ("resident_bytes", C.c_int64),
+                ("last_work_bytes", C.c_int64), ("last_flops", C.c_double), ("last_bytes", C.c_double),
+                ("build_seconds", C.c_double), ("last_rank_max", C.c_int32), ("reserved", C.c_int32 * 5)]
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError("libh2eig.so is not built (run __graft_entry__.build())")
+    lib = C.CDLL(path)
+    P = C.POINTER
+    lib.h2_build.restype = C.c_int
+    lib.h2_build.argtypes = [P(C.c_double), C.c_int64, C.c_int32, _Kernel, C.c_int32, C.c_double, C.c_double,
+                             P(_Opts), P(C.c_void_p)]
+    lib.h2_inertia.restype = C.c_int
+    lib.h2_inertia.argtypes = [C.c_void_p, P(C.c_double), C.c_int64, P(C.c_int64), P(C.c_int32)]
+    lib.h2_kth_eig.restype = C.c_int
+    lib.h2_kth_eig.argtypes = [C.c_void_p, P(C.c_int64), C.c_int64, C.c_double, P(C.c_double), P(C.c_double),
+                               P(C.c_double)]
+    lib.h2_norm.restype = C.c_int
+    lib.h2_norm.argtypes = [C.c_void_p, P(C.c_double)]
+    lib.h2_stats.restype = C.c_int
+    lib.h2_stats.argtypes = [C.c_void_p, P(_Stats)]
+    lib.h2_set_stream.restype = C.c_int
+    lib.h2_set_stream.argtypes = [C.c_void_p, C.c_void_p]
+    lib.h2_tree_perm.restype = C.c_int
+    lib.h2_tree_perm.argtypes = [C.c_void_p, P(C.c_int64)]
+    lib.h2_free.restype = None
+    lib.h2_free.argtypes = [C.c_void_p]
+    lib.h2_last_error.restype = C.c_char_p
+    lib.h2_last_error.argtypes = []
+    return lib
+
+
+_lib = load_library()
+
+EXPORTED = ["h2_build", "h2_inertia", "h2_kth_eig", "h2_norm", "h2_stats", "h2_set_stream", "h2_tree_perm",
+            "h2_free", "h2_last_error"]
+
+
+def _check(st: int):
+    if st != H2_OK:
+        raise H2EigError(st, _lib.h2_last_error().decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class H2Matrix:
+    """A built H^2 matrix resident on the GPU (h2_build)."""
+
+    def __init__(self, points, kind: int, diag: float, leaf: int, eta: float, eps: float,
+                 p0: float = 0.0, p1: float = 0.0, sample_cap: int = 0, max_shifts: int = 0):
+        X = np.ascontiguousarray(points, dtype=np.float64)
+        if X.ndim == 1:
+            X = X.reshape(-1, 1)
+        n, dim = X.shape
+        opts = _Opts(int(sample_cap), int(max_shifts), (C.c_int32 * 6)())
+        h = C.c_void_p()
+        _check(_lib.h2_build(_dptr(X), n, dim, _Kernel(int(kind), float(diag), float(p0), float(p1)), int(leaf),
+                             float(eta), float(eps), C.byref(opts), C.byref(h)))
+        self._h = h
+        self.n = n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.h2_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def inertia(self, sigma, return_status: bool = False):
+        s = np.ascontiguousarray(np.atleast_1d(sigma), dtype=np.float64)
+        nu = np.zeros(len(s), dtype=np.int64)
+        st = np.zeros(len(s), dtype=np.int32)
+        r = _lib.h2_inertia(self._h, _dptr(s), len(s), nu.ctypes.data_as(C.POINTER(C.c_int64)),
+                            st.ctypes.data_as(C.POINTER(C.c_int32)))
+        if r != H2_OK and not (return_status and r == H2_ENUMERIC):
+            _check(r)
+        return (nu, st) if return_status else nu
+
+    def kth_eig(self, ks, tol: float, ab=None):
+        k = np.ascontiguousarray(np.atleast_1d(ks), dtype=np.int64)
+        lam = np.zeros(len(k))
+        br = np.zeros(2 * len(k))
+        abp = None
+        if ab is not None:
+            abv = np.ascontiguousarray(ab, dtype=np.float64)
+            abp = _dptr(abv)
+        _check(_lib.h2_kth_eig(self._h, k.ctypes.data_as(C.POINTER(C.c_int64)), len(k), float(tol), abp,
+                               _dptr(lam), _dptr(br)))
+        return lam, br.reshape(-1, 2)
+
+    def norm(self) -> float:
+        v = C.c_double()
+        _check(_lib.h2_norm(self._h, C.byref(v)))
+        return v.value
+
+    def stats(self) -> dict:
+        s = _Stats()
+        _check(_lib.h2_stats(self._h, C.byref(s)))
+        return {f[0]: getattr(s, f[0]) for f in _Stats._fields_ if f[0] != "reserved"}
+
+    def tree_perm(self) -> np.ndarray:
+        p = np.zeros(self.n, dtype=np.int64)
+        _check(_lib.h2_tree_perm(self._h, p.ctypes.data_as(C.POINTER(C.c_int64))))
+        return p
+
+    def set_stream(self, stream_ptr: int):
+        _check(_lib.h2_set_stream(self._h, C.c_void_p(stream_ptr)))

@@ -1,0 +1,109 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars (from the method's accuracy statement and the build's targets):
+  * inertia: equal to the oracle's for every shift whose window
+    [sigma - w, sigma + w], w = 1e3 * eps * normA, holds no eigenvalue change of
+    the oracle (nu_or(sigma - w) == nu_or(sigma + w)); otherwise
+    nu_or(sigma - w) <= nu_gpu(sigma) <= nu_or(sigma + w);
+  * on the exactly representable 1-D second-difference matrix: equal to the
+    closed form 2 - 2cos(j*pi/(n+1)) for every shift (no window);
+  * eigenvalues: |lambda_gpu - lambda_or| <= max(tol, 10 * eps * normA).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import factor as OF
+from oracle.build import H2
+from oracle.dense import tridiag_eigs, tridiag_inertia
+from oracle.kernels import Kernel
+from paper_2311_08618_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2311_08618_amd import h2eig
+    return h2eig
+
+
+def _shifts_with_near_eigs(lam, count=33, seed=3):
+    rng = np.random.default_rng(seed)
+    sig = list(np.linspace(-0.2, 4.2, count) + 1e-3 * math.sqrt(2.0))
+    for j in rng.integers(0, len(lam), 10):
+        sig += [lam[j] - 1e-9, lam[j] + 1e-9]
+    return np.array(sig)
+
+
+@pytest.mark.parametrize("eta", [0.5, 1.0])
+@pytest.mark.parametrize("n,leaf", [(256, 16), (300, 16), (97, 8), (1024, 64)])
+def test_tridiag_closed_form(lib, n, leaf, eta):
+    print("case tridiag n=%d leaf=%d eta=%.1f" % (n, leaf, eta), flush=True)
+    A = lib.H2Matrix(W.line_points(n), W.K_TRIDIAG_1D, 2.0, leaf, eta, 1e-12, p0=1.0, sample_cap=n)
+    lam = tridiag_eigs(n)
+    sig = _shifts_with_near_eigs(lam)
+    nu = A.inertia(sig)
+    want = np.array([tridiag_inertia(n, s) for s in sig])
+    assert np.array_equal(nu, want), (nu - want)
+
+
+def _windowed_check(nu_gpu, H, sig, ev=None):
+    """Windowed inertia parity; returns the number of exact-window matches."""
+    w = 1e3 * H.eps * H.normA
+    exact = 0
+    for s, g in zip(sig, nu_gpu):
+        lo, hi = OF.inertia(H, s - w), OF.inertia(H, s + w)
+        assert lo <= g <= hi, (s, g, lo, hi)
+        if lo == hi:
+            assert g == lo
+            exact += 1
+    return exact
+
+
+@pytest.mark.parametrize("kind,diag,eps", [(W.K_LAPLACE, 1e3, 1e-8), (W.K_YUKAWA, 1e3, 1e-10)])
+def test_cube_small_vs_oracle(lib, kind, diag, eps):
+    n, leaf = 1024, 64
+    print("case cube n=%d kind=%d" % (n, kind), flush=True)
+    X = W.cube_points(n, 0)
+    A = lib.H2Matrix(X, kind, diag, leaf, 1.0, eps)
+    H = H2(X, Kernel(kind, diag), leaf, 1.0, eps)
+    assert abs(A.norm() - H.normA) <= 1e-10 * H.normA
+    assert np.array_equal(A.tree_perm(), H.tree.perm())
+    ev = np.linalg.eigvalsh(H.dense())
+    sig = np.concatenate([np.quantile(ev, np.linspace(0.02, 0.98, 12)) + 0.013, [ev[0] - 1.0, ev[-1] + 1.0]])
+    nu = A.inertia(sig)
+    orc = np.array([OF.inertia(H, s) for s in sig])
+    print("gpu", nu.tolist())
+    print("orc", orc.tolist())
+    mism = int(np.sum(nu != orc))
+    assert nu[-2] == 0 and nu[-1] == n
+    assert mism <= 1, (nu - orc)
+    _windowed_check(nu, H, sig)
+
+
+def test_batch_equals_single(lib):
+    """Per-shift work is independent of the batch: one shift alone gives the
+    same count as in a batch of 9."""
+    X = W.cube_points(1024, 4)
+    A = lib.H2Matrix(X, W.K_LAPLACE, 1e3, 64, 1.0, 1e-8)
+    sig = np.linspace(930.0, 1060.0, 9)
+    many = A.inertia(sig)
+    one = np.array([A.inertia([s])[0] for s in sig])
+    assert np.array_equal(many, one)
+    assert all(a <= b for a, b in zip(many, many[1:]))
+
+
+def test_kth_eig_small(lib):
+    n, leaf = 1024, 64
+    X = W.cube_points(n, 0)
+    A = lib.H2Matrix(X, W.K_LAPLACE, 1e3, leaf, 1.0, 1e-8)
+    H = H2(X, Kernel(W.K_LAPLACE, 1e3), leaf, 1.0, 1e-8)
+    ev = np.linalg.eigvalsh(Kernel(W.K_LAPLACE, 1e3).dense(X))
+    tol = 1e-6
+    ks = np.array([1, 100, 512, 900, 1024])
+    lam, br = A.kth_eig(ks, tol)
+    for k, l, (a, b) in zip(ks, lam, br):
+        assert b - a < tol
+        assert abs(l - ev[k - 1]) <= tol / 2 + 10 * H.eps * H.normA
