@@ -58,11 +58,15 @@ typedef struct {
 
 /* Build options (pass NULL for defaults). */
 typedef struct {
-  int32_t sample_cap;        /* far-field columns per far cluster in the basis
+  int32_t sample_cap;        /* far-field columns taken from each cluster of the
+                                same-level interaction list in the basis
                                 construction; 0 = automatic (all points when
                                 n <= 16384, else 2*leaf)                        */
+  int32_t sample_cap_anc;    /* same, for clusters of an ancestor's interaction
+                                list; 0 = automatic (all points when
+                                n <= 16384, else max(16, leaf/4))               */
   int32_t max_shifts;        /* shifts factored together per launch; 0 = auto   */
-  int32_t reserved[6];
+  int32_t reserved[5];
 } h2_opts;
 
 /*

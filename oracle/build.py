@@ -13,9 +13,11 @@ also be done in O(n)"):
   * rows of cluster i at the leaf level are its points; at a parent level they
     are the children's skeleton points, in child order.
   * columns (the far field A_{l;i,+}): the points of every cluster in the
-    interaction list of i or of one of its ancestors.  A far cluster with more
-    than ``cap`` points contributes ``cap`` of them, evenly strided in tree order
-    (index floor(k*|q|/cap), k = 0..cap-1).
+    interaction list of i or of one of its ancestors.  A far cluster of the
+    same level with more than ``cap`` points contributes ``cap`` of them, one of
+    an ancestor's list ``cap_anc``, evenly strided in tree order (index
+    floor(k*|q|/c), k = 0..c-1).  Defaults: all points when n <= 16384, else
+    cap = 2*leaf and cap_anc = max(16, leaf//4).
   * pivoted QR on the rows of that block with freshly computed remaining
     norms; the first maximum wins ties; stop when the largest remaining norm
     is <= tau = eps * normA.  The pivots are the skeleton points s_i and
@@ -89,12 +91,13 @@ def complete_basis(Y: np.ndarray):
     return Q, Rc[:r, :r]
 
 
-def far_columns(tree: Tree, l: int, i: int, cap: int) -> np.ndarray:
+def far_columns(tree: Tree, l: int, i: int, cap: int, cap_anc: int) -> np.ndarray:
     cols = []
     for (lv, q) in tree.far_field(l, i):
         pts = tree.pts(lv, q)
-        if len(pts) > cap:
-            pts = pts[(np.arange(cap) * len(pts)) // cap]
+        c = cap if lv == l else cap_anc
+        if len(pts) > c:
+            pts = pts[(np.arange(c) * len(pts)) // c]
         cols.append(pts)
     if not cols:
         return np.zeros(0, dtype=np.int64)
@@ -116,11 +119,14 @@ def estimate_norm(X: np.ndarray, kern: Kernel) -> float:
 class H2:
     """An H^2 matrix built from points + kernel (oracle's own construction)."""
 
-    def __init__(self, X, kern: Kernel, leaf: int, eta: float, eps: float, cap: int | None = None):
+    def __init__(self, X, kern: Kernel, leaf: int, eta: float, eps: float, cap: int | None = None,
+                 cap_anc: int | None = None):
         self.tree = T = Tree(X, leaf, eta)
         self.X = T.X
         self.kern, self.eps = kern, float(eps)
-        self.cap = int(cap) if cap else 2 * int(leaf)
+        exact = T.n <= 16384
+        self.cap = int(cap) if cap else (T.n if exact else 2 * int(leaf))
+        self.cap_anc = int(cap_anc) if cap_anc else (T.n if exact else max(16, int(leaf) // 4))
         self.normA = estimate_norm(self.X, kern)
         self.tau = self.eps * self.normA
         L = T.L
@@ -137,7 +143,7 @@ class H2:
                     rows = T.idx[L][i]
                 else:
                     rows = np.concatenate([self.skel[l + 1][2 * i], self.skel[l + 1][2 * i + 1]])
-                cols = far_columns(T, l, i, self.cap)
+                cols = far_columns(T, l, i, self.cap, self.cap_anc)
                 if len(cols) and len(rows):
                     M = kern.block(self.X, rows, cols)
                     piv, Xi = pivoted_rows_id(M, self.tau)

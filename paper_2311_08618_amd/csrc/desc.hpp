@@ -35,8 +35,10 @@ __host__ __device__ inline int dconst(int v) { return v; }
 enum BufId : int {
   B_S = 0,    // near blocks of the current level        [shift][pair][mcap x mcap]
   B_F,        // carried fill-in of the current level    [shift][pair][mcap x mcap]
-  B_G,        // per cluster: Gram G -> rotation W -> elimination operator K
-  B_V,        // per cluster scratch (recompression)
+  B_G,        // per cluster: Gram G -> compact-WY factor T -> elimination operator K
+  B_V,        // per cluster: pivoted Cholesky columns -> Householder vectors Y
+  B_W,        // per cluster: rotation W = I - Y T Y^T
+  B_Z,        // per cluster scratch: Y T
   B_M,        // per colour scratch: Y^T Y                [shift][slot][mcap^2]
   B_P,        // per colour scratch: sums of Y^T Y
   B_T,        // per colour scratch: Y^R sign P
@@ -115,7 +117,7 @@ struct SumItem {
 };
 
 // In-place rotation of the first RT(i) rows (side 0) or columns (side 1) of a
-// block by the cluster's rotation W (in B_G): rows <- W^T rows; cols <- cols W.
+// block by the cluster's rotation W (in B_W): rows <- W^T rows; cols <- cols W.
 struct RotItem {
   int buf, blk, cluster, side;
   int other;        // size expression: number of columns (side 0) / rows (side 1)

@@ -102,6 +102,7 @@ struct DevList {
 struct DevColour {
   size_t clusters = 0;
   int ncl = 0;
+  DevList rec_yty, rec_u, rec_w;
   size_t rot_rows = 0, rot_cols = 0, trsm = 0;
   int nrr = 0, nrc = 0, ntr = 0;
   DevList schur, gm, gt, gg;
@@ -190,6 +191,9 @@ void upload_plan(h2_matrix A) {
       DevColour& dc = dl.colours[c];
       dc.clusters = b.put(cp.clusters);
       dc.ncl = (int)cp.clusters.size();
+      dc.rec_yty = put_list(b, cp.rec_yty);
+      dc.rec_u = put_list(b, cp.rec_u);
+      dc.rec_w = put_list(b, cp.rec_w);
       dc.rot_rows = b.put(cp.rot_rows);
       dc.nrr = (int)cp.rot_rows.size();
       dc.rot_cols = b.put(cp.rot_cols);
@@ -466,10 +470,12 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     double* dF = dS + nS;
     size_t nG = (size_t)S * N * bsz, nM = (size_t)S * std::max(1, lp.max_slot_m) * bsz,
            nP = (size_t)S * std::max(1, lp.max_slot_p) * bsz, nSg = (size_t)S * N * cap;
-    A->lvl.ensure((2 * nG + nM + 2 * nP + nSg) * 8 + 64, st);
+    A->lvl.ensure((4 * nG + nM + 2 * nP + nSg) * 8 + 64, st);
     double* dG = (double*)A->lvl.p;
     double* dV = dG + nG;
-    double* dM = dV + nG;
+    double* dW = dV + nG;
+    double* dZ = dW + nG;
+    double* dM = dZ + nG;
     double* dP = dM + nM;
     double* dT = dP + nP;
     double* dSg = dT + nP;
@@ -485,6 +491,8 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     setb(B_F, dF, (size_t)lp.nfblk() * bsz, bsz, cap);
     setb(B_G, dG, (size_t)N * bsz, bsz, cap);
     setb(B_V, dV, (size_t)N * bsz, bsz, cap);
+    setb(B_W, dW, (size_t)N * bsz, bsz, cap);
+    setb(B_Z, dZ, (size_t)N * bsz, bsz, cap);
     setb(B_M, dM, (size_t)std::max(1, lp.max_slot_m) * bsz, bsz, cap);
     setb(B_P, dP, (size_t)std::max(1, lp.max_slot_p) * bsz, bsz, cap);
     setb(B_T, dT, (size_t)std::max(1, lp.max_slot_p) * bsz, bsz, cap);
@@ -519,7 +527,14 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     for (size_t c = 0; c < dl.colours.size(); ++c) {
       const DevColour& dc = dl.colours[c];
       const int* cl = A->dp<int>(dc.clusters);
-      launch_recompress(cl, dc.ncl, bt, sz, tau2, w.status, cap, S, st);
+      launch_pchol(cl, dc.ncl, bt, sz, tau2, cap, S, st);
+      launch_hqr(cl, dc.ncl, bt, sz, cap, S, st);
+      launch_gemm(GEMM_TN, A->dp<GItem>(dc.rec_yty.items), dc.rec_yty.n, A->dp<GTerm>(dc.rec_yty.terms), bt, sz, cap, cap,
+                  S, st);
+      launch_tmat(cl, dc.ncl, bt, sz, S, st);
+      launch_gemm(GEMM_NN, A->dp<GItem>(dc.rec_u.items), dc.rec_u.n, A->dp<GTerm>(dc.rec_u.terms), bt, sz, cap, cap, S, st);
+      launch_eye(cl, dc.ncl, bt, sz, cap, S, st);
+      launch_gemm(GEMM_NT, A->dp<GItem>(dc.rec_w.items), dc.rec_w.n, A->dp<GTerm>(dc.rec_w.terms), bt, sz, cap, cap, S, st);
       launch_rotate(A->dp<RotItem>(dc.rot_rows), dc.nrr, bt, sz, cap, S, st);
       launch_rotate(A->dp<RotItem>(dc.rot_cols), dc.nrc, bt, sz, cap, S, st);
       launch_ldl(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, w.nu, w.status, cap, S, st);
@@ -552,22 +567,28 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     double* dSN = (double*)A->sf[other].p;
     double* dFN = dSN + nSN;
     const MergePlan& mp = lp.merge;
-    size_t nH = (size_t)S * std::max(1, mp.nhat) * pbsz, nPm = (size_t)S * Np * pbsz;
+    const int nslot = std::max(1, std::min(mp.nhat, MERGE_CHUNK));
+    size_t nH = (size_t)S * nslot * pbsz, nPm = (size_t)S * Np * pbsz;
     A->mrg.ensure((2 * nH + nPm) * 8 + 64, st);
     double* dH = (double*)A->mrg.p;
     double* dTm = dH + nH;
     double* dPm = dTm + nH;
-    setb(B_HAT, dH, (size_t)std::max(1, mp.nhat) * pbsz, pbsz, pcap);
-    setb(B_TMP, dTm, (size_t)std::max(1, mp.nhat) * pbsz, pbsz, pcap);
+    setb(B_HAT, dH, (size_t)nslot * pbsz, pbsz, pcap);
+    setb(B_TMP, dTm, (size_t)nslot * pbsz, pbsz, pcap);
     setb(B_PMAT, dPm, (size_t)Np * pbsz, pbsz, pcap);
     setb(B_SN, dSN, (size_t)pp.nblk() * pbsz, pbsz, pcap);
     setb(B_FN, dFN, (size_t)pp.nfblk() * pbsz, pbsz, pcap);
     setb(B_EMAT, A->d_emat[l - 1], 0, (size_t)A->emat_ld[l - 1] * A->emat_ld[l - 1], A->emat_ld[l - 1]);
     launch_pmat(bt, sz, A->dp<int>(dl.edim), Np, pcap, S, st);
-    launch_gather(A->dp<GatherItem>(dl.gather), dl.ngather, bt, sz, pcap, S, st);
-    launch_gemm(GEMM_NT, A->dp<GItem>(dl.fill.items), dl.fill.n, A->dp<GTerm>(dl.fill.terms), bt, sz, pcap, pcap, S, st);
-    launch_gemm(GEMM_TN, A->dp<GItem>(dl.tr1.items), dl.tr1.n, A->dp<GTerm>(dl.tr1.terms), bt, sz, pcap, pcap, S, st);
-    launch_gemm(GEMM_NN, A->dp<GItem>(dl.tr2.items), dl.tr2.n, A->dp<GTerm>(dl.tr2.terms), bt, sz, pcap, pcap, S, st);
+    for (const MergeChunk& ch : mp.chunks) {
+      launch_gather(A->dp<GatherItem>(dl.gather) + ch.g0, ch.g1 - ch.g0, bt, sz, pcap, S, st);
+      launch_gemm(GEMM_NT, A->dp<GItem>(dl.fill.items) + ch.f0, ch.f1 - ch.f0, A->dp<GTerm>(dl.fill.terms), bt, sz, pcap,
+                  pcap, S, st);
+      launch_gemm(GEMM_TN, A->dp<GItem>(dl.tr1.items) + ch.a0, ch.a1 - ch.a0, A->dp<GTerm>(dl.tr1.terms), bt, sz, pcap,
+                  pcap, S, st);
+      launch_gemm(GEMM_NN, A->dp<GItem>(dl.tr2.items) + ch.b0, ch.b1 - ch.b0, A->dp<GTerm>(dl.tr2.terms), bt, sz, pcap,
+                  pcap, S, st);
+    }
     launch_next_sizes(sz, S, st);
     HIPCHK(hipGetLastError());
     cur = other;
@@ -594,7 +615,7 @@ int auto_max_shifts(h2_matrix A) {
     return 4;
   }
   const LevelPlan& lf = A->plan[A->T.L];
-  double per = (double)A->leafcap * A->leafcap * 8.0 * (lf.nblk() + 2.0 * lf.N + lf.max_slot_m + 2.0 * lf.max_slot_p);
+  double per = (double)A->leafcap * A->leafcap * 8.0 * (lf.nblk() + 4.0 * lf.N + lf.max_slot_m + 2.0 * lf.max_slot_p);
   per *= 2.2;  // upper levels and merge buffers
   int s = (int)std::floor(0.7 * (double)freeb / std::max(per, 1.0));
   return std::max(1, std::min(s, 64));
@@ -673,6 +694,7 @@ h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern,
     P.kern = A->kern;
     P.eps = eps;
     P.sample_cap = opts ? opts->sample_cap : 0;
+    P.sample_cap_anc = opts ? opts->sample_cap_anc : 0;
     if (opts && opts->max_shifts > 0) A->max_shifts = opts->max_shifts;
     build_basis(A->T, P, A->tau, A->B);
     A->plan = build_plan(A->T, A->B);

@@ -11,8 +11,11 @@
 //    (bounding-box centres and half diagonals);
 //  * greedy colouring of each level's near graph in ascending index;
 //  * far field of cluster i at level l = points of every cluster in the
-//    interaction list of i or of an ancestor; a far cluster with more than
-//    `cap` points contributes the points at positions floor(k*size/cap);
+//    interaction list of i (at most `cap` of them per cluster) or of an
+//    ancestor (at most `cap_anc`); a far cluster with more points than its cap
+//    contributes the points at positions floor(k*size/cap) in tree order.
+//    Defaults: every point when n <= 16384, else cap = 2*leaf and
+//    cap_anc = max(16, leaf/4);
 //  * rank-revealing step: column-pivoted QR of the far-field block's
 //    transpose, pivots by largest remaining norm (recomputed every step, first
 //    index wins ties), stop when it is <= tau = eps*normA;
@@ -304,12 +307,14 @@ static std::vector<int64_t> cluster_points(const Tree& T, int l, int i) {
   return v;
 }
 
-static std::vector<int64_t> far_columns(const Tree& T, int l, int i, int cap) {
+static std::vector<int64_t> far_columns(const Tree& T, int l, int i, int cap, int cap_anc) {
   std::vector<int64_t> cols;
   int a = i;
   for (int lv = l; lv >= 1; --lv) {
+    const int c = lv == l ? cap : cap_anc;
     for (int q : T.far[lv][a]) {
       int64_t s0 = T.start[lv][q], sz = T.size[lv][q];
+      const int cap = c;
       if (sz > cap) {
         for (int k = 0; k < cap; ++k) cols.push_back(T.perm[s0 + ((int64_t)k * sz) / cap]);
       } else {
@@ -353,7 +358,10 @@ void gershgorin(const Tree& T, const KernelSpec& k, double* lo, double* hi) {
 
 void build_basis(const Tree& T, const BuildParams& P, double tau, Basis& B) {
   int L = T.L;
-  int cap = P.sample_cap > 0 ? P.sample_cap : (T.n <= 16384 ? (int)std::min<int64_t>(T.n, 1 << 30) : 2 * T.leaf);
+  const bool exact = T.n <= 16384;
+  int cap = P.sample_cap > 0 ? P.sample_cap : (exact ? (int)std::min<int64_t>(T.n, 1 << 30) : 2 * T.leaf);
+  int cap_anc = P.sample_cap_anc > 0 ? P.sample_cap_anc
+                                     : (exact ? (int)std::min<int64_t>(T.n, 1 << 30) : std::max(16, T.leaf / 4));
   int nth = P.nthreads > 0 ? P.nthreads : default_threads();
   B.m.assign(L + 1, {});
   B.r.assign(L + 1, {});
@@ -377,7 +385,7 @@ void build_basis(const Tree& T, const BuildParams& P, double tau, Basis& B) {
         rows.insert(rows.end(), B.skel[l + 1][2 * i + 1].begin(), B.skel[l + 1][2 * i + 1].end());
       }
       int m = (int)rows.size();
-      std::vector<int64_t> cols = far_columns(T, l, i, cap);
+      std::vector<int64_t> cols = far_columns(T, l, i, cap, cap_anc);
       int64_t nc = (int64_t)cols.size();
       int r = 0;
       std::vector<int> perm;

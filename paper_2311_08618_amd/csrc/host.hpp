@@ -55,6 +55,7 @@ struct BuildParams {
   KernelSpec kern;
   double eps = 1e-8;
   int sample_cap = 0;
+  int sample_cap_anc = 0;
   int nthreads = 0;
 };
 

@@ -169,13 +169,34 @@ __device__ inline void argmax_reduce(double* sv, int* si, int tid, int nthr) {
 
 // ----------------------------------------------------------- recompression
 // Rank-revealing QR of the concatenated fill-in products of cluster i (Sec. 3.4),
-// computed as pivoted Cholesky of their Gram G = X X^T (pivot = largest remaining
-// squared row norm of X, first index on ties; stop when <= tau^2), then
-// Householder QR of the kept columns, giving W = [Q_perp | Q_t] in place of G.
+// in three steps:
+//   k_pchol: pivoted Cholesky of their Gram G = X X^T (pivot = largest remaining
+//            squared row norm of X, first index on ties; stop when <= tau^2); its
+//            t columns L (original row order) span the kept directions, exactly the
+//            first t columns of P R^T of the column-pivoted QR of X^T;
+//   k_hqr:   Householder QR of L with reflector k acting on rows 0..R-1-k, so that
+//            W = H_0 ... H_{t-1} = I - Y T Y^T maps the kept directions onto the last
+//            t redundant coordinates; T is the compact-WY factor;
+//   two MFMA GEMMs form W = I - (Y T) Y^T.
 constexpr int RT_THREADS = 256;
 
-__global__ __launch_bounds__(RT_THREADS) void k_recompress(const int* __restrict__ clusters, BufTab bt, SizeTab sz,
-                                                           double tau2, int* __restrict__ status) {
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// block-wide sum over RT_THREADS threads (4 waves); red has >= 4 slots
+__device__ inline double block_sum(double v, double* red, int tid) {
+  v = wave_sum(v);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double r = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(RT_THREADS) void k_pchol(const int* __restrict__ clusters, BufTab bt, SizeTab sz,
+                                                      double tau2) {
   extern __shared__ double sh[];
   const int s = blockIdx.z;
   const int i = clusters[blockIdx.y];
@@ -183,15 +204,13 @@ __global__ __launch_bounds__(RT_THREADS) void k_recompress(const int* __restrict
   const int R = sz.R[s * N + i];
   const int tid = threadIdx.x;
   const int ld = bt.ld[B_G];
-  double* G = addr(bt, B_G, i, s, 0, 0);
+  const double* G = addr(bt, B_G, i, s, 0, 0);
   double* V = addr(bt, B_V, i, s, 0, 0);
   const int cap = ld;
   double* d = sh;                       // remaining diagonal [cap]
-  double* beta = sh + cap;              // Householder scalars [cap]
-  double* red = sh + 2 * cap;           // reduction values [RT_THREADS]
-  int* redi = (int*)(sh + 2 * cap + RT_THREADS);
-  int* piv = redi + RT_THREADS;         // pivot order [cap]
-  char* used = (char*)(piv + cap);      // [cap]
+  double* red = sh + cap;               // [RT_THREADS]
+  int* redi = (int*)(red + RT_THREADS); // [RT_THREADS]
+  char* used = (char*)(redi + RT_THREADS);
   if (R <= 0) {
     if (tid == 0) sz.t[s * N + i] = 0;
     return;
@@ -202,8 +221,7 @@ __global__ __launch_bounds__(RT_THREADS) void k_recompress(const int* __restrict
   }
   __syncthreads();
   int t = 0;
-  for (;;) {
-    if (t >= R) break;
+  while (t < R) {
     double bv = -1.0;
     int bi = R;
     for (int a = tid; a < R; a += RT_THREADS)
@@ -216,27 +234,19 @@ __global__ __launch_bounds__(RT_THREADS) void k_recompress(const int* __restrict
     const int p = redi[0];
     __syncthreads();
     if (!(dmax > tau2)) break;
-    const double inv = 1.0 / sqrt(dmax);
-    // column t of L in original coordinates
+    const double sq = sqrt(dmax), inv = 1.0 / sq;
     for (int a = tid; a < R; a += RT_THREADS) {
       double v = 0.0;
-      if (!used[a] && a != p) {
+      if (a == p) v = sq;
+      else if (!used[a]) {
         v = G[a + (int64_t)p * ld];
         for (int l = 0; l < t; ++l) v -= V[a + (int64_t)l * ld] * V[p + (int64_t)l * ld];
         v *= inv;
-      } else if (a == p) {
-        v = sqrt(dmax);
+        d[a] -= v * v;
       }
       V[a + (int64_t)t * ld] = v;
     }
-    __syncthreads();
-    for (int a = tid; a < R; a += RT_THREADS) {
-      if (!used[a] && a != p) {
-        double v = V[a + (int64_t)t * ld];
-        d[a] -= v * v;
-      }
-    }
-    if (tid == 0) { used[p] = 1; piv[t] = p; }
+    if (tid == 0) used[p] = 1;
     __syncthreads();
     ++t;
   }
@@ -244,66 +254,197 @@ __global__ __launch_bounds__(RT_THREADS) void k_recompress(const int* __restrict
     sz.t[s * N + i] = t;
     sz.R[s * N + i] = R - t;
   }
+}
+
+// Blocked Householder QR of L (RT x t, in B_V) with reflector k anchored at row
+// RT-1-k.  Panels of HQR_NB columns are factored column by column; the trailing
+// columns then receive the panel's reflectors at once in compact-WY form,
+// V <- V - Y_p T_p^T (Y_p^T V), on the matrix cores.  On exit B_V holds the
+// reflectors Y (zero below each anchor) and sh-beta is written to beta_out.
+constexpr int HQR_NB = 16;
+
+__global__ __launch_bounds__(RT_THREADS) void k_hqr(const int* __restrict__ clusters, BufTab bt, SizeTab sz) {
+  extern __shared__ double sh[];
+  const int s = blockIdx.z;
+  const int i = clusters[blockIdx.y];
+  const int N = sz.N;
+  const int t = sz.t[s * N + i];
   if (t == 0) return;
-  // Householder QR of V[:, 0:t] (R x t) in place
-  for (int k = 0; k < t; ++k) {
-    double part = 0.0;
-    for (int a = k + tid; a < R; a += RT_THREADS) {
-      double x = V[a + (int64_t)k * ld];
-      part += x * x;
-    }
-    red[tid] = part;
-    __syncthreads();
-    for (int off = RT_THREADS / 2; off > 0; off >>= 1) {
-      if (tid < off) red[tid] += red[tid + off];
-      __syncthreads();
-    }
-    const double xn = sqrt(red[0]);
-    const double x0 = V[k + (int64_t)k * ld];
-    __syncthreads();
-    const double alpha = -copysign(xn, x0 != 0.0 ? x0 : 1.0);
-    // v = x - alpha e_k ; ||v||^2 = xn^2 - 2 alpha x0 + alpha^2
-    const double v0 = x0 - alpha;
-    const double vn = xn * xn - x0 * x0 + v0 * v0;
-    const double bk = vn > 0.0 ? 2.0 / vn : 0.0;
-    if (tid == 0) {
-      V[k + (int64_t)k * ld] = v0;
-      beta[k] = bk;
-    }
-    __syncthreads();
-    // apply to columns k+1..t-1: each thread group handles one column
-    for (int j = k + 1; j < t; ++j) {
-      double pj = 0.0;
-      for (int a = k + tid; a < R; a += RT_THREADS) pj += V[a + (int64_t)k * ld] * V[a + (int64_t)j * ld];
-      red[tid] = pj;
-      __syncthreads();
-      for (int off = RT_THREADS / 2; off > 0; off >>= 1) {
-        if (tid < off) red[tid] += red[tid + off];
-        __syncthreads();
+  const int RT = sz.R[s * N + i] + t;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ld = bt.ld[B_V];
+  double* V = addr(bt, B_V, i, s, 0, 0);
+  double* beta_out = addr(bt, B_G, i, s, 0, 0) + (int64_t)(ld - 1) * ld;   // last column of B_G
+  double* Zs = addr(bt, B_Z, i, s, 0, 0);                                  // HQR_NB x t scratch (ld)
+  double* red = sh;                          // [8]
+  double* wd = sh + 8;                       // [HQR_NB]
+  double* Tp = sh + 8 + HQR_NB;              // [HQR_NB * HQR_NB]
+  double* bp = Tp + HQR_NB * HQR_NB;         // [HQR_NB]
+  for (int k0 = 0; k0 < t; k0 += HQR_NB) {
+    const int nb = min(HQR_NB, t - k0);
+    // ---- panel: columns k0 .. k0+nb-1
+    for (int kk = 0; kk < nb; ++kk) {
+      const int k = k0 + kk;
+      const int p = RT - 1 - k;
+      double part = 0.0;
+      for (int a = tid; a <= p; a += RT_THREADS) {
+        double x = V[a + (int64_t)k * ld];
+        part += x * x;
       }
-      const double f = red[0] * bk;
+      const double xn2 = block_sum(part, red, tid);
+      const double x0 = V[p + (int64_t)k * ld];
+      const double xn = sqrt(xn2);
+      const double alpha = -copysign(xn, x0 != 0.0 ? x0 : 1.0);
+      const double v0 = x0 - alpha;
+      const double vn = xn2 - x0 * x0 + v0 * v0;
+      const double bk = vn > 0.0 ? 2.0 / vn : 0.0;
       __syncthreads();
-      for (int a = k + tid; a < R; a += RT_THREADS) V[a + (int64_t)j * ld] -= V[a + (int64_t)k * ld] * f;
+      if (tid == 0) {
+        V[p + (int64_t)k * ld] = v0;
+        bp[kk] = bk;
+        beta_out[k] = bk;
+      }
+      __syncthreads();
+      for (int j = k + 1 + wave; j < k0 + nb; j += RT_THREADS / 64) {
+        double q = 0.0;
+        for (int a = lane; a <= p; a += 64) q += V[a + (int64_t)k * ld] * V[a + (int64_t)j * ld];
+        q = wave_sum(q);
+        if (lane == 0) wd[j - k0] = q * bk;
+      }
+      __syncthreads();
+      const int nj = k0 + nb - k - 1, nr = p + 1;
+      for (int64_t e = tid; e < (int64_t)nj * nr; e += RT_THREADS) {
+        int a = (int)(e % nr), j = k + 1 + (int)(e / nr);
+        V[a + (int64_t)j * ld] -= V[a + (int64_t)k * ld] * wd[j - k0];
+      }
       __syncthreads();
     }
-  }
-  // W = Q with columns reordered [Q(:, t:R) | Q(:, 0:t)]: start from the permuted
-  // identity, then apply H_{t-1}, ..., H_0 from the left.
-  for (int64_t e = tid; e < (int64_t)R * R; e += RT_THREADS) {
-    int a = (int)(e % R), c = (int)(e / R);
-    int src = c < R - t ? c + t : c - (R - t);   // column of Q stored at position c
-    G[a + (int64_t)c * ld] = (a == src) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int k = t - 1; k >= 0; --k) {
-    const double bk = beta[k];
-    for (int c = tid; c < R; c += RT_THREADS) {
-      double pj = 0.0;
-      for (int a = k; a < R; ++a) pj += V[a + (int64_t)k * ld] * G[a + (int64_t)c * ld];
-      pj *= bk;
-      for (int a = k; a < R; ++a) G[a + (int64_t)c * ld] -= V[a + (int64_t)k * ld] * pj;
+    // zero the panel's reflectors below their anchors (those rows hold R entries)
+    for (int64_t e = tid; e < (int64_t)nb * RT; e += RT_THREADS) {
+      int a = (int)(e % RT), kk = (int)(e / RT);
+      if (a > RT - 1 - (k0 + kk)) V[a + (int64_t)(k0 + kk) * ld] = 0.0;
     }
     __syncthreads();
+    const int nt = t - k0 - nb;
+    if (nt <= 0) continue;
+    // ---- T_p of the panel: T_kk = beta_k, T[0:kk, kk] = -beta_k T[0:kk, 0:kk] (Y_p^T y_kk)
+    for (int e = tid; e < nb * nb; e += RT_THREADS) Tp[e] = 0.0;
+    __syncthreads();
+    for (int kk = 0; kk < nb; ++kk) {
+      const int p = RT - 1 - (k0 + kk);
+      for (int j = wave; j < kk; j += RT_THREADS / 64) {
+        double q = 0.0;
+        for (int a = lane; a <= p; a += 64) q += V[a + (int64_t)(k0 + j) * ld] * V[a + (int64_t)(k0 + kk) * ld];
+        q = wave_sum(q);
+        if (lane == 0) wd[j] = q;
+      }
+      __syncthreads();
+      if (tid < kk) {
+        double v = 0.0;
+        for (int b = tid; b < kk; ++b) v += Tp[tid + b * HQR_NB] * wd[b];
+        Tp[tid + kk * HQR_NB] = -bp[kk] * v;
+      } else if (tid == kk) {
+        Tp[kk + kk * HQR_NB] = bp[kk];
+      }
+      __syncthreads();
+    }
+    // ---- trailing update, columns c in [k0+nb, t):
+    // Z = Y_p^T V_trail (nb x nt) ; Z <- T_p^T Z ; V_trail -= Y_p Z
+    const int rows = RT - k0;   // reflectors of the panel live in rows 0 .. RT-1-k0
+    for (int cc = wave; cc < nt; cc += RT_THREADS / 64) {
+      const int c = k0 + nb + cc;
+      for (int kk = 0; kk < nb; ++kk) {
+        double q = 0.0;
+        for (int a = lane; a < rows; a += 64) q += V[a + (int64_t)(k0 + kk) * ld] * V[a + (int64_t)c * ld];
+        q = wave_sum(q);
+        if (lane == 0) Zs[kk + (int64_t)cc * ld] = q;
+      }
+    }
+    __syncthreads();
+    for (int cc = tid; cc < nt; cc += RT_THREADS) {
+      double z[HQR_NB];
+      for (int kk = 0; kk < nb; ++kk) z[kk] = Zs[kk + (int64_t)cc * ld];
+      for (int kk = 0; kk < nb; ++kk) {
+        double v = 0.0;
+        for (int b = 0; b <= kk; ++b) v += Tp[b + kk * HQR_NB] * z[b];   // (T_p^T z)_kk
+        Zs[kk + (int64_t)cc * ld] = v;
+      }
+    }
+    __syncthreads();
+    // V_trail[a, c] -= sum_kk Y[a, kk] Z[kk, c]: MFMA tiles of 32 x 32 per wave
+    {
+      const int tr = (rows + 31) / 32, tc = (nt + 31) / 32;
+      for (int tile = wave; tile < tr * tc; tile += RT_THREADS / 64) {
+        const int r0 = (tile % tr) * 32, c0 = (tile / tr) * 32;
+        v4d acc[2][2];
+        for (int x = 0; x < 2; ++x)
+          for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int kb = 0; kb < nb; kb += 4) {
+          const int kc = kb + (lane >> 4);
+          double av[2], bv[2];
+          for (int x = 0; x < 2; ++x) {
+            int r = r0 + x * 16 + (lane & 15);
+            av[x] = (kc < nb && r < rows) ? V[r + (int64_t)(k0 + kc) * ld] : 0.0;
+            int c = c0 + x * 16 + (lane & 15);
+            bv[x] = (kc < nb && c < nt) ? Zs[kc + (int64_t)c * ld] : 0.0;
+          }
+          for (int x = 0; x < 2; ++x)
+            for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+        }
+        for (int x = 0; x < 2; ++x)
+          for (int y = 0; y < 2; ++y)
+            for (int v = 0; v < 4; ++v) {
+              int r = r0 + x * 16 + (lane >> 4) + 4 * v;
+              int c = c0 + y * 16 + (lane & 15);
+              if (r < rows && c < nt) V[r + (int64_t)(k0 + nb + c) * ld] -= acc[x][y][v];
+            }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// T (t x t, upper) of W = H_0 ... H_{t-1} = I - Y T Y^T from YtY = Y^T Y (in B_W)
+// and the scalars beta (last column of B_G): T_kk = beta_k,
+// T[0:k, k] = -beta_k T[0:k, 0:k] YtY[0:k, k].  Written to B_G[0:t, 0:t].
+__global__ __launch_bounds__(RT_THREADS) void k_tmat(const int* __restrict__ clusters, BufTab bt, SizeTab sz) {
+  const int s = blockIdx.z;
+  const int i = clusters[blockIdx.y];
+  const int t = sz.t[s * sz.N + i];
+  if (t == 0) return;
+  const int tid = threadIdx.x;
+  const int ld = bt.ld[B_G];
+  double* Tm = addr(bt, B_G, i, s, 0, 0);
+  const double* beta = Tm + (int64_t)(ld - 1) * ld;
+  const double* YtY = addr(bt, B_W, i, s, 0, 0);
+  const int ldy = bt.ld[B_W];
+  for (int k = 0; k < t; ++k) {
+    for (int a = tid; a < t; a += RT_THREADS) {
+      double v = 0.0;
+      if (a < k) {
+        for (int b = a; b < k; ++b) v += Tm[a + (int64_t)b * ld] * YtY[b + (int64_t)k * ldy];
+        v *= -beta[k];
+      } else if (a == k) {
+        v = beta[k];
+      }
+      Tm[a + (int64_t)k * ld] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// W = I on the first RT x RT entries of B_W (clusters with t > 0)
+__global__ void k_eye(const int* __restrict__ clusters, BufTab bt, SizeTab sz) {
+  const int s = blockIdx.z;
+  const int i = clusters[blockIdx.y];
+  const int t = sz.t[s * sz.N + i];
+  if (t == 0) return;
+  const int RT = sz.R[s * sz.N + i] + t;
+  double* W = addr(bt, B_W, i, s, 0, 0);
+  const int ld = bt.ld[B_W];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)RT * RT; e += (int64_t)gridDim.x * blockDim.x) {
+    int a = (int)(e % RT), c = (int)(e / RT);
+    W[a + (int64_t)c * ld] = a == c ? 1.0 : 0.0;
   }
 }
 
@@ -323,8 +464,8 @@ __global__ __launch_bounds__(256) void k_rotate(const RotItem* __restrict__ item
   const int o0 = blockIdx.x * STRIP;
   if (o0 >= other) return;
   const int no = min(STRIP, other - o0);
-  const double* W = addr(bt, B_G, it.cluster, s, 0, 0);
-  const int ldw = bt.ld[B_G];
+  const double* W = addr(bt, B_W, it.cluster, s, 0, 0);
+  const int ldw = bt.ld[B_W];
   double* X = addr(bt, it.buf, it.blk, s, 0, 0);
   const int ldx = bt.ld[it.buf];
   const int tid = threadIdx.x;
@@ -347,14 +488,52 @@ __global__ __launch_bounds__(256) void k_rotate(const RotItem* __restrict__ item
 
 // ------------------------------------------------------- pivot-block LDL^T
 // Bunch-Kaufman (partial pivoting, alpha = (1+sqrt(17))/8) on the redundant
-// block P = S_ii^{RR} (Eq. blr2-diag-ldl), in place, full storage.  With
-// P[perm, perm] = L D L^T and D = J Lambda J^T (2x2 blocks diagonalised by a
+// block P = S_ii^{RR} (Eq. blr2-diag-ldl), in place, full storage, blocked: a
+// panel of up to LDL_NB columns is factored lazily (columns are brought up to
+// date from the panel's L and W = L D columns only when needed), then the
+// trailing matrix receives one rank-(panel) update L W^T on the matrix cores.
+// With P[perm, perm] = L D L^T and D = J Lambda J^T (2x2 blocks diagonalised by a
 // Jacobi rotation), the elimination operator K = Pi L^{-T} J |Lambda|^{-1/2} and
 // the signs sgn(Lambda) let every later step use the scaled generators
 // Y~ = B K (Eq. blr2-diag-elimination) and S -= Y~ diag(sgn) Y~^T
 // (Eq. blr2-diag-schur).  The number of negative entries of Lambda is added to
 // nu (Sylvester's law of inertia).
-constexpr int LDL_THREADS = 256;
+constexpr int LDL_THREADS = 512;
+constexpr int LDL_NB = 32;
+
+__device__ inline double block_max512(double v, double* red, int tid) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int w = 1; w < LDL_THREADS / 64; ++w) r = fmax(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
+// argmax of |x[a]| over a in [lo, R), first index on ties; returns value, index in *idx
+__device__ inline double block_argmax512(const double* x, int lo, int R, double* red, int* redi, int tid, int* idx) {
+  double bv = -1.0;
+  int bi = R;
+  for (int a = lo + tid; a < R; a += LDL_THREADS) {
+    double v = fabs(x[a]);
+    if (v > bv) { bv = v; bi = a; }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    double ov = __shfl_xor(bv, off, 64);
+    int oi = __shfl_xor(bi, off, 64);
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+  }
+  if ((tid & 63) == 0) { red[tid >> 6] = bv; redi[tid >> 6] = bi; }
+  __syncthreads();
+  double r = red[0];
+  int ri = redi[0];
+  for (int w = 1; w < LDL_THREADS / 64; ++w)
+    if (red[w] > r || (red[w] == r && redi[w] < ri)) { r = red[w]; ri = redi[w]; }
+  __syncthreads();
+  *idx = ri;
+  return r;
+}
 
 __global__ __launch_bounds__(LDL_THREADS) void k_ldl(const int* __restrict__ clusters, const int* __restrict__ diag_blk,
                                                      BufTab bt, SizeTab sz, unsigned long long* __restrict__ nu,
@@ -364,164 +543,191 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl(const int* __restrict__ clu
   const int i = clusters[blockIdx.y];
   const int N = sz.N;
   const int R = sz.R[s * N + i];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (R <= 0) return;
   const int ld = bt.ld[B_S];
   double* A = addr(bt, B_S, diag_blk[i], s, 0, 0);
   double* K = addr(bt, B_G, i, s, 0, 0);
-  double* Li = addr(bt, B_V, i, s, 0, 0);
+  double* Y = addr(bt, B_V, i, s, 0, 0);      // L^{-T} after the factorization
+  double* Wp = addr(bt, B_Z, i, s, 0, 0);     // panel workspace W = L D, ld, LDL_NB + 2 columns
   double* sg = addr(bt, B_SIGN, 0, s, 0, 0) + (int64_t)i * bt.bs[B_SIGN];
   const int cap = ld;
-  double* l1 = sh;                 // [cap]
-  double* l2 = sh + cap;           // [cap]
-  double* c1 = sh + 2 * cap;       // [cap]
-  double* c2 = sh + 3 * cap;       // [cap]
-  double* red = sh + 4 * cap;      // [LDL_THREADS]
-  int* redi = (int*)(red + LDL_THREADS);
-  int* perm = redi + LDL_THREADS;  // [cap]
-  int* psz = perm + cap;           // [cap] 1, 2 (first of a 2x2), 0 (second)
+  double* red = sh;                       // [16]
+  int* redi = (int*)(sh + 16);            // [16]
+  double* rowc = sh + 32;                 // [cap] row cache / coefficients
+  double* cf1 = rowc + cap;               // [cap]
+  double* cf2 = cf1 + cap;                // [cap]
+  int* perm = (int*)(cf2 + cap);          // [cap]
+  int* psz = perm + cap;                  // [cap] 1, 2 (first of a 2x2), 0 (second)
   __shared__ int s_bad;
   const double alpha = (1.0 + sqrt(17.0)) / 8.0;
+  const int NB = min(LDL_NB, cap - 2);    // the workspace holds NB + 2 columns
   for (int a = tid; a < R; a += LDL_THREADS) perm[a] = a;
   if (tid == 0) s_bad = 0;
   __syncthreads();
+
   int k = 0;
   while (k < R) {
-    // column max below the diagonal
-    double bv = -1.0;
-    int bi = R;
-    for (int a = k + 1 + tid; a < R; a += LDL_THREADS) {
-      double v = fabs(A[a + (int64_t)k * ld]);
-      if (v > bv) { bv = v; bi = a; }
-    }
-    red[tid] = bv;
-    redi[tid] = bi;
-    __syncthreads();
-    argmax_reduce(red, redi, tid, LDL_THREADS);
-    const double colmax = red[0] < 0.0 ? 0.0 : red[0];
-    const int imax = redi[0];
-    __syncthreads();
-    const double absakk = fabs(A[k + (int64_t)k * ld]);
-    int kind = 1, kp = k;
-    if (fmax(absakk, colmax) == 0.0 || !(absakk == absakk)) {
-      kind = 1; kp = k;
-      if (tid == 0) s_bad = 1;
-    } else if (absakk >= alpha * colmax) {
-      kind = 1; kp = k;
-    } else {
-      double rv = 0.0;
-      for (int j = k + tid; j < R; j += LDL_THREADS)
-        if (j != imax) rv = fmax(rv, fabs(A[imax + (int64_t)j * ld]));
-      red[tid] = rv;
+    const int k0 = k;
+    int jw = 0;   // panel columns done
+    while (jw < NB && k < R) {
+      // w = column k of the up-to-date matrix, rows k..R-1 -> Wp[:, jw]
+      double* w = Wp + (int64_t)jw * ld;
+      double* u = Wp + (int64_t)(jw + 1) * ld;
+      for (int a = k + tid; a < R; a += LDL_THREADS) {
+        double v = A[a + (int64_t)k * ld];
+        for (int c = 0; c < jw; ++c) v -= A[a + (int64_t)(k0 + c) * ld] * Wp[k + (int64_t)c * ld];
+        w[a] = v;
+      }
       __syncthreads();
-      for (int off = LDL_THREADS / 2; off > 0; off >>= 1) {
-        if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
+      int imax = R;
+      const double colmax0 = block_argmax512(w, k + 1, R, red, redi, tid, &imax);
+      const double colmax = colmax0 < 0.0 ? 0.0 : colmax0;
+      const double absakk = fabs(w[k]);
+      int kind = 1, kp = k;
+      bool use_u = false;
+      if (fmax(absakk, colmax) == 0.0 || !(absakk == absakk)) {
+        if (tid == 0) s_bad = 1;
+      } else if (absakk < alpha * colmax) {
+        // u = column imax of the up-to-date matrix, rows k..R-1
+        for (int a = k + tid; a < R; a += LDL_THREADS) {
+          double v = A[a + (int64_t)imax * ld];
+          for (int c = 0; c < jw; ++c) v -= A[a + (int64_t)(k0 + c) * ld] * Wp[imax + (int64_t)c * ld];
+          u[a] = v;
+        }
+        __syncthreads();
+        double rv = 0.0;
+        for (int a = k + tid; a < R; a += LDL_THREADS)
+          if (a != imax) rv = fmax(rv, fabs(u[a]));
+        const double rowmax = block_max512(rv, red, tid);
+        if (absakk >= alpha * colmax * (colmax / rowmax)) {
+          kind = 1; kp = k;
+        } else if (fabs(u[imax]) >= alpha * rowmax) {
+          kind = 1; kp = imax; use_u = true;
+        } else {
+          kind = 2; kp = imax;
+        }
+      }
+      const int kk = (kind == 2) ? k + 1 : k;
+      if (use_u) {
+        for (int a = k + tid; a < R; a += LDL_THREADS) w[a] = u[a];
         __syncthreads();
       }
-      const double rowmax = red[0];
-      __syncthreads();
-      if (absakk >= alpha * colmax * (colmax / rowmax)) {
-        kind = 1; kp = k;
-      } else if (fabs(A[imax + (int64_t)imax * ld]) >= alpha * rowmax) {
-        kind = 1; kp = imax;
+      if (kp != kk) {
+        // symmetric interchange kk <-> kp: full rows and columns of A, rows of Wp
+        for (int j = tid; j < R; j += LDL_THREADS) {
+          double x = A[kk + (int64_t)j * ld];
+          A[kk + (int64_t)j * ld] = A[kp + (int64_t)j * ld];
+          A[kp + (int64_t)j * ld] = x;
+        }
+        for (int c = tid; c < jw + 2; c += LDL_THREADS) {
+          double x = Wp[kk + (int64_t)c * ld];
+          Wp[kk + (int64_t)c * ld] = Wp[kp + (int64_t)c * ld];
+          Wp[kp + (int64_t)c * ld] = x;
+        }
+        __syncthreads();
+        for (int a = tid; a < R; a += LDL_THREADS) {
+          double x = A[a + (int64_t)kk * ld];
+          A[a + (int64_t)kk * ld] = A[a + (int64_t)kp * ld];
+          A[a + (int64_t)kp * ld] = x;
+        }
+        if (tid == 0) {
+          int x = perm[kk];
+          perm[kk] = perm[kp];
+          perm[kp] = x;
+        }
+        __syncthreads();
+      }
+      if (kind == 1) {
+        const double dk = w[k];
+        const double inv = dk != 0.0 ? 1.0 / dk : 0.0;
+        for (int a = k + 1 + tid; a < R; a += LDL_THREADS) A[a + (int64_t)k * ld] = w[a] * inv;
+        if (tid == 0) {
+          A[k + (int64_t)k * ld] = dk;
+          psz[k] = 1;
+        }
+        __syncthreads();
+        k += 1;
+        jw += 1;
       } else {
-        kind = 2; kp = imax;
+        // pivot columns (k, k+1) = (w, u) after the interchange; u is column k+1
+        const double a11 = w[k], a21 = w[k + 1], a22 = u[k + 1];
+        const double det = a11 * a22 - a21 * a21;
+        if (tid == 0 && !(det != 0.0 && det == det)) s_bad = 1;
+        const double idet = det != 0.0 ? 1.0 / det : 0.0;
+        for (int a = k + 2 + tid; a < R; a += LDL_THREADS) {
+          double x1 = w[a], x2 = u[a];
+          A[a + (int64_t)k * ld] = (x1 * a22 - x2 * a21) * idet;
+          A[a + (int64_t)(k + 1) * ld] = (x2 * a11 - x1 * a21) * idet;
+        }
+        if (tid == 0) {
+          A[k + (int64_t)k * ld] = a11;
+          A[k + 1 + (int64_t)k * ld] = a21;
+          A[k + 1 + (int64_t)(k + 1) * ld] = a22;
+          psz[k] = 2;
+          psz[k + 1] = 0;
+        }
+        __syncthreads();
+        k += 2;
+        jw += 2;
       }
     }
-    const int kk = (kind == 2) ? k + 1 : k;   // position receiving the pivot row
-    __syncthreads();                          // every thread has read the pivot data
-    if (kp != kk) {
-      // symmetric swap kk <-> kp: full rows then full columns
-      for (int j = tid; j < R; j += LDL_THREADS) {
-        double x = A[kk + (int64_t)j * ld];
-        A[kk + (int64_t)j * ld] = A[kp + (int64_t)j * ld];
-        A[kp + (int64_t)j * ld] = x;
+    // trailing update A[k:R, k:R] -= Lp W^T, Lp = A[:, k0:k0+jw], W = Wp[:, 0:jw]
+    const int n2 = R - k;
+    if (n2 > 0) {
+      const int nt = (n2 + 31) / 32;
+      for (int tile = wave; tile < nt * nt; tile += LDL_THREADS / 64) {
+        const int r0 = k + (tile % nt) * 32, c0 = k + (tile / nt) * 32;
+        v4d acc[2][2];
+        for (int x = 0; x < 2; ++x)
+          for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int kb = 0; kb < jw; kb += 4) {
+          const int kc = kb + (lane >> 4);
+          double av[2], bv[2];
+          for (int x = 0; x < 2; ++x) {
+            int r = r0 + x * 16 + (lane & 15);
+            av[x] = (kc < jw && r < R) ? A[r + (int64_t)(k0 + kc) * ld] : 0.0;
+            int c = c0 + x * 16 + (lane & 15);
+            bv[x] = (kc < jw && c < R) ? Wp[c + (int64_t)kc * ld] : 0.0;
+          }
+          for (int x = 0; x < 2; ++x)
+            for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+        }
+        for (int x = 0; x < 2; ++x)
+          for (int y = 0; y < 2; ++y)
+            for (int v = 0; v < 4; ++v) {
+              int r = r0 + x * 16 + (lane >> 4) + 4 * v;
+              int c = c0 + y * 16 + (lane & 15);
+              if (r < R && c < R) A[r + (int64_t)c * ld] -= acc[x][y][v];
+            }
       }
       __syncthreads();
-      for (int a = tid; a < R; a += LDL_THREADS) {
-        double x = A[a + (int64_t)kk * ld];
-        A[a + (int64_t)kk * ld] = A[a + (int64_t)kp * ld];
-        A[a + (int64_t)kp * ld] = x;
-      }
-      if (tid == 0) {
-        int x = perm[kk];
-        perm[kk] = perm[kp];
-        perm[kp] = x;
-      }
-      __syncthreads();
-    }
-    if (kind == 1) {
-      const double dk = A[k + (int64_t)k * ld];
-      const double inv = dk != 0.0 ? 1.0 / dk : 0.0;
-      for (int a = k + 1 + tid; a < R; a += LDL_THREADS) {
-        c1[a] = A[a + (int64_t)k * ld];
-        l1[a] = c1[a] * inv;
-      }
-      if (tid == 0) psz[k] = 1;
-      __syncthreads();
-      const int nt = R - k - 1;
-      for (int64_t e = tid; e < (int64_t)nt * nt; e += LDL_THREADS) {
-        int a = k + 1 + (int)(e % nt), b = k + 1 + (int)(e / nt);
-        A[a + (int64_t)b * ld] -= l1[a] * c1[b];
-      }
-      __syncthreads();
-      for (int a = k + 1 + tid; a < R; a += LDL_THREADS) A[a + (int64_t)k * ld] = l1[a];
-      __syncthreads();
-      k += 1;
-    } else {
-      const double a11 = A[k + (int64_t)k * ld], a21 = A[k + 1 + (int64_t)k * ld], a22 = A[k + 1 + (int64_t)(k + 1) * ld];
-      const double det = a11 * a22 - a21 * a21;
-      if (tid == 0 && !(det != 0.0 && det == det)) s_bad = 1;
-      const double idet = det != 0.0 ? 1.0 / det : 0.0;
-      for (int a = k + 2 + tid; a < R; a += LDL_THREADS) {
-        double x1 = A[a + (int64_t)k * ld], x2 = A[a + (int64_t)(k + 1) * ld];
-        c1[a] = x1;
-        c2[a] = x2;
-        l1[a] = (x1 * a22 - x2 * a21) * idet;
-        l2[a] = (x2 * a11 - x1 * a21) * idet;
-      }
-      if (tid == 0) { psz[k] = 2; psz[k + 1] = 0; }
-      __syncthreads();
-      const int nt = R - k - 2;
-      for (int64_t e = tid; e < (int64_t)nt * nt; e += LDL_THREADS) {
-        int a = k + 2 + (int)(e % nt), b = k + 2 + (int)(e / nt);
-        A[a + (int64_t)b * ld] -= l1[a] * c1[b] + l2[a] * c2[b];
-      }
-      __syncthreads();
-      for (int a = k + 2 + tid; a < R; a += LDL_THREADS) {
-        A[a + (int64_t)k * ld] = l1[a];
-        A[a + (int64_t)(k + 1) * ld] = l2[a];
-      }
-      __syncthreads();
-      k += 2;
     }
   }
-  // unit lower inverse: column j of L^{-1} by forward substitution (L_{k+1,k} = 0
-  // inside a 2x2 pivot block, where A holds D's off-diagonal entry)
-  for (int j = tid; j < R; j += LDL_THREADS) {
-    for (int a = 0; a < j; ++a) Li[a + (int64_t)j * ld] = 0.0;
-    Li[j + (int64_t)j * ld] = 1.0;
-    for (int a = j + 1; a < R; ++a) {
-      double acc = 0.0;
-      for (int b = j; b < a; ++b) {
-        double lab = (psz[b] == 2 && a == b + 1) ? 0.0 : A[a + (int64_t)b * ld];
-        acc -= lab * Li[b + (int64_t)j * ld];
-      }
-      Li[a + (int64_t)j * ld] = acc;
+
+  // Y = L^{-T}: row a of X = L^{-1} from rows b < a (forward substitution over rows),
+  // stored transposed, Y[j + a*ld] = X[a][j]; L_{k+1,k} = 0 inside a 2x2 block.
+  for (int a = 0; a < R; ++a) {
+    for (int b = tid; b < a; b += LDL_THREADS)
+      rowc[b] = (psz[b] == 2 && a == b + 1) ? 0.0 : A[a + (int64_t)b * ld];
+    __syncthreads();
+    for (int j = tid; j <= a; j += LDL_THREADS) {
+      double v = (j == a) ? 1.0 : 0.0;
+      for (int b = j; b < a; ++b) v -= rowc[b] * Y[j + (int64_t)b * ld];
+      Y[j + (int64_t)a * ld] = v;
     }
+    __syncthreads();
   }
-  __syncthreads();
-  // K[perm[a], b] = (L^{-T} J |Lambda|^{-1/2})[a, b],  (L^{-T})[a, b] = Li[b, a]
+  // per column: K[:, b] = Y[:, c] cf1[b] + Y[:, c'] cf2[b] (J |Lambda|^{-1/2} mixing)
   int neg = 0;
   for (int b = tid; b < R; b += LDL_THREADS) {
-    if (psz[b] == 0) continue;
     if (psz[b] == 1) {
       const double dk = A[b + (int64_t)b * ld];
-      const double sc = (dk != 0.0 && dk == dk) ? 1.0 / sqrt(fabs(dk)) : 0.0;
+      cf1[b] = (dk != 0.0 && dk == dk) ? 1.0 / sqrt(fabs(dk)) : 0.0;
+      cf2[b] = 0.0;
       sg[b] = dk < 0.0 ? -1.0 : 1.0;
       neg += dk < 0.0 ? 1 : 0;
-      for (int a = 0; a < R; ++a) K[perm[a] + (int64_t)b * ld] = Li[b + (int64_t)a * ld] * sc;
-    } else {
+    } else if (psz[b] == 2) {
       const double a11 = A[b + (int64_t)b * ld], a21 = A[b + 1 + (int64_t)b * ld], a22 = A[b + 1 + (int64_t)(b + 1) * ld];
       double cs = 1.0, sn = 0.0;
       if (a21 != 0.0) {
@@ -535,24 +741,34 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl(const int* __restrict__ clu
       const double lam2 = sn * sn * a11 + 2.0 * cs * sn * a21 + cs * cs * a22;
       const double s1 = (lam1 != 0.0 && lam1 == lam1) ? 1.0 / sqrt(fabs(lam1)) : 0.0;
       const double s2 = (lam2 != 0.0 && lam2 == lam2) ? 1.0 / sqrt(fabs(lam2)) : 0.0;
+      cf1[b] = cs * s1;          // column b   = cs*s1*Y[:, b] - sn*s1*Y[:, b+1]
+      cf2[b] = -sn * s1;
+      cf1[b + 1] = sn * s2;      // column b+1 = sn*s2*Y[:, b] + cs*s2*Y[:, b+1]
+      cf2[b + 1] = cs * s2;
       sg[b] = lam1 < 0.0 ? -1.0 : 1.0;
       sg[b + 1] = lam2 < 0.0 ? -1.0 : 1.0;
       neg += (lam1 < 0.0 ? 1 : 0) + (lam2 < 0.0 ? 1 : 0);
-      for (int a = 0; a < R; ++a) {
-        double x1 = Li[b + (int64_t)a * ld], x2 = Li[b + 1 + (int64_t)a * ld];
-        K[perm[a] + (int64_t)b * ld] = (x1 * cs - x2 * sn) * s1;
-        K[perm[a] + (int64_t)(b + 1) * ld] = (x1 * sn + x2 * cs) * s2;
-      }
     }
   }
-  red[tid] = (double)neg;
   __syncthreads();
-  for (int off = LDL_THREADS / 2; off > 0; off >>= 1) {
-    if (tid < off) red[tid] += red[tid + off];
-    __syncthreads();
+  for (int64_t e = tid; e < (int64_t)R * R; e += LDL_THREADS) {
+    const int a = (int)(e % R), b = (int)(e / R);
+    int c1i, c2i;
+    if (psz[b] == 0) { c1i = b - 1; c2i = b; }
+    else if (psz[b] == 2) { c1i = b; c2i = b + 1; }
+    else { c1i = b; c2i = -1; }
+    double v = (a <= c1i) ? Y[a + (int64_t)c1i * ld] * cf1[b] : 0.0;
+    if (c2i >= 0 && a <= c2i) v += Y[a + (int64_t)c2i * ld] * cf2[b];
+    K[perm[a] + (int64_t)b * ld] = v;
   }
+  double nv = (double)neg;
+  for (int off = 32; off > 0; off >>= 1) nv += __shfl_xor(nv, off, 64);
+  if (lane == 0) red[wave] = nv;
+  __syncthreads();
   if (tid == 0) {
-    atomicAdd(nu + s, (unsigned long long)(red[0] + 0.5));
+    double tot = 0.0;
+    for (int w2 = 0; w2 < LDL_THREADS / 64; ++w2) tot += red[w2];
+    atomicAdd(nu + s, (unsigned long long)(tot + 0.5));
     if (s_bad) atomicOr(status + s, 1);
   }
 }
@@ -781,12 +997,28 @@ void launch_matsum(const SumItem* items, int nitems, const int* src, const BufTa
   }
 }
 
-void launch_recompress(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, double tau2, int* status,
-                       int cap, int nshift, hipStream_t st) {
+void launch_pchol(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, double tau2, int cap, int nshift,
+                  hipStream_t st) {
   if (n <= 0) return;
-  size_t shmem = (size_t)2 * cap * sizeof(double) + RT_THREADS * sizeof(double) + RT_THREADS * sizeof(int) +
-                 (size_t)cap * sizeof(int) + cap + 16;
-  hipLaunchKernelGGL(k_recompress, dim3(1, n, nshift), dim3(RT_THREADS), shmem, st, clusters, bt, sz, tau2, status);
+  size_t shmem = (size_t)cap * sizeof(double) + RT_THREADS * (sizeof(double) + sizeof(int)) + cap + 16;
+  hipLaunchKernelGGL(k_pchol, dim3(1, n, nshift), dim3(RT_THREADS), shmem, st, clusters, bt, sz, tau2);
+}
+
+void launch_hqr(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st) {
+  if (n <= 0) return;
+  size_t shmem = (size_t)(8 + HQR_NB + HQR_NB * HQR_NB + HQR_NB) * sizeof(double);
+  hipLaunchKernelGGL(k_hqr, dim3(1, n, nshift), dim3(RT_THREADS), shmem, st, clusters, bt, sz);
+}
+
+void launch_tmat(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_tmat, dim3(1, n, nshift), dim3(RT_THREADS), 0, st, clusters, bt, sz);
+}
+
+void launch_eye(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_eye, dim3(std::max(1u, cdiv((int64_t)cap * cap, 256 * 8)), n, nshift), dim3(256), 0, st, clusters,
+                     bt, sz);
 }
 
 void launch_rotate(const RotItem* items, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st) {
@@ -802,7 +1034,7 @@ void launch_rotate(const RotItem* items, int n, const BufTab& bt, const SizeTab&
 void launch_ldl(const int* clusters, int n, const int* diag_blk, const BufTab& bt, const SizeTab& sz,
                 unsigned long long* nu, int* status, int cap, int nshift, hipStream_t st) {
   if (n <= 0) return;
-  size_t shmem = (size_t)4 * cap * sizeof(double) + LDL_THREADS * (sizeof(double) + sizeof(int)) + (size_t)2 * cap * sizeof(int);
+  size_t shmem = 32 * sizeof(double) + (size_t)3 * cap * sizeof(double) + (size_t)2 * cap * sizeof(int);
   hipLaunchKernelGGL(k_ldl, dim3(1, n, nshift), dim3(LDL_THREADS), shmem, st, clusters, diag_blk, bt, sz, nu, status);
 }
 

@@ -14,8 +14,11 @@ void launch_gemm(int kind, const GItem* items, int nitems, const GTerm* terms, c
                  int mcap, int ncap, int nshift, hipStream_t st);
 void launch_matsum(const SumItem* items, int nitems, const int* src, const BufTab& bt, const SizeTab& sz, int cap,
                    int nshift, hipStream_t st);
-void launch_recompress(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, double tau2, int* status,
-                       int cap, int nshift, hipStream_t st);
+void launch_pchol(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, double tau2, int cap, int nshift,
+                  hipStream_t st);
+void launch_hqr(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
+void launch_tmat(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st);
+void launch_eye(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
 void launch_rotate(const RotItem* items, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
 void launch_ldl(const int* clusters, int n, const int* diag_blk, const BufTab& bt, const SizeTab& sz,
                 unsigned long long* nu, int* status, int cap, int nshift, hipStream_t st);

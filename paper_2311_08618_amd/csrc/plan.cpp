@@ -100,6 +100,14 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
       auto row0 = [&](int k) { return done(k) ? dx(DK_R, k) : dconst(0); };
       auto nrows = [&](int k) { return done(k) ? dx(DK_S, k) : dx(DK_M, k); };
       for (int i : cp.clusters) {
+        cp.rec_yty.add(item(ref(B_W, i), noref(), dx(DK_T, i), dx(DK_T, i), 1.0, 0.0),
+                       {term(ref(B_V, i), ref(B_V, i), dx(DK_RT, i))});
+        cp.rec_u.add(item(ref(B_Z, i), noref(), dx(DK_RT, i), dx(DK_T, i), 1.0, 0.0),
+                      {term(ref(B_V, i), ref(B_G, i), dx(DK_T, i))});
+        cp.rec_w.add(item(ref(B_W, i), noref(), dx(DK_RT, i), dx(DK_RT, i), -1.0, 1.0),
+                      {term(ref(B_Z, i), ref(B_V, i), dx(DK_T, i))});
+      }
+      for (int i : cp.clusters) {
         for (int k : T.near[l][i]) {
           RotItem r;
           r.buf = B_S; r.blk = lp.blk(i, k); r.cluster = i; r.side = 0; r.other = dx(DK_M, k);
@@ -208,8 +216,18 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
     }
     int h = 0;
     auto add_out = [&](int p, int q, bool is_near) {
+      if (h % MERGE_CHUNK == 0) {
+        MergeChunk ch;
+        ch.g0 = (int)mp.gather.size();
+        ch.f0 = (int)mp.fill.items.size();
+        ch.a0 = (int)mp.tr1.items.size();
+        ch.b0 = (int)mp.tr2.items.size();
+        ch.g1 = ch.f1 = ch.a1 = ch.b1 = 0;
+        mp.chunks.push_back(ch);
+      }
+      const int slot = h % MERGE_CHUNK;
       GatherItem g;
-      g.out_blk = h;
+      g.out_blk = slot;
       g.p = p;
       g.q = q;
       for (int a = 0; a < 2; ++a)
@@ -232,16 +250,21 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
               for (int i : cn)
                 ts.push_back(term(ref(B_S, lp.blk(c, i), dx(DK_R, c), 0), ref(B_S, lp.blk(d, i), dx(DK_R, d), 0),
                                   dx(DK_R, i), B_SIGN, i));
-              mp.fill.add(item(ref(B_HAT, h, offc, offd), noref(), dx(DK_S, c), dx(DK_S, d), -1.0, 1.0), ts);
+              mp.fill.add(item(ref(B_HAT, slot, offc, offd), noref(), dx(DK_S, c), dx(DK_S, d), -1.0, 1.0), ts);
             }
           }
         }
       mp.gather.push_back(g);
-      mp.tr1.add(item(ref(B_TMP, h), noref(), dx(DK_PM, p), dx(DK_PM, q), 1.0, 0.0),
-                 {term(ref(B_PMAT, p), ref(B_HAT, h), dx(DK_PM, p))});
+      mp.tr1.add(item(ref(B_TMP, slot), noref(), dx(DK_PM, p), dx(DK_PM, q), 1.0, 0.0),
+                 {term(ref(B_PMAT, p), ref(B_HAT, slot), dx(DK_PM, p))});
       Ref out = is_near ? ref(B_SN, pp.blk(p, q)) : ref(B_FN, pp.fblk(p, q));
       mp.tr2.add(item(out, noref(), dx(DK_PM, p), dx(DK_PM, q), 1.0, 0.0),
-                 {term(ref(B_TMP, h), ref(B_PMAT, q), dx(DK_PM, q))});
+                 {term(ref(B_TMP, slot), ref(B_PMAT, q), dx(DK_PM, q))});
+      MergeChunk& ch = mp.chunks.back();
+      ch.g1 = (int)mp.gather.size();
+      ch.f1 = (int)mp.fill.items.size();
+      ch.a1 = (int)mp.tr1.items.size();
+      ch.b1 = (int)mp.tr2.items.size();
       ++h;
     };
     for (int p = 0; p < Np; ++p) {

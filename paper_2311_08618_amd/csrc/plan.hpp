@@ -28,6 +28,9 @@ struct SumList {
 
 struct ColourPlan {
   std::vector<int> clusters;
+  GList rec_yty;               // TN: Y^T Y (into B_W, before W exists)
+  GList rec_u;                 // NN: U = Y T
+  GList rec_w;                 // NT: W = I - U Y^T
   std::vector<RotItem> rot_rows, rot_cols;
   std::vector<TrsmItem> trsm;
   GList schur;                 // NT, alpha -1
@@ -38,9 +41,18 @@ struct ColourPlan {
   int nslot_m = 0, nslot_p = 0;
 };
 
+// Merge outputs are processed in chunks of MERGE_CHUNK parent blocks, which
+// share the B_HAT / B_TMP slots (slot = output index % MERGE_CHUNK).
+constexpr int MERGE_CHUNK = 512;
+
+struct MergeChunk {
+  int g0, g1, f0, f1, a0, a1, b0, b1;   // item ranges in gather, fill, tr1, tr2
+};
+
 struct MergePlan {
   int Np = 0;
   int nhat = 0;
+  std::vector<MergeChunk> chunks;
   std::vector<GatherItem> gather;
   GList fill;                  // NT into B_HAT
   GList tr1;                   // TN: TMP = P_p^T HAT

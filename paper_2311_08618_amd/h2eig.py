@@ -30,7 +30,8 @@ class _Kernel(C.Structure):
 
 
 class _Opts(C.Structure):
-    _fields_ = [("sample_cap", C.c_int32), ("max_shifts", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("sample_cap", C.c_int32), ("sample_cap_anc", C.c_int32), ("max_shifts", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class _Stats(C.Structure):
@@ -87,12 +88,13 @@ class H2Matrix:
     """A built H^2 matrix resident on the GPU (h2_build)."""
 
     def __init__(self, points, kind: int, diag: float, leaf: int, eta: float, eps: float,
-                 p0: float = 0.0, p1: float = 0.0, sample_cap: int = 0, max_shifts: int = 0):
+                 p0: float = 0.0, p1: float = 0.0, sample_cap: int = 0, sample_cap_anc: int = 0,
+                 max_shifts: int = 0):
         X = np.ascontiguousarray(points, dtype=np.float64)
         if X.ndim == 1:
             X = X.reshape(-1, 1)
         n, dim = X.shape
-        opts = _Opts(int(sample_cap), int(max_shifts), (C.c_int32 * 6)())
+        opts = _Opts(int(sample_cap), int(sample_cap_anc), int(max_shifts), (C.c_int32 * 5)())
         h = C.c_void_p()
         _check(_lib.h2_build(_dptr(X), n, dim, _Kernel(int(kind), float(diag), float(p0), float(p1)), int(leaf),
                              float(eta), float(eps), C.byref(opts), C.byref(h)))
