@@ -151,6 +151,20 @@ h2_status h2_set_stream(h2_matrix A, void* hip_stream);
  * (n int64, host output). */
 h2_status h2_tree_perm(h2_matrix A, int64_t* perm);
 
+/*
+ * Diagnostic profiling (not needed for results).  When enabled, every kernel
+ * launch of h2_inertia is bracketed by HIP events on the handle's stream, and
+ * each kernel class accumulates its algorithmic flops (the method's own
+ * operation counts from the actual per-shift ranks, e.g. 2*M*N*K per block
+ * product, R^3/3 + R^3/3 per pivot LDL and its inverse) in device counters.
+ * Enabling resets the totals.  Classes are numbered 0 .. h2_profile_classes()-1.
+ */
+h2_status h2_profile_enable(h2_matrix A, int32_t enable);
+int32_t h2_profile_classes(void);
+const char* h2_profile_class_name(int32_t cls);
+/* launches: events pairs recorded; ms: summed event time; flops: algorithmic flops */
+h2_status h2_profile_read(h2_matrix A, int32_t cls, int64_t* launches, double* ms, double* flops);
+
 void h2_free(h2_matrix A);
 
 const char* h2_last_error(void);

@@ -51,6 +51,7 @@ enum BufId : int {
   B_BRES,     // resident leaf near blocks (shift independent)
   B_CPL,      // resident couplings of the current level
   B_EMAT,     // resident transfer matrices of the parent level
+  B_RS,       // per launch scratch for out-of-place products (slot = item index in the launch)
   NBUF
 };
 
@@ -59,6 +60,7 @@ struct BufTab {
   int64_t ss[NBUF];  // shift stride (elements)
   int64_t bs[NBUF];  // block stride (elements)
   int ld[NBUF];      // leading dimension
+  unsigned long long* fc;  // algorithmic flop counter of the launch's kernel class (or null)
 };
 
 struct SizeTab {
@@ -104,10 +106,18 @@ struct GTerm {
 // One output block: C = beta*C + alpha * sum_t op(A_t) diag(w_t) op(B_t)
 // optional C2 = beta*C2 + alpha*(...)^T (the transposed twin of a symmetric pair)
 struct GItem {
-  Ref c, c2;        // c2.buf = -1 when absent
+  Ref c, c2;        // c2.buf = -1 when absent; c.blk = -1: scratch slot of the item
   int M, N;         // size expressions
   int t0, nt;       // term range
   double alpha, beta;
+  int guard;        // size expression; the item is skipped when it evaluates to 0 (-1: none)
+};
+
+// Copy of a scratch slot back into a block: X[r0 + a][c0 + b] = RS[slot][a][b]
+struct CopyItem {
+  Ref x;
+  int M, N;
+  int guard;
 };
 
 // Matrix sum: C[M x N] = sum_t A_t[M x N] (all at origin)

@@ -103,8 +103,8 @@ struct DevColour {
   size_t clusters = 0;
   int ncl = 0;
   DevList rec_yty, rec_u, rec_w;
-  size_t rot_rows = 0, rot_cols = 0, trsm = 0;
-  int nrr = 0, nrc = 0, ntr = 0;
+  DevList rot_rows, rot_cols, trsm;
+  size_t rr_copy = 0, rc_copy = 0, tr_copy = 0;
   DevList schur, gm, gt, gg;
   size_t gp_items = 0, gp_src = 0;
   int ngp = 0;
@@ -115,6 +115,62 @@ struct DevLevel {
   size_t diag_blk = 0, r0 = 0, pr0 = 0, edim = 0, gather = 0;
   int ngather = 0;
   DevList gram_init, fill, tr1, tr2;
+};
+
+// Kernel classes of the level engine, for the diagnostic profiler.
+enum ProfClass {
+  PC_INIT = 0, PC_PCHOL, PC_HQR, PC_TMAT, PC_WFORM, PC_ROTATE, PC_LDL, PC_ELIM, PC_COPY, PC_SCHUR, PC_GRAM, PC_MERGE,
+  PC_N
+};
+const char* const kProfNames[PC_N] = {"init", "recompress_pchol", "recompress_hqr", "recompress_t", "recompress_w",
+                                      "rotate", "pivot_ldl", "elimination", "copyback", "schur", "fillin_gram",
+                                      "merge"};
+
+// Brackets kernel launches with HIP events on the handle's stream and keeps a
+// device array of per-class algorithmic flop counters.
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> recs;
+  double ms[PC_N] = {0};
+  long long launches[PC_N] = {0};
+  unsigned long long flops[PC_N] = {0};
+  unsigned long long* d_fc = nullptr;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void reset() {
+    for (int c = 0; c < PC_N; ++c) { ms[c] = 0; launches[c] = 0; flops[c] = 0; }
+  }
+  // after the stream is synchronized: fold the recorded pairs into the totals
+  void collect() {
+    for (auto& r : recs) {
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, r.second.first, r.second.second));
+      ms[r.first] += t;
+      launches[r.first] += 1;
+    }
+    recs.clear();
+    used = 0;
+    if (d_fc) {
+      unsigned long long h[PC_N];
+      HIPCHK(hipMemcpy(h, d_fc, sizeof(h), hipMemcpyDeviceToHost));
+      for (int c = 0; c < PC_N; ++c) flops[c] += h[c];
+      HIPCHK(hipMemset(d_fc, 0, sizeof(h)));
+    }
+  }
+  void release() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+    if (d_fc) (void)hipFree(d_fc);
+    d_fc = nullptr;
+  }
 };
 
 }  // namespace
@@ -140,13 +196,14 @@ struct h2_matrix_s {
   size_t leaf_m0 = 0, leaf_blkdiag = 0;
   int64_t resident = 0;
   // workspace
-  Arena sf[2], lvl, mrg, small;
+  Arena sf[2], lvl, mrg, small, rs;
   // slicing cache and statistics
   std::vector<std::pair<double, int64_t>> cache;
   bool have_gersh = false;
   double g_lo = 0, g_hi = 0;
   h2_stats_t st{};
   int max_shifts = 0;
+  Profiler prof;
 
   template <class T>
   const T* dp(size_t off) const { return reinterpret_cast<const T*>(d_plan + off); }
@@ -194,12 +251,12 @@ void upload_plan(h2_matrix A) {
       dc.rec_yty = put_list(b, cp.rec_yty);
       dc.rec_u = put_list(b, cp.rec_u);
       dc.rec_w = put_list(b, cp.rec_w);
-      dc.rot_rows = b.put(cp.rot_rows);
-      dc.nrr = (int)cp.rot_rows.size();
-      dc.rot_cols = b.put(cp.rot_cols);
-      dc.nrc = (int)cp.rot_cols.size();
-      dc.trsm = b.put(cp.trsm);
-      dc.ntr = (int)cp.trsm.size();
+      dc.rot_rows = put_list(b, cp.rot_rows);
+      dc.rot_cols = put_list(b, cp.rot_cols);
+      dc.trsm = put_list(b, cp.trsm);
+      dc.rr_copy = b.put(cp.rot_rows_copy);
+      dc.rc_copy = b.put(cp.rot_cols_copy);
+      dc.tr_copy = b.put(cp.trsm_copy);
       dc.schur = put_list(b, cp.schur);
       dc.gm = put_list(b, cp.gram_m);
       dc.gt = put_list(b, cp.gram_t);
@@ -305,9 +362,9 @@ void build_near_blocks(h2_matrix A) {
       int i = bi[b0 + k], j = bj[b0 + k];
       Ref q{B_PMAT, i, 0, 0, 0, 0}, a{B_HAT, k, 0, 0, 0, 0}, t{B_TMP, k, 0, 0, 0, 0}, o{B_BRES, b0 + k, 0, 0, 0, 0};
       Ref none{-1, 0, 0, 0, 0, 0};
-      GItem it1{t, none, msz[i], msz[j], 0, 0, 1.0, 0.0};
+      GItem it1{t, none, msz[i], msz[j], 0, 0, 1.0, 0.0, -1};
       g1.add(it1, {GTerm{q, a, msz[i], -1, 0}});
-      GItem it2{o, none, msz[i], msz[j], 0, 0, 1.0, 0.0};
+      GItem it2{o, none, msz[i], msz[j], 0, 0, 1.0, 0.0, -1};
       g2.add(it2, {GTerm{t, Ref{B_PMAT, j, 0, 0, 0, 0}, msz[j], -1, 0}});
     }
     GItem *di1, *di2;
@@ -415,7 +472,10 @@ void debug_dump_level(int l, int N, int S, const Work& w, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(nu.data(), w.nu, S * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(stv.data(), w.status, S * 4, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  std::fprintf(stderr, "[h2eig] level %d: nu[0]=%llu status[0]=%d\n", l, nu[0], stv[0]);
+  int mmax = 0, tmax = 0;
+  for (int v : m) mmax = std::max(mmax, v);
+  for (int v : t) tmax = std::max(tmax, v);
+  std::fprintf(stderr, "[h2eig] level %d: nu[0]=%llu status[0]=%d max m %d max t %d\n", l, nu[0], stv[0], mmax, tmax);
   std::fprintf(stderr, "[h2eig]   m:");
   for (int i = 0; i < std::min(N, 32); ++i) std::fprintf(stderr, " %d", m[i]);
   std::fprintf(stderr, "\n[h2eig]   R:");
@@ -501,6 +561,22 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
       const LevelPlan& lpl = A->plan[l];
       setb(B_CPL, A->d_cpl[l], 0, (size_t)std::max(1, lpl.rmax) * std::max(1, lpl.rmax), std::max(1, lpl.rmax));
     }
+    Profiler& prof = A->prof;
+    auto run = [&](int cls, auto&& fn) {
+      bt.fc = prof.on ? prof.d_fc + cls : nullptr;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (prof.on) {
+        e0 = prof.get();
+        HIPCHK(hipEventRecord(e0, st));
+      }
+      fn();
+      if (prof.on) {
+        e1 = prof.get();
+        HIPCHK(hipEventRecord(e1, st));
+        prof.recs.push_back({cls, {e0, e1}});
+      }
+      bt.fc = nullptr;
+    };
     SizeTab sz{};
     sz.m = w.m;
     sz.R = w.R;
@@ -516,42 +592,67 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
       bt.ss[B_BRES] = 0;
       bt.bs[B_BRES] = (int64_t)bsz;
       bt.ld[B_BRES] = cap;
-      launch_sizes_init(sz, A->dp<int>(A->leaf_m0), S, st);
-      launch_leaf_init(bt, lp.nblk(), A->dp<int>(A->leaf_blkdiag), w.sigma, cap, S, st);
+      run(PC_INIT, [&] { launch_sizes_init(sz, A->dp<int>(A->leaf_m0), S, st); });
+      run(PC_INIT, [&] { launch_leaf_init(bt, lp.nblk(), A->dp<int>(A->leaf_blkdiag), w.sigma, cap, S, st); });
     }
-    launch_fill(dG, nG, 0.0, st);
-    launch_fill(dSg, nSg, 0.0, st);
-    launch_gemm(GEMM_NT, A->dp<GItem>(dl.gram_init.items), dl.gram_init.n, A->dp<GTerm>(dl.gram_init.terms), bt, sz,
-                cap, cap, S, st);
+    run(PC_INIT, [&] { launch_fill(dG, nG, 0.0, st); });
+    run(PC_INIT, [&] { launch_fill(dSg, nSg, 0.0, st); });
+    if (dl.gram_init.n)
+      run(PC_GRAM, [&] {
+        launch_gemm(GEMM_NT, A->dp<GItem>(dl.gram_init.items), dl.gram_init.n, A->dp<GTerm>(dl.gram_init.terms), bt,
+                    sz, cap, cap, S, st);
+      });
     const double tau2 = A->tau * A->tau;
+    // scratch slots of the out-of-place products: about 2 GB per shift at most
+    int max_items = 1;
+    for (const DevColour& dc : dl.colours)
+      max_items = std::max({max_items, dc.rot_rows.n, dc.rot_cols.n, dc.trsm.n});
+    const int CH = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)max_items, 65535,
+                                                                (int64_t)(2LL << 30) / (int64_t)(bsz * 8)}));
+    A->rs.ensure((size_t)S * CH * bsz * 8 + 64, st);
+    setb(B_RS, (double*)A->rs.p, (size_t)CH * bsz, bsz, cap);
+    auto chunked = [&](int cls, int kind, const DevList& gl, size_t copies) {
+      for (int c0 = 0; c0 < gl.n; c0 += CH) {
+        int nc = std::min(CH, gl.n - c0);
+        run(cls, [&] { launch_gemm(kind, A->dp<GItem>(gl.items) + c0, nc, A->dp<GTerm>(gl.terms), bt, sz, cap, cap, S, st); });
+        run(PC_COPY, [&] { launch_copyback(A->dp<CopyItem>(copies) + c0, nc, bt, sz, cap, S, st); });
+      }
+    };
     for (size_t c = 0; c < dl.colours.size(); ++c) {
       const DevColour& dc = dl.colours[c];
       const int* cl = A->dp<int>(dc.clusters);
-      launch_pchol(cl, dc.ncl, bt, sz, tau2, cap, S, st);
-      launch_hqr(cl, dc.ncl, bt, sz, cap, S, st);
-      launch_gemm(GEMM_TN, A->dp<GItem>(dc.rec_yty.items), dc.rec_yty.n, A->dp<GTerm>(dc.rec_yty.terms), bt, sz, cap, cap,
-                  S, st);
-      launch_tmat(cl, dc.ncl, bt, sz, S, st);
-      launch_gemm(GEMM_NN, A->dp<GItem>(dc.rec_u.items), dc.rec_u.n, A->dp<GTerm>(dc.rec_u.terms), bt, sz, cap, cap, S, st);
-      launch_eye(cl, dc.ncl, bt, sz, cap, S, st);
-      launch_gemm(GEMM_NT, A->dp<GItem>(dc.rec_w.items), dc.rec_w.n, A->dp<GTerm>(dc.rec_w.terms), bt, sz, cap, cap, S, st);
-      launch_rotate(A->dp<RotItem>(dc.rot_rows), dc.nrr, bt, sz, cap, S, st);
-      launch_rotate(A->dp<RotItem>(dc.rot_cols), dc.nrc, bt, sz, cap, S, st);
-      launch_ldl(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, w.nu, w.status, cap, S, st);
-      launch_trsm(A->dp<TrsmItem>(dc.trsm), dc.ntr, bt, sz, cap, S, st);
-      launch_gemm(GEMM_NT, A->dp<GItem>(dc.schur.items), dc.schur.n, A->dp<GTerm>(dc.schur.terms), bt, sz, cap, cap, S, st);
-      launch_gemm(GEMM_TN, A->dp<GItem>(dc.gm.items), dc.gm.n, A->dp<GTerm>(dc.gm.terms), bt, sz, cap, cap, S, st);
-      launch_matsum(A->dp<SumItem>(dc.gp_items), dc.ngp, A->dp<int>(dc.gp_src), bt, sz, cap, S, st);
-      launch_gemm(GEMM_NN, A->dp<GItem>(dc.gt.items), dc.gt.n, A->dp<GTerm>(dc.gt.terms), bt, sz, cap, cap, S, st);
-      launch_gemm(GEMM_NT, A->dp<GItem>(dc.gg.items), dc.gg.n, A->dp<GTerm>(dc.gg.terms), bt, sz, cap, cap, S, st);
+      auto gl = [&](int cls, int kind, const DevList& L) {
+        if (L.n) run(cls, [&] { launch_gemm(kind, A->dp<GItem>(L.items), L.n, A->dp<GTerm>(L.terms), bt, sz, cap, cap, S, st); });
+      };
+      run(PC_PCHOL, [&] { launch_pchol(cl, dc.ncl, bt, sz, tau2, cap, S, st); });
+      run(PC_HQR, [&] { launch_hqr(cl, dc.ncl, bt, sz, cap, S, st); });
+      gl(PC_WFORM, GEMM_TN, dc.rec_yty);
+      run(PC_TMAT, [&] { launch_tmat(cl, dc.ncl, bt, sz, S, st); });
+      gl(PC_WFORM, GEMM_NN, dc.rec_u);
+      run(PC_WFORM, [&] { launch_eye(cl, dc.ncl, bt, sz, cap, S, st); });
+      gl(PC_WFORM, GEMM_NT, dc.rec_w);
+      chunked(PC_ROTATE, GEMM_TN, dc.rot_rows, dc.rr_copy);
+      chunked(PC_ROTATE, GEMM_NN, dc.rot_cols, dc.rc_copy);
+      run(PC_LDL, [&] { launch_ldl(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, w.nu, w.status, cap, S, st); });
+      chunked(PC_ELIM, GEMM_NN, dc.trsm, dc.tr_copy);
+      gl(PC_SCHUR, GEMM_NT, dc.schur);
+      gl(PC_GRAM, GEMM_TN, dc.gm);
+      if (dc.ngp)
+        run(PC_GRAM, [&] { launch_matsum(A->dp<SumItem>(dc.gp_items), dc.ngp, A->dp<int>(dc.gp_src), bt, sz, cap, S, st); });
+      gl(PC_GRAM, GEMM_NN, dc.gt);
+      gl(PC_GRAM, GEMM_NT, dc.gg);
     }
     HIPCHK(hipGetLastError());
-    if (debug_level()) debug_dump_level(l, N, S, w, st);
+    if (debug_level()) {
+      debug_dump_level(l, N, S, w, st);
+      std::fprintf(stderr, "[h2eig]   cap %d arenas GB: sf %.2f %.2f lvl %.2f mrg %.2f\n", cap, A->sf[0].cap / 1e9,
+                   A->sf[1].cap / 1e9, A->lvl.cap / 1e9, A->mrg.cap / 1e9);
+    }
     if (l == 0) break;
     // ---- merge into level l-1
     const LevelPlan& pp = A->plan[l - 1];
     const int Np = N >> 1;
-    launch_merge_sizes(sz, Np, S, st);
+    run(PC_MERGE, [&] { launch_merge_sizes(sz, Np, S, st); });
     hpm.resize((size_t)S * Np);
     HIPCHK(hipMemcpyAsync(hpm.data(), w.pm, (size_t)S * Np * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -579,17 +680,24 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     setb(B_SN, dSN, (size_t)pp.nblk() * pbsz, pbsz, pcap);
     setb(B_FN, dFN, (size_t)pp.nfblk() * pbsz, pbsz, pcap);
     setb(B_EMAT, A->d_emat[l - 1], 0, (size_t)A->emat_ld[l - 1] * A->emat_ld[l - 1], A->emat_ld[l - 1]);
-    launch_pmat(bt, sz, A->dp<int>(dl.edim), Np, pcap, S, st);
+    run(PC_MERGE, [&] { launch_pmat(bt, sz, A->dp<int>(dl.edim), Np, pcap, S, st); });
     for (const MergeChunk& ch : mp.chunks) {
-      launch_gather(A->dp<GatherItem>(dl.gather) + ch.g0, ch.g1 - ch.g0, bt, sz, pcap, S, st);
-      launch_gemm(GEMM_NT, A->dp<GItem>(dl.fill.items) + ch.f0, ch.f1 - ch.f0, A->dp<GTerm>(dl.fill.terms), bt, sz, pcap,
-                  pcap, S, st);
-      launch_gemm(GEMM_TN, A->dp<GItem>(dl.tr1.items) + ch.a0, ch.a1 - ch.a0, A->dp<GTerm>(dl.tr1.terms), bt, sz, pcap,
-                  pcap, S, st);
-      launch_gemm(GEMM_NN, A->dp<GItem>(dl.tr2.items) + ch.b0, ch.b1 - ch.b0, A->dp<GTerm>(dl.tr2.terms), bt, sz, pcap,
-                  pcap, S, st);
+      run(PC_MERGE, [&] { launch_gather(A->dp<GatherItem>(dl.gather) + ch.g0, ch.g1 - ch.g0, bt, sz, pcap, S, st); });
+      if (ch.f1 > ch.f0)
+        run(PC_MERGE, [&] {
+          launch_gemm(GEMM_NT, A->dp<GItem>(dl.fill.items) + ch.f0, ch.f1 - ch.f0, A->dp<GTerm>(dl.fill.terms), bt, sz,
+                      pcap, pcap, S, st);
+        });
+      run(PC_MERGE, [&] {
+        launch_gemm(GEMM_TN, A->dp<GItem>(dl.tr1.items) + ch.a0, ch.a1 - ch.a0, A->dp<GTerm>(dl.tr1.terms), bt, sz, pcap,
+                    pcap, S, st);
+      });
+      run(PC_MERGE, [&] {
+        launch_gemm(GEMM_NN, A->dp<GItem>(dl.tr2.items) + ch.b0, ch.b1 - ch.b0, A->dp<GTerm>(dl.tr2.terms), bt, sz, pcap,
+                    pcap, S, st);
+      });
     }
-    launch_next_sizes(sz, S, st);
+    run(PC_MERGE, [&] { launch_next_sizes(sz, S, st); });
     HIPCHK(hipGetLastError());
     cur = other;
     cap = pcap;
@@ -599,6 +707,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
   HIPCHK(hipMemcpyAsync(hnu.data(), w.nu, S * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(hst.data(), w.status, S * 4, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  if (A->prof.on) A->prof.collect();
   for (int s = 0; s < S; ++s) {
     nu_out[s] = hst[s] ? -1 : (int64_t)hnu[s];
     if (st_out) st_out[s] = hst[s] ? H2_ENUMERIC : H2_OK;
@@ -638,6 +747,7 @@ h2_status run_inertia(h2_matrix A, const double* sigma, int64_t ns, int64_t* nu,
       for (auto& a : A->sf) a.release();
       A->lvl.release();
       A->mrg.release();
+      A->rs.release();
       continue;
     }
     for (int k = 0; k < S; ++k) {
@@ -647,7 +757,7 @@ h2_status run_inertia(h2_matrix A, const double* sigma, int64_t ns, int64_t* nu,
     s0 += S;
   }
   (void)t0;
-  int64_t ws = (int64_t)(A->sf[0].cap + A->sf[1].cap + A->lvl.cap + A->mrg.cap + A->small.cap);
+  int64_t ws = (int64_t)(A->sf[0].cap + A->sf[1].cap + A->lvl.cap + A->mrg.cap + A->small.cap + A->rs.cap);
   A->st.last_work_bytes = ws;
   return anybad ? H2_ENUMERIC : H2_OK;
 }
@@ -836,6 +946,34 @@ h2_status h2_tree_perm(h2_matrix A, int64_t* perm) {
   return H2_OK;
 }
 
+h2_status h2_profile_enable(h2_matrix A, int32_t enable) {
+  if (!A) return fail(H2_EINVAL, "NULL handle");
+  try {
+    HIPCHK(hipSetDevice(A->device));
+    if (enable && !A->prof.d_fc) {
+      HIPCHK(hipMalloc(&A->prof.d_fc, PC_N * sizeof(unsigned long long)));
+      HIPCHK(hipMemset(A->prof.d_fc, 0, PC_N * sizeof(unsigned long long)));
+    }
+  } catch (HipError& e) {
+    return fail(H2_EDEVICE, e.where + ": " + hipGetErrorString(e.e));
+  }
+  A->prof.on = enable != 0;
+  A->prof.reset();
+  return H2_OK;
+}
+
+int32_t h2_profile_classes(void) { return PC_N; }
+
+const char* h2_profile_class_name(int32_t cls) { return (cls >= 0 && cls < PC_N) ? kProfNames[cls] : ""; }
+
+h2_status h2_profile_read(h2_matrix A, int32_t cls, int64_t* launches, double* ms, double* flops) {
+  if (!A || cls < 0 || cls >= PC_N) return fail(H2_EINVAL, "bad handle or class");
+  if (launches) *launches = A->prof.launches[cls];
+  if (ms) *ms = A->prof.ms[cls];
+  if (flops) *flops = (double)A->prof.flops[cls];
+  return H2_OK;
+}
+
 void h2_free(h2_matrix A) {
   if (!A) return;
   if (A->stream) (void)hipStreamSynchronize(A->stream);
@@ -843,12 +981,14 @@ void h2_free(h2_matrix A) {
   A->lvl.release();
   A->mrg.release();
   A->small.release();
+  A->rs.release();
   if (A->d_bres) (void)hipFree(A->d_bres);
   for (auto p : A->d_cpl)
     if (p) (void)hipFree(p);
   for (auto p : A->d_emat)
     if (p) (void)hipFree(p);
   if (A->d_plan) (void)hipFree(A->d_plan);
+  A->prof.release();
   if (A->own_stream) (void)hipStreamDestroy(A->own_stream);
   delete A;
 }

@@ -44,12 +44,18 @@ constexpr int GK = 16;   // k step
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, const GTerm* __restrict__ terms,
-                                              BufTab bt, SizeTab sz, int tiles_n) {
+                                              BufTab bt, SizeTab sz, int tiles_n, int slot_base) {
   const int s = blockIdx.z;
   const GItem it = items[blockIdx.y];
+  if (it.guard != -1 && dev_eval(it.guard, sz, s) == 0) return;
   const int M = dev_eval(it.M, sz, s), N = dev_eval(it.N, sz, s);
   const int m0 = (blockIdx.x / tiles_n) * GT, n0 = (blockIdx.x % tiles_n) * GT;
   if (m0 >= M || n0 >= N) return;
+  if (bt.fc && blockIdx.x == 0 && threadIdx.x == 0) {
+    unsigned long long kk = 0;
+    for (int tt = 0; tt < it.nt; ++tt) kk += (unsigned long long)max(0, dev_eval(terms[it.t0 + tt].K, sz, s));
+    atomicAdd(bt.fc, 2ull * (unsigned long long)M * (unsigned long long)N * kk);
+  }
   __shared__ double As[GK][GT + 1];
   __shared__ double Bs[GK][GT + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -109,7 +115,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, c
   }
   int cr, cc;
   ref_origin(it.c, sz, s, &cr, &cc);
-  double* C = addr(bt, it.c.buf, it.c.blk, s, cr, cc);
+  double* C = addr(bt, it.c.buf, it.c.blk >= 0 ? it.c.blk : (int)blockIdx.y + slot_base, s, cr, cc);
   const int ldc = bt.ld[it.c.buf];
   double* C2 = nullptr;
   int ldc2 = 0;
@@ -151,6 +157,24 @@ __global__ void k_matsum(const SumItem* __restrict__ items, const int* __restric
       acc += addr(bt, b, k, s, r, c)[0];
     }
     C[r + (int64_t)c * ldc] = acc;
+  }
+}
+
+// -------------------------------------------------------- scratch copy-back
+__global__ void k_copyback(const CopyItem* __restrict__ items, BufTab bt, SizeTab sz, int slot_base) {
+  const int s = blockIdx.z;
+  const CopyItem it = items[blockIdx.y];
+  if (it.guard != -1 && dev_eval(it.guard, sz, s) == 0) return;
+  const int M = dev_eval(it.M, sz, s), N = dev_eval(it.N, sz, s);
+  int r0, c0;
+  ref_origin(it.x, sz, s, &r0, &c0);
+  double* X = addr(bt, it.x.buf, it.x.blk, s, r0, c0);
+  const int ldx = bt.ld[it.x.buf];
+  const double* Sc = addr(bt, B_RS, (int)blockIdx.y + slot_base, s, 0, 0);
+  const int lds = bt.ld[B_RS];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)M * N; e += (int64_t)gridDim.x * blockDim.x) {
+    int a = (int)(e % M), b = (int)(e / M);
+    X[a + (int64_t)b * ldx] = Sc[a + (int64_t)b * lds];
   }
 }
 
@@ -253,6 +277,7 @@ __global__ __launch_bounds__(RT_THREADS) void k_pchol(const int* __restrict__ cl
   if (tid == 0) {
     sz.t[s * N + i] = t;
     sz.R[s * N + i] = R - t;
+    if (bt.fc) atomicAdd(bt.fc, (unsigned long long)R * (unsigned long long)t * (unsigned long long)(t > 0 ? t - 1 : 0));
   }
 }
 
@@ -272,6 +297,10 @@ __global__ __launch_bounds__(RT_THREADS) void k_hqr(const int* __restrict__ clus
   if (t == 0) return;
   const int RT = sz.R[s * N + i] + t;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (bt.fc && tid == 0) {
+    double f = 2.0 * RT * (double)t * t - 2.0 / 3.0 * (double)t * t * t;
+    atomicAdd(bt.fc, (unsigned long long)(f > 0 ? f : 0));
+  }
   const int ld = bt.ld[B_V];
   double* V = addr(bt, B_V, i, s, 0, 0);
   double* beta_out = addr(bt, B_G, i, s, 0, 0) + (int64_t)(ld - 1) * ld;   // last column of B_G
@@ -413,6 +442,7 @@ __global__ __launch_bounds__(RT_THREADS) void k_tmat(const int* __restrict__ clu
   const int t = sz.t[s * sz.N + i];
   if (t == 0) return;
   const int tid = threadIdx.x;
+  if (bt.fc && tid == 0) atomicAdd(bt.fc, (unsigned long long)((double)t * t * t / 3.0));
   const int ld = bt.ld[B_G];
   double* Tm = addr(bt, B_G, i, s, 0, 0);
   const double* beta = Tm + (int64_t)(ld - 1) * ld;
@@ -770,6 +800,7 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl(const int* __restrict__ clu
     for (int w2 = 0; w2 < LDL_THREADS / 64; ++w2) tot += red[w2];
     atomicAdd(nu + s, (unsigned long long)(tot + 0.5));
     if (s_bad) atomicOr(status + s, 1);
+    if (bt.fc) atomicAdd(bt.fc, (unsigned long long)(2.0 / 3.0 * (double)R * R * R));
   }
 }
 
@@ -979,11 +1010,20 @@ void launch_gemm(int kind, const GItem* items, int nitems, const GTerm* terms, c
     int ni = std::min(65535, nitems - i0);
     dim3 grid(tm * tn, ni, nshift);
     switch (kind) {
-      case GEMM_NN: hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, items + i0, terms, bt, sz, tn); break;
-      case GEMM_NT: hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, items + i0, terms, bt, sz, tn); break;
-      case GEMM_TN: hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, items + i0, terms, bt, sz, tn); break;
-      default: hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, items + i0, terms, bt, sz, tn); break;
+      case GEMM_NN: hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, items + i0, terms, bt, sz, tn, i0); break;
+      case GEMM_NT: hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, items + i0, terms, bt, sz, tn, i0); break;
+      case GEMM_TN: hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, items + i0, terms, bt, sz, tn, i0); break;
+      default: hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, items + i0, terms, bt, sz, tn, i0); break;
     }
+  }
+}
+
+void launch_copyback(const CopyItem* items, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st) {
+  if (n <= 0) return;
+  for (int i0 = 0; i0 < n; i0 += 65535) {
+    int ni = std::min(65535, n - i0);
+    hipLaunchKernelGGL(k_copyback, dim3(std::max(1u, cdiv((int64_t)cap * cap, 256 * 8)), ni, nshift), dim3(256), 0, st,
+                       items + i0, bt, sz, i0);
   }
 }
 

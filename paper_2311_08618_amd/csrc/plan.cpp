@@ -40,7 +40,7 @@ static GTerm term(Ref a, Ref b, int K, int wbuf = -1, int wblk = 0) {
 
 static GItem item(Ref c, Ref c2, int M, int N, double alpha, double beta) {
   GItem g;
-  g.c = c; g.c2 = c2; g.M = M; g.N = N; g.alpha = alpha; g.beta = beta; g.t0 = 0; g.nt = 0;
+  g.c = c; g.c2 = c2; g.M = M; g.N = N; g.alpha = alpha; g.beta = beta; g.t0 = 0; g.nt = 0; g.guard = -1;
   return g;
 }
 
@@ -107,25 +107,29 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
         cp.rec_w.add(item(ref(B_W, i), noref(), dx(DK_RT, i), dx(DK_RT, i), -1.0, 1.0),
                       {term(ref(B_Z, i), ref(B_V, i), dx(DK_T, i))});
       }
+      // rotation by W (rows, then columns) and elimination by K, each as an
+      // out-of-place product into a scratch slot followed by a copy back
+      auto rot = [&](int buf, int blk_row, int blk_col, int i, int other) {
+        GItem g = item(ref(B_RS, -1), noref(), dx(DK_RT, i), other, 1.0, 0.0);
+        g.guard = dx(DK_T, i);
+        cp.rot_rows.add(g, {term(ref(B_W, i), ref(buf, blk_row), dx(DK_RT, i))});
+        CopyItem cr{ref(buf, blk_row), dx(DK_RT, i), other, dx(DK_T, i)};
+        cp.rot_rows_copy.push_back(cr);
+        GItem h = item(ref(B_RS, -1), noref(), other, dx(DK_RT, i), 1.0, 0.0);
+        h.guard = dx(DK_T, i);
+        cp.rot_cols.add(h, {term(ref(buf, blk_col), ref(B_W, i), dx(DK_RT, i))});
+        CopyItem cc{ref(buf, blk_col), other, dx(DK_RT, i), dx(DK_T, i)};
+        cp.rot_cols_copy.push_back(cc);
+      };
       for (int i : cp.clusters) {
+        for (int k : T.near[l][i]) rot(B_S, lp.blk(i, k), lp.blk(k, i), i, dx(DK_M, k));
+        for (int q : carried[l][i]) rot(B_F, lp.fblk(i, q), lp.fblk(q, i), i, dx(DK_M, q));
         for (int k : T.near[l][i]) {
-          RotItem r;
-          r.buf = B_S; r.blk = lp.blk(i, k); r.cluster = i; r.side = 0; r.other = dx(DK_M, k);
-          cp.rot_rows.push_back(r);
-          r.blk = lp.blk(k, i); r.side = 1;
-          cp.rot_cols.push_back(r);
-        }
-        for (int q : carried[l][i]) {
-          RotItem r;
-          r.buf = B_F; r.blk = lp.fblk(i, q); r.cluster = i; r.side = 0; r.other = dx(DK_M, q);
-          cp.rot_rows.push_back(r);
-          r.blk = lp.fblk(q, i); r.side = 1;
-          cp.rot_cols.push_back(r);
-        }
-        for (int k : T.near[l][i]) {
-          TrsmItem t;
-          t.blk = lp.blk(k, i); t.cluster = i; t.row0 = row0(k); t.nrows = nrows(k);
-          cp.trsm.push_back(t);
+          GItem g = item(ref(B_RS, -1), noref(), nrows(k), dx(DK_R, i), 1.0, 0.0);
+          g.guard = dx(DK_R, i);
+          cp.trsm.add(g, {term(ref(B_S, lp.blk(k, i), row0(k), 0), ref(B_G, i), dx(DK_R, i))});
+          CopyItem ct{ref(B_S, lp.blk(k, i), row0(k), 0), nrows(k), dx(DK_R, i), dx(DK_R, i)};
+          cp.trsm_copy.push_back(ct);
         }
       }
       // Schur updates, aggregated per target pair (j <= k)

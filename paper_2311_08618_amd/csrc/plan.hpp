@@ -31,8 +31,10 @@ struct ColourPlan {
   GList rec_yty;               // TN: Y^T Y (into B_W, before W exists)
   GList rec_u;                 // NN: U = Y T
   GList rec_w;                 // NT: W = I - U Y^T
-  std::vector<RotItem> rot_rows, rot_cols;
-  std::vector<TrsmItem> trsm;
+  GList rot_rows, rot_cols;    // TN: RS = W^T X ; NN: RS = X W
+  std::vector<CopyItem> rot_rows_copy, rot_cols_copy;
+  GList trsm;                  // NN: RS = X K
+  std::vector<CopyItem> trsm_copy;
   GList schur;                 // NT, alpha -1
   GList gram_m;                // TN
   SumList gram_p;

@@ -62,6 +62,14 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.h2_set_stream.argtypes = [C.c_void_p, C.c_void_p]
     lib.h2_tree_perm.restype = C.c_int
     lib.h2_tree_perm.argtypes = [C.c_void_p, P(C.c_int64)]
+    lib.h2_profile_enable.restype = C.c_int
+    lib.h2_profile_enable.argtypes = [C.c_void_p, C.c_int32]
+    lib.h2_profile_classes.restype = C.c_int32
+    lib.h2_profile_classes.argtypes = []
+    lib.h2_profile_class_name.restype = C.c_char_p
+    lib.h2_profile_class_name.argtypes = [C.c_int32]
+    lib.h2_profile_read.restype = C.c_int
+    lib.h2_profile_read.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double)]
     lib.h2_free.restype = None
     lib.h2_free.argtypes = [C.c_void_p]
     lib.h2_last_error.restype = C.c_char_p
@@ -72,6 +80,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
 _lib = load_library()
 
 EXPORTED = ["h2_build", "h2_inertia", "h2_kth_eig", "h2_norm", "h2_stats", "h2_set_stream", "h2_tree_perm",
+            "h2_profile_enable", "h2_profile_classes", "h2_profile_class_name", "h2_profile_read",
             "h2_free", "h2_last_error"]
 
 
@@ -145,6 +154,19 @@ class H2Matrix:
         p = np.zeros(self.n, dtype=np.int64)
         _check(_lib.h2_tree_perm(self._h, p.ctypes.data_as(C.POINTER(C.c_int64))))
         return p
+
+    def profile_enable(self, on: bool = True):
+        _check(_lib.h2_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        out = {}
+        for c in range(_lib.h2_profile_classes()):
+            n = C.c_int64()
+            ms = C.c_double()
+            fl = C.c_double()
+            _check(_lib.h2_profile_read(self._h, c, C.byref(n), C.byref(ms), C.byref(fl)))
+            out[_lib.h2_profile_class_name(c).decode()] = {"launches": n.value, "ms": ms.value, "flops": fl.value}
+        return out
 
     def set_stream(self, stream_ptr: int):
         _check(_lib.h2_set_stream(self._h, C.c_void_p(stream_ptr)))
