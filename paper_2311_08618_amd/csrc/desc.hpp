@@ -26,6 +26,12 @@ enum DimKind : int {
   DK_R0 = 6,     // r0(c): skeleton rank of the construction
   DK_PM = 7,     // parent dimension m(p) (merge)
   DK_PR = 8,     // parent redundant count R(p) (merge)
+  DK_A0 = 9,     // a0(c): panel start of the current blocked factorization step
+  DK_A1 = 10,    // a1(c): panel width of the current step
+  DK_TMA0 = 11,  // t(c) - a0(c)
+  DK_TREM = 12,  // t(c) - a0(c) - a1(c): columns to the right of the panel
+  DK_RTMA0 = 13, // R(c) + t(c) - a0(c)
+  DK_RMK = 14,   // R(c) - a0(c) - a1(c): trailing rows of a pivot block
 };
 
 __host__ __device__ inline int dx(int kind, int arg) { return (kind << 24) | arg; }
@@ -67,6 +73,8 @@ struct SizeTab {
   int* m;          // [S][N]
   int* R;          // [S][N]
   int* t;          // [S][N]
+  int* a0;         // [S][N] panel state of the blocked per-cluster factorizations
+  int* a1;         // [S][N]
   const int* r0;   // [N]
   int* pm;         // [S][Np]
   int* pR;         // [S][Np]
@@ -86,6 +94,12 @@ __host__ __device__ inline int dev_eval(int e, const SizeTab& z, int s) {
     case DK_R0: return z.r0[a];
     case DK_PM: return z.pm[s * z.Np + a];
     case DK_PR: return z.pR[s * z.Np + a];
+    case DK_A0: return z.a0[s * z.N + a];
+    case DK_A1: return z.a1[s * z.N + a];
+    case DK_TMA0: return z.t[s * z.N + a] - z.a0[s * z.N + a];
+    case DK_TREM: return z.t[s * z.N + a] - z.a0[s * z.N + a] - z.a1[s * z.N + a];
+    case DK_RTMA0: return z.R[s * z.N + a] + z.t[s * z.N + a] - z.a0[s * z.N + a];
+    case DK_RMK: return z.R[s * z.N + a] - z.a0[s * z.N + a] - z.a1[s * z.N + a];
   }
   return 0;
 }

@@ -102,7 +102,7 @@ struct DevList {
 struct DevColour {
   size_t clusters = 0;
   int ncl = 0;
-  DevList rec_yty, rec_u, rec_w;
+  DevList pc_upd, hq_z, hq_v, w_q, w_w, ldl_upd, inv_t, inv_x;
   DevList rot_rows, rot_cols, trsm;
   size_t rr_copy = 0, rc_copy = 0, tr_copy = 0;
   DevList schur, gm, gt, gg;
@@ -119,12 +119,13 @@ struct DevLevel {
 
 // Kernel classes of the level engine, for the diagnostic profiler.
 enum ProfClass {
-  PC_INIT = 0, PC_PCHOL, PC_HQR, PC_TMAT, PC_WFORM, PC_ROTATE, PC_LDL, PC_ELIM, PC_COPY, PC_SCHUR, PC_GRAM, PC_MERGE,
-  PC_N
+  PC_INIT = 0, PC_PCHOL, PC_PCHOL_UPD, PC_HQR, PC_HQR_UPD, PC_WFORM, PC_ROTATE, PC_LDL, PC_LDL_UPD, PC_LDL_INV, PC_ELIM,
+  PC_COPY, PC_SCHUR, PC_GRAM, PC_MERGE, PC_N
 };
-const char* const kProfNames[PC_N] = {"init", "recompress_pchol", "recompress_hqr", "recompress_t", "recompress_w",
-                                      "rotate", "pivot_ldl", "elimination", "copyback", "schur", "fillin_gram",
-                                      "merge"};
+const char* const kProfNames[PC_N] = {"init", "recompress_pchol", "recompress_pchol_update", "recompress_hqr",
+                                      "recompress_hqr_update", "recompress_w", "rotate", "pivot_ldl",
+                                      "pivot_ldl_update", "pivot_ldl_inverse", "elimination", "copyback", "schur",
+                                      "fillin_gram", "merge"};
 
 // Brackets kernel launches with HIP events on the handle's stream and keeps a
 // device array of per-class algorithmic flop counters.
@@ -204,6 +205,8 @@ struct h2_matrix_s {
   h2_stats_t st{};
   int max_shifts = 0;
   Profiler prof;
+  int* d_more = nullptr;   // "more panels needed" counter of the blocked factorizations
+  int* h_more = nullptr;   // pinned host copy
 
   template <class T>
   const T* dp(size_t off) const { return reinterpret_cast<const T*>(d_plan + off); }
@@ -248,9 +251,14 @@ void upload_plan(h2_matrix A) {
       DevColour& dc = dl.colours[c];
       dc.clusters = b.put(cp.clusters);
       dc.ncl = (int)cp.clusters.size();
-      dc.rec_yty = put_list(b, cp.rec_yty);
-      dc.rec_u = put_list(b, cp.rec_u);
-      dc.rec_w = put_list(b, cp.rec_w);
+      dc.pc_upd = put_list(b, cp.pc_upd);
+      dc.hq_z = put_list(b, cp.hq_z);
+      dc.hq_v = put_list(b, cp.hq_v);
+      dc.w_q = put_list(b, cp.w_q);
+      dc.w_w = put_list(b, cp.w_w);
+      dc.ldl_upd = put_list(b, cp.ldl_upd);
+      dc.inv_t = put_list(b, cp.inv_t);
+      dc.inv_x = put_list(b, cp.inv_x);
       dc.rot_rows = put_list(b, cp.rot_rows);
       dc.rot_cols = put_list(b, cp.rot_cols);
       dc.trsm = put_list(b, cp.trsm);
@@ -448,11 +456,19 @@ void upload_resident(h2_matrix A) {
 struct Work {
   int S = 0;
   int *m = nullptr, *R = nullptr, *t = nullptr, *pm = nullptr, *pR = nullptr, *status = nullptr;
+  int *a0 = nullptr, *a1 = nullptr;
   unsigned long long* nu = nullptr;
   double* sigma = nullptr;
 };
 
 inline int round_cap(int v) { return std::max(8, (v + 7) & ~7); }
+
+// Number of clusters that need another panel (read back synchronously).
+int read_more(h2_matrix A, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(A->h_more, A->d_more, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return *A->h_more;
+}
 
 int debug_level() {
   static int v = [] {
@@ -495,8 +511,8 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
   // small arena: sizes tables + sigma + nu + status
   size_t nsz = (size_t)S * Nmax;
   size_t off_m = 0, off_R = off_m + nsz * 4, off_t = off_R + nsz * 4, off_pm = off_t + nsz * 4,
-         off_pR = off_pm + nsz * 4, off_st = off_pR + nsz * 4, off_sig = ((off_st + S * 4 + 255) / 256) * 256,
-         off_nu = off_sig + S * 8, total = off_nu + S * 8;
+         off_pR = off_pm + nsz * 4, off_a0 = off_pR + nsz * 4, off_a1 = off_a0 + nsz * 4, off_st = off_a1 + nsz * 4,
+         off_sig = ((off_st + S * 4 + 255) / 256) * 256, off_nu = off_sig + S * 8, total = off_nu + S * 8;
   A->small.ensure(total, st);
   char* base = (char*)A->small.p;
   Work w;
@@ -506,6 +522,8 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
   w.t = (int*)(base + off_t);
   w.pm = (int*)(base + off_pm);
   w.pR = (int*)(base + off_pR);
+  w.a0 = (int*)(base + off_a0);
+  w.a1 = (int*)(base + off_a1);
   w.status = (int*)(base + off_st);
   w.sigma = (double*)(base + off_sig);
   w.nu = (unsigned long long*)(base + off_nu);
@@ -584,6 +602,8 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     sz.r0 = A->dp<int>(dl.r0);
     sz.pm = w.pm;
     sz.pR = w.pR;
+    sz.a0 = w.a0;
+    sz.a1 = w.a1;
     sz.N = N;
     sz.Np = std::max(1, N >> 1);
     sz.pr0 = l >= 1 ? A->dp<int>(dl.pr0) : nullptr;
@@ -621,20 +641,57 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     for (size_t c = 0; c < dl.colours.size(); ++c) {
       const DevColour& dc = dl.colours[c];
       const int* cl = A->dp<int>(dc.clusters);
-      auto gl = [&](int cls, int kind, const DevList& L) {
-        if (L.n) run(cls, [&] { launch_gemm(kind, A->dp<GItem>(L.items), L.n, A->dp<GTerm>(L.terms), bt, sz, cap, cap, S, st); });
+      auto gl = [&](int cls, int kind, const DevList& L, int mcap = 0) {
+        const int mc = mcap > 0 ? mcap : cap;
+        if (L.n) run(cls, [&] { launch_gemm(kind, A->dp<GItem>(L.items), L.n, A->dp<GTerm>(L.terms), bt, sz, mc, cap, S, st); });
       };
-      run(PC_PCHOL, [&] { launch_pchol(cl, dc.ncl, bt, sz, tau2, cap, S, st); });
-      run(PC_HQR, [&] { launch_hqr(cl, dc.ncl, bt, sz, cap, S, st); });
-      gl(PC_WFORM, GEMM_TN, dc.rec_yty);
-      run(PC_TMAT, [&] { launch_tmat(cl, dc.ncl, bt, sz, S, st); });
-      gl(PC_WFORM, GEMM_NN, dc.rec_u);
+      // pivoted Cholesky of the fill-in Gram, panel by panel
+      run(PC_PCHOL, [&] { launch_pchol_init(cl, dc.ncl, bt, sz, S, st); });
+      for (int it = 0; it <= cap / 32 + 2; ++it) {
+        HIPCHK(hipMemsetAsync(A->d_more, 0, sizeof(int), st));
+        run(PC_PCHOL, [&] { launch_pchol_panel(cl, dc.ncl, bt, sz, tau2, A->d_more, cap, S, st); });
+        gl(PC_PCHOL_UPD, GEMM_NT, dc.pc_upd);
+        if (read_more(A, st) == 0) break;
+      }
+      run(PC_PCHOL, [&] { launch_pchol_finish(cl, dc.ncl, bt, sz, S, st); });
+      // Householder QR of the kept columns, panel by panel
+      int npanel = 0;
+      for (int it = 0; it <= cap / 32 + 2; ++it) {
+        HIPCHK(hipMemsetAsync(A->d_more, 0, sizeof(int), st));
+        run(PC_HQR, [&] { launch_hqr_panel(cl, dc.ncl, bt, sz, it, A->d_more, S, st); });
+        gl(PC_HQR_UPD, GEMM_TN, dc.hq_z);
+        gl(PC_HQR_UPD, GEMM_NN, dc.hq_v);
+        npanel = it + 1;
+        if (read_more(A, st) == 0) break;
+      }
+      // W = prod_p (I - Y_p T_p Y_p^T)
       run(PC_WFORM, [&] { launch_eye(cl, dc.ncl, bt, sz, cap, S, st); });
-      gl(PC_WFORM, GEMM_NT, dc.rec_w);
+      for (int it = 0; it < npanel; ++it) {
+        run(PC_WFORM, [&] { launch_set_panel(cl, dc.ncl, sz, it, S, st); });
+        gl(PC_WFORM, GEMM_NN, dc.w_q);
+        gl(PC_WFORM, GEMM_NT, dc.w_w);
+      }
       chunked(PC_ROTATE, GEMM_TN, dc.rot_rows, dc.rr_copy);
       chunked(PC_ROTATE, GEMM_NN, dc.rot_cols, dc.rc_copy);
-      run(PC_LDL, [&] { launch_ldl(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, w.nu, w.status, cap, S, st); });
-      chunked(PC_ELIM, GEMM_NN, dc.trsm, dc.tr_copy);
+      // pivot LDL, panel by panel, then the elimination operator
+      run(PC_LDL, [&] { launch_ldl_init(cl, dc.ncl, bt, sz, S, st); });
+      for (int it = 0; it <= cap / 16 + 2; ++it) {
+        HIPCHK(hipMemsetAsync(A->d_more, 0, sizeof(int), st));
+        run(PC_LDL, [&] { launch_ldl_panel(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, w.status, A->d_more, S, st); });
+        gl(PC_LDL_UPD, GEMM_NT, dc.ldl_upd);
+        if (read_more(A, st) == 0) break;
+      }
+      run(PC_LDL, [&] { launch_ldl_prep(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, w.nu, S, st); });
+      // X = L^{-1}: diagonal blocks, then block rows by GEMMs
+      run(PC_LDL, [&] { launch_zero_clusters(cl, dc.ncl, bt, B_V, cap, S, st); });
+      run(PC_LDL, [&] { launch_diag_inv(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, cap, S, st); });
+      for (int ib = 1; ib * inv_block() < cap; ++ib) {
+        run(PC_LDL, [&] { launch_set_block(cl, dc.ncl, sz, ib, S, st); });
+        gl(PC_LDL_INV, GEMM_NN, dc.inv_t, inv_block());
+        gl(PC_LDL_INV, GEMM_NN, dc.inv_x, inv_block());
+      }
+      run(PC_LDL, [&] { launch_kform(cl, dc.ncl, bt, sz, cap, S, st); });
+      chunked(PC_ELIM, GEMM_NT, dc.trsm, dc.tr_copy);
       gl(PC_SCHUR, GEMM_NT, dc.schur);
       gl(PC_GRAM, GEMM_TN, dc.gm);
       if (dc.ngp)
@@ -812,6 +869,8 @@ h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern,
     A->leafcap = 0;
     for (int i = 0; i < (1 << L); ++i) A->leafcap = std::max<int>(A->leafcap, (int)A->T.size[L][i]);
     A->leafcap = round_cap(A->leafcap);
+    HIPCHK(hipMalloc(&A->d_more, sizeof(int)));
+    HIPCHK(hipHostMalloc(&A->h_more, sizeof(int)));
     upload_plan(A);
     upload_resident(A);
     build_near_blocks(A);
@@ -989,6 +1048,8 @@ void h2_free(h2_matrix A) {
     if (p) (void)hipFree(p);
   if (A->d_plan) (void)hipFree(A->d_plan);
   A->prof.release();
+  if (A->d_more) (void)hipFree(A->d_more);
+  if (A->h_more) (void)hipHostFree(A->h_more);
   if (A->own_stream) (void)hipStreamDestroy(A->own_stream);
   delete A;
 }

@@ -192,17 +192,24 @@ __device__ inline void argmax_reduce(double* sv, int* si, int tid, int nthr) {
 }
 
 // ----------------------------------------------------------- recompression
-// Rank-revealing QR of the concatenated fill-in products of cluster i (Sec. 3.4),
-// in three steps:
-//   k_pchol: pivoted Cholesky of their Gram G = X X^T (pivot = largest remaining
-//            squared row norm of X, first index on ties; stop when <= tau^2); its
-//            t columns L (original row order) span the kept directions, exactly the
-//            first t columns of P R^T of the column-pivoted QR of X^T;
-//   k_hqr:   Householder QR of L with reflector k acting on rows 0..R-1-k, so that
-//            W = H_0 ... H_{t-1} = I - Y T Y^T maps the kept directions onto the last
-//            t redundant coordinates; T is the compact-WY factor;
-//   two MFMA GEMMs form W = I - (Y T) Y^T.
+// Rank-revealing QR of the concatenated fill-in products of cluster i (Sec. 3.4):
+//  * pivoted Cholesky of their Gram G = X X^T (pivot = largest remaining squared
+//    row norm of X, first index on ties; stop when <= tau^2).  Its t columns L
+//    (original row order) span the kept directions: they are the first t columns
+//    of P R^T of the column-pivoted QR of X^T.  Blocked: a panel of PC_NB pivots
+//    per step (k_pchol_panel), then G -= L_p L_p^T on the matrix cores;
+//  * Householder QR of L with reflector k acting on rows 0..R-1-k, so that
+//    W = H_0 ... H_{t-1} maps the kept directions onto the last t redundant
+//    coordinates.  Blocked: a panel of HB columns (k_hqr_panel, which also forms
+//    T_p and Y_p T_p^T), then the trailing columns receive
+//    V <- V - (Y_p T_p^T)(Y_p^T V) on the matrix cores;
+//  * W = prod_p (I - Y_p T_p Y_p^T), accumulated panel by panel with GEMMs.
+// Per-cluster panel state: a0 = panel start, a1 = panel width; the scratch
+// B_Z holds the remaining diagonal (column 0) during the Cholesky and the
+// columns Y_p T_p^T during the QR.
 constexpr int RT_THREADS = 256;
+constexpr int PC_NB = 32;
+constexpr int HB = 32;
 
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -219,37 +226,54 @@ __device__ inline double block_sum(double v, double* red, int tid) {
   return r;
 }
 
-__global__ __launch_bounds__(RT_THREADS) void k_pchol(const int* __restrict__ clusters, BufTab bt, SizeTab sz,
-                                                      double tau2) {
-  extern __shared__ double sh[];
+__global__ void k_pchol_init(const int* __restrict__ clusters, BufTab bt, SizeTab sz) {
   const int s = blockIdx.z;
   const int i = clusters[blockIdx.y];
   const int N = sz.N;
   const int R = sz.R[s * N + i];
+  const int ld = bt.ld[B_G];
+  const double* G = addr(bt, B_G, i, s, 0, 0);
+  double* d = addr(bt, B_Z, i, s, 0, 0);
+  for (int a = threadIdx.x; a < R; a += blockDim.x) d[a] = G[a + (int64_t)a * ld];
+  if (threadIdx.x == 0) {
+    sz.t[s * N + i] = 0;
+    sz.a0[s * N + i] = 0;
+    sz.a1[s * N + i] = R > 0 ? 1 : 0;   // a1 = 1 while the Cholesky runs
+  }
+}
+
+// One panel of at most PC_NB pivots.  G holds the Gram updated by all previous
+// panels; columns of this panel are formed from G and the panel's own columns.
+__global__ __launch_bounds__(RT_THREADS) void k_pchol_panel(const int* __restrict__ clusters, BufTab bt, SizeTab sz,
+                                                            double tau2, int* __restrict__ more) {
+  extern __shared__ double sh[];
+  const int s = blockIdx.z;
+  const int i = clusters[blockIdx.y];
+  const int N = sz.N;
   const int tid = threadIdx.x;
+  if (sz.a1[s * N + i] == 0) {                // finished: no new columns for the update
+    if (tid == 0) sz.a0[s * N + i] = sz.t[s * N + i];
+    return;
+  }
+  const int R = sz.R[s * N + i];
   const int ld = bt.ld[B_G];
   const double* G = addr(bt, B_G, i, s, 0, 0);
   double* V = addr(bt, B_V, i, s, 0, 0);
-  const int cap = ld;
-  double* d = sh;                       // remaining diagonal [cap]
-  double* red = sh + cap;               // [RT_THREADS]
-  int* redi = (int*)(red + RT_THREADS); // [RT_THREADS]
-  char* used = (char*)(redi + RT_THREADS);
-  if (R <= 0) {
-    if (tid == 0) sz.t[s * N + i] = 0;
-    return;
-  }
-  for (int a = tid; a < R; a += RT_THREADS) {
-    d[a] = G[a + (int64_t)a * ld];
-    used[a] = 0;
-  }
+  double* dg = addr(bt, B_Z, i, s, 0, 0);
+  double* d = sh;                             // [cap]
+  double* red = sh + ld;                      // [RT_THREADS]
+  int* redi = (int*)(red + RT_THREADS);       // [RT_THREADS]
+  __shared__ int s_stop;
+  for (int a = tid; a < R; a += RT_THREADS) d[a] = dg[a];
+  if (tid == 0) s_stop = 0;
   __syncthreads();
-  int t = 0;
-  while (t < R) {
-    double bv = -1.0;
+  const int t0 = sz.t[s * N + i];
+  int t = t0;
+  for (int j = 0; j < PC_NB && t < R; ++j) {
+    double bv = -INFINITY;
     int bi = R;
     for (int a = tid; a < R; a += RT_THREADS)
-      if (!used[a] && (d[a] > bv || (d[a] == bv && a < bi))) { bv = d[a]; bi = a; }
+      if (d[a] > bv || (d[a] == bv && a < bi)) { bv = d[a]; bi = a; }
     red[tid] = bv;
     redi[tid] = bi;
     __syncthreads();
@@ -257,209 +281,160 @@ __global__ __launch_bounds__(RT_THREADS) void k_pchol(const int* __restrict__ cl
     const double dmax = red[0];
     const int p = redi[0];
     __syncthreads();
-    if (!(dmax > tau2)) break;
+    if (!(dmax > tau2)) {
+      if (tid == 0) s_stop = 1;
+      break;
+    }
     const double sq = sqrt(dmax), inv = 1.0 / sq;
     for (int a = tid; a < R; a += RT_THREADS) {
       double v = 0.0;
       if (a == p) v = sq;
-      else if (!used[a]) {
+      else if (d[a] != -INFINITY) {
         v = G[a + (int64_t)p * ld];
-        for (int l = 0; l < t; ++l) v -= V[a + (int64_t)l * ld] * V[p + (int64_t)l * ld];
+        for (int l = t0; l < t; ++l) v -= V[a + (int64_t)l * ld] * V[p + (int64_t)l * ld];
         v *= inv;
         d[a] -= v * v;
       }
       V[a + (int64_t)t * ld] = v;
     }
-    if (tid == 0) used[p] = 1;
+    __syncthreads();
+    if (tid == 0) d[p] = -INFINITY;
     __syncthreads();
     ++t;
   }
+  for (int a = tid; a < R; a += RT_THREADS) dg[a] = d[a];
   if (tid == 0) {
     sz.t[s * N + i] = t;
+    sz.a0[s * N + i] = t0;
+    const bool go = !s_stop && t < R;
+    sz.a1[s * N + i] = go ? 1 : 0;
+    if (go) atomicAdd(more, 1);
+  }
+}
+
+__global__ void k_pchol_finish(const int* __restrict__ clusters, BufTab bt, SizeTab sz) {
+  const int s = blockIdx.z;
+  const int i = clusters[blockIdx.y];
+  const int N = sz.N;
+  if (threadIdx.x == 0) {
+    const int R = sz.R[s * N + i], t = sz.t[s * N + i];
     sz.R[s * N + i] = R - t;
     if (bt.fc) atomicAdd(bt.fc, (unsigned long long)R * (unsigned long long)t * (unsigned long long)(t > 0 ? t - 1 : 0));
   }
 }
 
-// Blocked Householder QR of L (RT x t, in B_V) with reflector k anchored at row
-// RT-1-k.  Panels of HQR_NB columns are factored column by column; the trailing
-// columns then receive the panel's reflectors at once in compact-WY form,
-// V <- V - Y_p T_p^T (Y_p^T V), on the matrix cores.  On exit B_V holds the
-// reflectors Y (zero below each anchor) and sh-beta is written to beta_out.
-constexpr int HQR_NB = 16;
-
-__global__ __launch_bounds__(RT_THREADS) void k_hqr(const int* __restrict__ clusters, BufTab bt, SizeTab sz) {
+// Panel `it` of the Householder QR: columns k0 = it*HB .. k0+nb-1 of V (RT x t).
+__global__ __launch_bounds__(RT_THREADS) void k_hqr_panel(const int* __restrict__ clusters, BufTab bt, SizeTab sz, int it,
+                                                          int* __restrict__ more) {
   extern __shared__ double sh[];
   const int s = blockIdx.z;
   const int i = clusters[blockIdx.y];
   const int N = sz.N;
   const int t = sz.t[s * N + i];
-  if (t == 0) return;
-  const int RT = sz.R[s * N + i] + t;
+  const int k0 = it * HB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (bt.fc && tid == 0) {
-    double f = 2.0 * RT * (double)t * t - 2.0 / 3.0 * (double)t * t * t;
-    atomicAdd(bt.fc, (unsigned long long)(f > 0 ? f : 0));
+  if (k0 >= t) {
+    if (tid == 0) { sz.a0[s * N + i] = k0; sz.a1[s * N + i] = 0; }
+    return;
+  }
+  const int nb = min(HB, t - k0);
+  const int RT = sz.R[s * N + i] + t;
+  if (bt.fc && tid == 0) {   // Householder QR flops of this panel's columns
+    double f = 0.0;
+    for (int k = k0; k < k0 + nb; ++k) f += 4.0 * (double)(RT - k) * (double)(t - k);
+    atomicAdd(bt.fc, (unsigned long long)f);
   }
   const int ld = bt.ld[B_V];
   double* V = addr(bt, B_V, i, s, 0, 0);
-  double* beta_out = addr(bt, B_G, i, s, 0, 0) + (int64_t)(ld - 1) * ld;   // last column of B_G
-  double* Zs = addr(bt, B_Z, i, s, 0, 0);                                  // HQR_NB x t scratch (ld)
-  double* red = sh;                          // [8]
-  double* wd = sh + 8;                       // [HQR_NB]
-  double* Tp = sh + 8 + HQR_NB;              // [HQR_NB * HQR_NB]
-  double* bp = Tp + HQR_NB * HQR_NB;         // [HQR_NB]
-  for (int k0 = 0; k0 < t; k0 += HQR_NB) {
-    const int nb = min(HQR_NB, t - k0);
-    // ---- panel: columns k0 .. k0+nb-1
-    for (int kk = 0; kk < nb; ++kk) {
-      const int k = k0 + kk;
-      const int p = RT - 1 - k;
-      double part = 0.0;
-      for (int a = tid; a <= p; a += RT_THREADS) {
-        double x = V[a + (int64_t)k * ld];
-        part += x * x;
-      }
-      const double xn2 = block_sum(part, red, tid);
-      const double x0 = V[p + (int64_t)k * ld];
-      const double xn = sqrt(xn2);
-      const double alpha = -copysign(xn, x0 != 0.0 ? x0 : 1.0);
-      const double v0 = x0 - alpha;
-      const double vn = xn2 - x0 * x0 + v0 * v0;
-      const double bk = vn > 0.0 ? 2.0 / vn : 0.0;
-      __syncthreads();
-      if (tid == 0) {
-        V[p + (int64_t)k * ld] = v0;
-        bp[kk] = bk;
-        beta_out[k] = bk;
-      }
-      __syncthreads();
-      for (int j = k + 1 + wave; j < k0 + nb; j += RT_THREADS / 64) {
-        double q = 0.0;
-        for (int a = lane; a <= p; a += 64) q += V[a + (int64_t)k * ld] * V[a + (int64_t)j * ld];
-        q = wave_sum(q);
-        if (lane == 0) wd[j - k0] = q * bk;
-      }
-      __syncthreads();
-      const int nj = k0 + nb - k - 1, nr = p + 1;
-      for (int64_t e = tid; e < (int64_t)nj * nr; e += RT_THREADS) {
-        int a = (int)(e % nr), j = k + 1 + (int)(e / nr);
-        V[a + (int64_t)j * ld] -= V[a + (int64_t)k * ld] * wd[j - k0];
-      }
-      __syncthreads();
+  double* Yt = addr(bt, B_Z, i, s, 0, 0);
+  double* red = sh;                 // [8]
+  double* wd = sh + 8;              // [HB]
+  double* Tp = sh + 8 + HB;         // [HB * HB]
+  double* bp = Tp + HB * HB;        // [HB]
+  for (int kk = 0; kk < nb; ++kk) {
+    const int k = k0 + kk;
+    const int p = RT - 1 - k;
+    double part = 0.0;
+    for (int a = tid; a <= p; a += RT_THREADS) {
+      double x = V[a + (int64_t)k * ld];
+      part += x * x;
     }
-    // zero the panel's reflectors below their anchors (those rows hold R entries)
-    for (int64_t e = tid; e < (int64_t)nb * RT; e += RT_THREADS) {
-      int a = (int)(e % RT), kk = (int)(e / RT);
-      if (a > RT - 1 - (k0 + kk)) V[a + (int64_t)(k0 + kk) * ld] = 0.0;
+    const double xn2 = block_sum(part, red, tid);
+    const double x0 = V[p + (int64_t)k * ld];
+    const double xn = sqrt(xn2);
+    const double alpha = -copysign(xn, x0 != 0.0 ? x0 : 1.0);
+    const double v0 = x0 - alpha;
+    const double vn = xn2 - x0 * x0 + v0 * v0;
+    const double bk = vn > 0.0 ? 2.0 / vn : 0.0;
+    __syncthreads();
+    if (tid == 0) {
+      V[p + (int64_t)k * ld] = v0;
+      bp[kk] = bk;
     }
     __syncthreads();
-    const int nt = t - k0 - nb;
-    if (nt <= 0) continue;
-    // ---- T_p of the panel: T_kk = beta_k, T[0:kk, kk] = -beta_k T[0:kk, 0:kk] (Y_p^T y_kk)
-    for (int e = tid; e < nb * nb; e += RT_THREADS) Tp[e] = 0.0;
-    __syncthreads();
-    for (int kk = 0; kk < nb; ++kk) {
-      const int p = RT - 1 - (k0 + kk);
-      for (int j = wave; j < kk; j += RT_THREADS / 64) {
-        double q = 0.0;
-        for (int a = lane; a <= p; a += 64) q += V[a + (int64_t)(k0 + j) * ld] * V[a + (int64_t)(k0 + kk) * ld];
-        q = wave_sum(q);
-        if (lane == 0) wd[j] = q;
-      }
-      __syncthreads();
-      if (tid < kk) {
-        double v = 0.0;
-        for (int b = tid; b < kk; ++b) v += Tp[tid + b * HQR_NB] * wd[b];
-        Tp[tid + kk * HQR_NB] = -bp[kk] * v;
-      } else if (tid == kk) {
-        Tp[kk + kk * HQR_NB] = bp[kk];
-      }
-      __syncthreads();
-    }
-    // ---- trailing update, columns c in [k0+nb, t):
-    // Z = Y_p^T V_trail (nb x nt) ; Z <- T_p^T Z ; V_trail -= Y_p Z
-    const int rows = RT - k0;   // reflectors of the panel live in rows 0 .. RT-1-k0
-    for (int cc = wave; cc < nt; cc += RT_THREADS / 64) {
-      const int c = k0 + nb + cc;
-      for (int kk = 0; kk < nb; ++kk) {
-        double q = 0.0;
-        for (int a = lane; a < rows; a += 64) q += V[a + (int64_t)(k0 + kk) * ld] * V[a + (int64_t)c * ld];
-        q = wave_sum(q);
-        if (lane == 0) Zs[kk + (int64_t)cc * ld] = q;
-      }
+    for (int j = k + 1 + wave; j < k0 + nb; j += RT_THREADS / 64) {
+      double q = 0.0;
+      for (int a = lane; a <= p; a += 64) q += V[a + (int64_t)k * ld] * V[a + (int64_t)j * ld];
+      q = wave_sum(q);
+      if (lane == 0) wd[j - k0] = q * bk;
     }
     __syncthreads();
-    for (int cc = tid; cc < nt; cc += RT_THREADS) {
-      double z[HQR_NB];
-      for (int kk = 0; kk < nb; ++kk) z[kk] = Zs[kk + (int64_t)cc * ld];
-      for (int kk = 0; kk < nb; ++kk) {
-        double v = 0.0;
-        for (int b = 0; b <= kk; ++b) v += Tp[b + kk * HQR_NB] * z[b];   // (T_p^T z)_kk
-        Zs[kk + (int64_t)cc * ld] = v;
-      }
-    }
-    __syncthreads();
-    // V_trail[a, c] -= sum_kk Y[a, kk] Z[kk, c]: MFMA tiles of 32 x 32 per wave
-    {
-      const int tr = (rows + 31) / 32, tc = (nt + 31) / 32;
-      for (int tile = wave; tile < tr * tc; tile += RT_THREADS / 64) {
-        const int r0 = (tile % tr) * 32, c0 = (tile / tr) * 32;
-        v4d acc[2][2];
-        for (int x = 0; x < 2; ++x)
-          for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
-        for (int kb = 0; kb < nb; kb += 4) {
-          const int kc = kb + (lane >> 4);
-          double av[2], bv[2];
-          for (int x = 0; x < 2; ++x) {
-            int r = r0 + x * 16 + (lane & 15);
-            av[x] = (kc < nb && r < rows) ? V[r + (int64_t)(k0 + kc) * ld] : 0.0;
-            int c = c0 + x * 16 + (lane & 15);
-            bv[x] = (kc < nb && c < nt) ? Zs[kc + (int64_t)c * ld] : 0.0;
-          }
-          for (int x = 0; x < 2; ++x)
-            for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
-        }
-        for (int x = 0; x < 2; ++x)
-          for (int y = 0; y < 2; ++y)
-            for (int v = 0; v < 4; ++v) {
-              int r = r0 + x * 16 + (lane >> 4) + 4 * v;
-              int c = c0 + y * 16 + (lane & 15);
-              if (r < rows && c < nt) V[r + (int64_t)(k0 + nb + c) * ld] -= acc[x][y][v];
-            }
-      }
+    const int nj = k0 + nb - k - 1, nr = p + 1;
+    for (int64_t e = tid; e < (int64_t)nj * nr; e += RT_THREADS) {
+      int a = (int)(e % nr), j = k + 1 + (int)(e / nr);
+      V[a + (int64_t)j * ld] -= V[a + (int64_t)k * ld] * wd[j - k0];
     }
     __syncthreads();
   }
-}
-
-// T (t x t, upper) of W = H_0 ... H_{t-1} = I - Y T Y^T from YtY = Y^T Y (in B_W)
-// and the scalars beta (last column of B_G): T_kk = beta_k,
-// T[0:k, k] = -beta_k T[0:k, 0:k] YtY[0:k, k].  Written to B_G[0:t, 0:t].
-__global__ __launch_bounds__(RT_THREADS) void k_tmat(const int* __restrict__ clusters, BufTab bt, SizeTab sz) {
-  const int s = blockIdx.z;
-  const int i = clusters[blockIdx.y];
-  const int t = sz.t[s * sz.N + i];
-  if (t == 0) return;
-  const int tid = threadIdx.x;
-  if (bt.fc && tid == 0) atomicAdd(bt.fc, (unsigned long long)((double)t * t * t / 3.0));
-  const int ld = bt.ld[B_G];
-  double* Tm = addr(bt, B_G, i, s, 0, 0);
-  const double* beta = Tm + (int64_t)(ld - 1) * ld;
-  const double* YtY = addr(bt, B_W, i, s, 0, 0);
-  const int ldy = bt.ld[B_W];
-  for (int k = 0; k < t; ++k) {
-    for (int a = tid; a < t; a += RT_THREADS) {
-      double v = 0.0;
-      if (a < k) {
-        for (int b = a; b < k; ++b) v += Tm[a + (int64_t)b * ld] * YtY[b + (int64_t)k * ldy];
-        v *= -beta[k];
-      } else if (a == k) {
-        v = beta[k];
-      }
-      Tm[a + (int64_t)k * ld] = v;
+  // reflectors of the panel: zero below their anchors (those rows hold R entries)
+  for (int64_t e = tid; e < (int64_t)nb * RT; e += RT_THREADS) {
+    int a = (int)(e % RT), kk = (int)(e / RT);
+    if (a > RT - 1 - (k0 + kk)) V[a + (int64_t)(k0 + kk) * ld] = 0.0;
+  }
+  for (int e = tid; e < HB * HB; e += RT_THREADS) Tp[e] = 0.0;
+  __syncthreads();
+  // T_p: T_kk = beta_k, T[0:kk, kk] = -beta_kk T[0:kk, 0:kk] (Y_p^T y_kk)
+  for (int kk = 0; kk < nb; ++kk) {
+    const int p = RT - 1 - (k0 + kk);
+    for (int j = wave; j < kk; j += RT_THREADS / 64) {
+      double q = 0.0;
+      for (int a = lane; a <= p; a += 64) q += V[a + (int64_t)(k0 + j) * ld] * V[a + (int64_t)(k0 + kk) * ld];
+      q = wave_sum(q);
+      if (lane == 0) wd[j] = q;
     }
     __syncthreads();
+    if (tid < kk) {
+      double v = 0.0;
+      for (int b2 = tid; b2 < kk; ++b2) v += Tp[tid + b2 * HB] * wd[b2];
+      Tp[tid + kk * HB] = -bp[kk] * v;
+    } else if (tid == kk) {
+      Tp[kk + kk * HB] = bp[kk];
+    }
+    __syncthreads();
+  }
+  // Yt = Y_p T_p^T  (RT x nb) into B_Z columns k0 .. k0+nb-1
+  for (int64_t e = tid; e < (int64_t)nb * RT; e += RT_THREADS) {
+    int a = (int)(e % RT), c = (int)(e / RT);
+    double v = 0.0;
+    for (int b2 = c; b2 < nb; ++b2) v += V[a + (int64_t)(k0 + b2) * ld] * Tp[c + b2 * HB];   // T^T[b2][c] = T[c][b2]
+    Yt[a + (int64_t)(k0 + c) * ld] = v;
+  }
+  if (tid == 0) {
+    sz.a0[s * N + i] = k0;
+    sz.a1[s * N + i] = nb;
+    if (k0 + nb < t) atomicAdd(more, 1);
+  }
+}
+
+// panel state of step `it` for the accumulation of W (a0 = it*HB, a1 = panel width)
+__global__ void k_set_panel(const int* __restrict__ clusters, SizeTab sz, int it) {
+  const int s = blockIdx.z;
+  const int i = clusters[blockIdx.y];
+  const int N = sz.N;
+  if (threadIdx.x == 0) {
+    const int t = sz.t[s * N + i], k0 = it * HB;
+    sz.a0[s * N + i] = k0;
+    sz.a1[s * N + i] = k0 < t ? min(HB, t - k0) : 0;
   }
 }
 
@@ -478,56 +453,20 @@ __global__ void k_eye(const int* __restrict__ clusters, BufTab bt, SizeTab sz) {
   }
 }
 
-// ---------------------------------------------------------------- rotation
-// side 0: rows [0, RT) of the block <- W^T rows ; side 1: cols [0, RT) <- cols W.
-static inline int strip_for(int cap) { return std::max(1, std::min(16, 65536 / (cap * 8))); }
-
-__global__ __launch_bounds__(256) void k_rotate(const RotItem* __restrict__ items, BufTab bt, SizeTab sz, int STRIP) {
-  extern __shared__ double sh[];
-  const int s = blockIdx.z;
-  const RotItem it = items[blockIdx.y];
-  const int N = sz.N;
-  const int t = sz.t[s * N + it.cluster];
-  if (t == 0) return;
-  const int RT = sz.R[s * N + it.cluster] + t;
-  const int other = dev_eval(it.other, sz, s);
-  const int o0 = blockIdx.x * STRIP;
-  if (o0 >= other) return;
-  const int no = min(STRIP, other - o0);
-  const double* W = addr(bt, B_W, it.cluster, s, 0, 0);
-  const int ldw = bt.ld[B_W];
-  double* X = addr(bt, it.buf, it.blk, s, 0, 0);
-  const int ldx = bt.ld[it.buf];
-  const int tid = threadIdx.x;
-  // load strip: RT x no (side 0: rows 0..RT, cols o0..; side 1: cols 0..RT, rows o0..)
-  for (int e = tid; e < RT * no; e += 256) {
-    int a = e % RT, o = e / RT;
-    sh[a + o * RT] = it.side == 0 ? X[a + (int64_t)(o0 + o) * ldx] : X[(o0 + o) + (int64_t)a * ldx];
-  }
-  __syncthreads();
-  for (int e = tid; e < RT * no; e += 256) {
-    int a = e % RT, o = e / RT;
-    const double* wc = W + (int64_t)a * ldw;   // column a of W
-    const double* xs = sh + o * RT;
-    double acc = 0.0;
-    for (int b = 0; b < RT; ++b) acc += wc[b] * xs[b];
-    if (it.side == 0) X[a + (int64_t)(o0 + o) * ldx] = acc;
-    else X[(o0 + o) + (int64_t)a * ldx] = acc;
-  }
-}
-
 // ------------------------------------------------------- pivot-block LDL^T
 // Bunch-Kaufman (partial pivoting, alpha = (1+sqrt(17))/8) on the redundant
 // block P = S_ii^{RR} (Eq. blr2-diag-ldl), in place, full storage, blocked: a
-// panel of up to LDL_NB columns is factored lazily (columns are brought up to
-// date from the panel's L and W = L D columns only when needed), then the
-// trailing matrix receives one rank-(panel) update L W^T on the matrix cores.
-// With P[perm, perm] = L D L^T and D = J Lambda J^T (2x2 blocks diagonalised by a
-// Jacobi rotation), the elimination operator K = Pi L^{-T} J |Lambda|^{-1/2} and
-// the signs sgn(Lambda) let every later step use the scaled generators
-// Y~ = B K (Eq. blr2-diag-elimination) and S -= Y~ diag(sgn) Y~^T
-// (Eq. blr2-diag-schur).  The number of negative entries of Lambda is added to
-// nu (Sylvester's law of inertia).
+// panel of up to LDL_NB columns is factored lazily by one workgroup
+// (k_ldl_panel: columns are brought up to date from the panel's L and
+// W = L D columns only when needed), then the trailing matrix receives
+// A -= L_p W_p^T on the matrix cores.  With P[perm, perm] = L D L^T and
+// D = J Lambda J^T (2x2 blocks diagonalised by a Jacobi rotation), k_ldl_finish
+// forms the elimination operator K = Pi L^{-T} J |Lambda|^{-1/2} and the signs
+// sgn(Lambda): every later step uses the scaled generators Y~ = B K
+// (Eq. blr2-diag-elimination) and S -= Y~ diag(sgn) Y~^T (Eq. blr2-diag-schur).
+// The number of negative entries of Lambda is added to nu (Sylvester's law).
+// State: a0 = panel start, a1 = panel width, perm and pivot sizes in B_Z
+// columns 0 and 1, the panel's W columns in B_W.
 constexpr int LDL_THREADS = 512;
 constexpr int LDL_NB = 32;
 
@@ -565,10 +504,166 @@ __device__ inline double block_argmax512(const double* x, int lo, int R, double*
   return r;
 }
 
-__global__ __launch_bounds__(LDL_THREADS) void k_ldl(const int* __restrict__ clusters, const int* __restrict__ diag_blk,
-                                                     BufTab bt, SizeTab sz, unsigned long long* __restrict__ nu,
-                                                     int* __restrict__ status) {
-  extern __shared__ double sh[];
+__global__ void k_ldl_init(const int* __restrict__ clusters, BufTab bt, SizeTab sz) {
+  const int s = blockIdx.z;
+  const int i = clusters[blockIdx.y];
+  const int N = sz.N;
+  const int R = sz.R[s * N + i];
+  double* pz = addr(bt, B_Z, i, s, 0, 0);
+  const int ld = bt.ld[B_Z];
+  for (int a = threadIdx.x; a < R; a += blockDim.x) {
+    pz[a] = (double)a;              // perm
+    pz[a + ld] = 0.0;               // pivot size
+  }
+  if (threadIdx.x == 0) {
+    sz.a0[s * N + i] = 0;
+    sz.a1[s * N + i] = 0;
+  }
+}
+
+__global__ __launch_bounds__(LDL_THREADS) void k_ldl_panel(const int* __restrict__ clusters,
+                                                           const int* __restrict__ diag_blk, BufTab bt, SizeTab sz,
+                                                           int* __restrict__ status, int* __restrict__ more) {
+  const int s = blockIdx.z;
+  const int i = clusters[blockIdx.y];
+  const int N = sz.N;
+  const int R = sz.R[s * N + i];
+  const int tid = threadIdx.x;
+  const int kstart = sz.a0[s * N + i] + sz.a1[s * N + i];
+  if (kstart >= R) {
+    if (tid == 0) { sz.a0[s * N + i] = kstart; sz.a1[s * N + i] = 0; }
+    return;
+  }
+  const int ld = bt.ld[B_S];
+  double* A = addr(bt, B_S, diag_blk[i], s, 0, 0);
+  double* Wp = addr(bt, B_W, i, s, 0, 0);     // panel W = L D columns, LDL_NB + 2 columns
+  double* pz = addr(bt, B_Z, i, s, 0, 0);     // perm (col 0), pivot sizes (col 1)
+  const int cap = ld;
+  __shared__ double red[16];
+  __shared__ int redi[16];
+  __shared__ int s_bad;
+  const double alpha = (1.0 + sqrt(17.0)) / 8.0;
+  const int NB = min(LDL_NB, cap - 2);
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  const int k0 = kstart;
+  int k = k0, jw = 0;
+  while (jw < NB && k < R) {
+    double* w = Wp + (int64_t)jw * ld;
+    double* u = Wp + (int64_t)(jw + 1) * ld;
+    for (int a = k + tid; a < R; a += LDL_THREADS) {
+      double v = A[a + (int64_t)k * ld];
+      for (int c = 0; c < jw; ++c) v -= A[a + (int64_t)(k0 + c) * ld] * Wp[k + (int64_t)c * ld];
+      w[a] = v;
+    }
+    __syncthreads();
+    int imax = R;
+    const double colmax0 = block_argmax512(w, k + 1, R, red, redi, tid, &imax);
+    const double colmax = colmax0 < 0.0 ? 0.0 : colmax0;
+    const double absakk = fabs(w[k]);
+    int kind = 1, kp = k;
+    bool use_u = false;
+    if (fmax(absakk, colmax) == 0.0 || !(absakk == absakk)) {
+      if (tid == 0) s_bad = 1;
+    } else if (absakk < alpha * colmax) {
+      for (int a = k + tid; a < R; a += LDL_THREADS) {
+        double v = A[a + (int64_t)imax * ld];
+        for (int c = 0; c < jw; ++c) v -= A[a + (int64_t)(k0 + c) * ld] * Wp[imax + (int64_t)c * ld];
+        u[a] = v;
+      }
+      __syncthreads();
+      double rv = 0.0;
+      for (int a = k + tid; a < R; a += LDL_THREADS)
+        if (a != imax) rv = fmax(rv, fabs(u[a]));
+      const double rowmax = block_max512(rv, red, tid);
+      if (absakk >= alpha * colmax * (colmax / rowmax)) {
+        kind = 1; kp = k;
+      } else if (fabs(u[imax]) >= alpha * rowmax) {
+        kind = 1; kp = imax; use_u = true;
+      } else {
+        kind = 2; kp = imax;
+      }
+    }
+    const int kk = (kind == 2) ? k + 1 : k;
+    __syncthreads();
+    if (use_u) {
+      for (int a = k + tid; a < R; a += LDL_THREADS) w[a] = u[a];
+      __syncthreads();
+    }
+    if (kp != kk) {
+      for (int j = tid; j < R; j += LDL_THREADS) {
+        double x = A[kk + (int64_t)j * ld];
+        A[kk + (int64_t)j * ld] = A[kp + (int64_t)j * ld];
+        A[kp + (int64_t)j * ld] = x;
+      }
+      for (int c = tid; c < jw + 2; c += LDL_THREADS) {
+        double x = Wp[kk + (int64_t)c * ld];
+        Wp[kk + (int64_t)c * ld] = Wp[kp + (int64_t)c * ld];
+        Wp[kp + (int64_t)c * ld] = x;
+      }
+      __syncthreads();
+      for (int a = tid; a < R; a += LDL_THREADS) {
+        double x = A[a + (int64_t)kk * ld];
+        A[a + (int64_t)kk * ld] = A[a + (int64_t)kp * ld];
+        A[a + (int64_t)kp * ld] = x;
+      }
+      if (tid == 0) {
+        double x = pz[kk];
+        pz[kk] = pz[kp];
+        pz[kp] = x;
+      }
+      __syncthreads();
+    }
+    if (kind == 1) {
+      const double dk = w[k];
+      const double inv = dk != 0.0 ? 1.0 / dk : 0.0;
+      for (int a = k + 1 + tid; a < R; a += LDL_THREADS) A[a + (int64_t)k * ld] = w[a] * inv;
+      if (tid == 0) {
+        A[k + (int64_t)k * ld] = dk;
+        pz[k + ld] = 1.0;
+      }
+      __syncthreads();
+      k += 1;
+      jw += 1;
+    } else {
+      const double a11 = w[k], a21 = w[k + 1], a22 = u[k + 1];
+      const double det = a11 * a22 - a21 * a21;
+      if (tid == 0 && !(det != 0.0 && det == det)) s_bad = 1;
+      const double idet = det != 0.0 ? 1.0 / det : 0.0;
+      for (int a = k + 2 + tid; a < R; a += LDL_THREADS) {
+        double x1 = w[a], x2 = u[a];
+        A[a + (int64_t)k * ld] = (x1 * a22 - x2 * a21) * idet;
+        A[a + (int64_t)(k + 1) * ld] = (x2 * a11 - x1 * a21) * idet;
+      }
+      if (tid == 0) {
+        A[k + (int64_t)k * ld] = a11;
+        A[k + 1 + (int64_t)k * ld] = a21;
+        A[k + 1 + (int64_t)(k + 1) * ld] = a22;
+        pz[k + ld] = 2.0;
+        pz[k + 1 + ld] = 0.0;
+      }
+      __syncthreads();
+      k += 2;
+      jw += 2;
+    }
+  }
+  if (tid == 0) {
+    sz.a0[s * N + i] = k0;
+    sz.a1[s * N + i] = jw;
+    if (s_bad) atomicOr(status + s, 1);
+    if (k < R) atomicAdd(more, 1);
+  }
+}
+
+// After the panels: pivot coefficients and inertia.  For every pivot column b,
+// K^T row b = cf1[b] * X[c1, :] + cf2[b] * X[c2, :] with X = L^{-1} and (c1, c2)
+// the columns of its 1x1 / 2x2 block; coefficients go to B_Z columns 2 and 3,
+// signs to B_SIGN; D's off-diagonal entries are cleared so that the strictly
+// lower part of A is exactly L.
+__global__ __launch_bounds__(LDL_THREADS) void k_ldl_prep(const int* __restrict__ clusters,
+                                                          const int* __restrict__ diag_blk, BufTab bt, SizeTab sz,
+                                                          unsigned long long* __restrict__ nu) {
+  __shared__ double red[16];
   const int s = blockIdx.z;
   const int i = clusters[blockIdx.y];
   const int N = sz.N;
@@ -577,187 +672,19 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl(const int* __restrict__ clu
   if (R <= 0) return;
   const int ld = bt.ld[B_S];
   double* A = addr(bt, B_S, diag_blk[i], s, 0, 0);
-  double* K = addr(bt, B_G, i, s, 0, 0);
-  double* Y = addr(bt, B_V, i, s, 0, 0);      // L^{-T} after the factorization
-  double* Wp = addr(bt, B_Z, i, s, 0, 0);     // panel workspace W = L D, ld, LDL_NB + 2 columns
+  double* pz = addr(bt, B_Z, i, s, 0, 0);
+  const int ldz = bt.ld[B_Z];
   double* sg = addr(bt, B_SIGN, 0, s, 0, 0) + (int64_t)i * bt.bs[B_SIGN];
-  const int cap = ld;
-  double* red = sh;                       // [16]
-  int* redi = (int*)(sh + 16);            // [16]
-  double* rowc = sh + 32;                 // [cap] row cache / coefficients
-  double* cf1 = rowc + cap;               // [cap]
-  double* cf2 = cf1 + cap;                // [cap]
-  int* perm = (int*)(cf2 + cap);          // [cap]
-  int* psz = perm + cap;                  // [cap] 1, 2 (first of a 2x2), 0 (second)
-  __shared__ int s_bad;
-  const double alpha = (1.0 + sqrt(17.0)) / 8.0;
-  const int NB = min(LDL_NB, cap - 2);    // the workspace holds NB + 2 columns
-  for (int a = tid; a < R; a += LDL_THREADS) perm[a] = a;
-  if (tid == 0) s_bad = 0;
-  __syncthreads();
-
-  int k = 0;
-  while (k < R) {
-    const int k0 = k;
-    int jw = 0;   // panel columns done
-    while (jw < NB && k < R) {
-      // w = column k of the up-to-date matrix, rows k..R-1 -> Wp[:, jw]
-      double* w = Wp + (int64_t)jw * ld;
-      double* u = Wp + (int64_t)(jw + 1) * ld;
-      for (int a = k + tid; a < R; a += LDL_THREADS) {
-        double v = A[a + (int64_t)k * ld];
-        for (int c = 0; c < jw; ++c) v -= A[a + (int64_t)(k0 + c) * ld] * Wp[k + (int64_t)c * ld];
-        w[a] = v;
-      }
-      __syncthreads();
-      int imax = R;
-      const double colmax0 = block_argmax512(w, k + 1, R, red, redi, tid, &imax);
-      const double colmax = colmax0 < 0.0 ? 0.0 : colmax0;
-      const double absakk = fabs(w[k]);
-      int kind = 1, kp = k;
-      bool use_u = false;
-      if (fmax(absakk, colmax) == 0.0 || !(absakk == absakk)) {
-        if (tid == 0) s_bad = 1;
-      } else if (absakk < alpha * colmax) {
-        // u = column imax of the up-to-date matrix, rows k..R-1
-        for (int a = k + tid; a < R; a += LDL_THREADS) {
-          double v = A[a + (int64_t)imax * ld];
-          for (int c = 0; c < jw; ++c) v -= A[a + (int64_t)(k0 + c) * ld] * Wp[imax + (int64_t)c * ld];
-          u[a] = v;
-        }
-        __syncthreads();
-        double rv = 0.0;
-        for (int a = k + tid; a < R; a += LDL_THREADS)
-          if (a != imax) rv = fmax(rv, fabs(u[a]));
-        const double rowmax = block_max512(rv, red, tid);
-        if (absakk >= alpha * colmax * (colmax / rowmax)) {
-          kind = 1; kp = k;
-        } else if (fabs(u[imax]) >= alpha * rowmax) {
-          kind = 1; kp = imax; use_u = true;
-        } else {
-          kind = 2; kp = imax;
-        }
-      }
-      const int kk = (kind == 2) ? k + 1 : k;
-      if (use_u) {
-        for (int a = k + tid; a < R; a += LDL_THREADS) w[a] = u[a];
-        __syncthreads();
-      }
-      if (kp != kk) {
-        // symmetric interchange kk <-> kp: full rows and columns of A, rows of Wp
-        for (int j = tid; j < R; j += LDL_THREADS) {
-          double x = A[kk + (int64_t)j * ld];
-          A[kk + (int64_t)j * ld] = A[kp + (int64_t)j * ld];
-          A[kp + (int64_t)j * ld] = x;
-        }
-        for (int c = tid; c < jw + 2; c += LDL_THREADS) {
-          double x = Wp[kk + (int64_t)c * ld];
-          Wp[kk + (int64_t)c * ld] = Wp[kp + (int64_t)c * ld];
-          Wp[kp + (int64_t)c * ld] = x;
-        }
-        __syncthreads();
-        for (int a = tid; a < R; a += LDL_THREADS) {
-          double x = A[a + (int64_t)kk * ld];
-          A[a + (int64_t)kk * ld] = A[a + (int64_t)kp * ld];
-          A[a + (int64_t)kp * ld] = x;
-        }
-        if (tid == 0) {
-          int x = perm[kk];
-          perm[kk] = perm[kp];
-          perm[kp] = x;
-        }
-        __syncthreads();
-      }
-      if (kind == 1) {
-        const double dk = w[k];
-        const double inv = dk != 0.0 ? 1.0 / dk : 0.0;
-        for (int a = k + 1 + tid; a < R; a += LDL_THREADS) A[a + (int64_t)k * ld] = w[a] * inv;
-        if (tid == 0) {
-          A[k + (int64_t)k * ld] = dk;
-          psz[k] = 1;
-        }
-        __syncthreads();
-        k += 1;
-        jw += 1;
-      } else {
-        // pivot columns (k, k+1) = (w, u) after the interchange; u is column k+1
-        const double a11 = w[k], a21 = w[k + 1], a22 = u[k + 1];
-        const double det = a11 * a22 - a21 * a21;
-        if (tid == 0 && !(det != 0.0 && det == det)) s_bad = 1;
-        const double idet = det != 0.0 ? 1.0 / det : 0.0;
-        for (int a = k + 2 + tid; a < R; a += LDL_THREADS) {
-          double x1 = w[a], x2 = u[a];
-          A[a + (int64_t)k * ld] = (x1 * a22 - x2 * a21) * idet;
-          A[a + (int64_t)(k + 1) * ld] = (x2 * a11 - x1 * a21) * idet;
-        }
-        if (tid == 0) {
-          A[k + (int64_t)k * ld] = a11;
-          A[k + 1 + (int64_t)k * ld] = a21;
-          A[k + 1 + (int64_t)(k + 1) * ld] = a22;
-          psz[k] = 2;
-          psz[k + 1] = 0;
-        }
-        __syncthreads();
-        k += 2;
-        jw += 2;
-      }
-    }
-    // trailing update A[k:R, k:R] -= Lp W^T, Lp = A[:, k0:k0+jw], W = Wp[:, 0:jw]
-    const int n2 = R - k;
-    if (n2 > 0) {
-      const int nt = (n2 + 31) / 32;
-      for (int tile = wave; tile < nt * nt; tile += LDL_THREADS / 64) {
-        const int r0 = k + (tile % nt) * 32, c0 = k + (tile / nt) * 32;
-        v4d acc[2][2];
-        for (int x = 0; x < 2; ++x)
-          for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
-        for (int kb = 0; kb < jw; kb += 4) {
-          const int kc = kb + (lane >> 4);
-          double av[2], bv[2];
-          for (int x = 0; x < 2; ++x) {
-            int r = r0 + x * 16 + (lane & 15);
-            av[x] = (kc < jw && r < R) ? A[r + (int64_t)(k0 + kc) * ld] : 0.0;
-            int c = c0 + x * 16 + (lane & 15);
-            bv[x] = (kc < jw && c < R) ? Wp[c + (int64_t)kc * ld] : 0.0;
-          }
-          for (int x = 0; x < 2; ++x)
-            for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
-        }
-        for (int x = 0; x < 2; ++x)
-          for (int y = 0; y < 2; ++y)
-            for (int v = 0; v < 4; ++v) {
-              int r = r0 + x * 16 + (lane >> 4) + 4 * v;
-              int c = c0 + y * 16 + (lane & 15);
-              if (r < R && c < R) A[r + (int64_t)c * ld] -= acc[x][y][v];
-            }
-      }
-      __syncthreads();
-    }
-  }
-
-  // Y = L^{-T}: row a of X = L^{-1} from rows b < a (forward substitution over rows),
-  // stored transposed, Y[j + a*ld] = X[a][j]; L_{k+1,k} = 0 inside a 2x2 block.
-  for (int a = 0; a < R; ++a) {
-    for (int b = tid; b < a; b += LDL_THREADS)
-      rowc[b] = (psz[b] == 2 && a == b + 1) ? 0.0 : A[a + (int64_t)b * ld];
-    __syncthreads();
-    for (int j = tid; j <= a; j += LDL_THREADS) {
-      double v = (j == a) ? 1.0 : 0.0;
-      for (int b = j; b < a; ++b) v -= rowc[b] * Y[j + (int64_t)b * ld];
-      Y[j + (int64_t)a * ld] = v;
-    }
-    __syncthreads();
-  }
-  // per column: K[:, b] = Y[:, c] cf1[b] + Y[:, c'] cf2[b] (J |Lambda|^{-1/2} mixing)
   int neg = 0;
   for (int b = tid; b < R; b += LDL_THREADS) {
-    if (psz[b] == 1) {
+    const int ps = (int)pz[b + ldz];
+    if (ps == 1) {
       const double dk = A[b + (int64_t)b * ld];
-      cf1[b] = (dk != 0.0 && dk == dk) ? 1.0 / sqrt(fabs(dk)) : 0.0;
-      cf2[b] = 0.0;
+      pz[b + 2 * ldz] = (dk != 0.0 && dk == dk) ? 1.0 / sqrt(fabs(dk)) : 0.0;
+      pz[b + 3 * ldz] = 0.0;
       sg[b] = dk < 0.0 ? -1.0 : 1.0;
       neg += dk < 0.0 ? 1 : 0;
-    } else if (psz[b] == 2) {
+    } else if (ps == 2) {
       const double a11 = A[b + (int64_t)b * ld], a21 = A[b + 1 + (int64_t)b * ld], a22 = A[b + 1 + (int64_t)(b + 1) * ld];
       double cs = 1.0, sn = 0.0;
       if (a21 != 0.0) {
@@ -771,26 +698,18 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl(const int* __restrict__ clu
       const double lam2 = sn * sn * a11 + 2.0 * cs * sn * a21 + cs * cs * a22;
       const double s1 = (lam1 != 0.0 && lam1 == lam1) ? 1.0 / sqrt(fabs(lam1)) : 0.0;
       const double s2 = (lam2 != 0.0 && lam2 == lam2) ? 1.0 / sqrt(fabs(lam2)) : 0.0;
-      cf1[b] = cs * s1;          // column b   = cs*s1*Y[:, b] - sn*s1*Y[:, b+1]
-      cf2[b] = -sn * s1;
-      cf1[b + 1] = sn * s2;      // column b+1 = sn*s2*Y[:, b] + cs*s2*Y[:, b+1]
-      cf2[b + 1] = cs * s2;
+      pz[b + 2 * ldz] = cs * s1;          // column b   = cs*s1*col(b) - sn*s1*col(b+1)
+      pz[b + 3 * ldz] = -sn * s1;
+      pz[b + 1 + 2 * ldz] = sn * s2;      // column b+1 = sn*s2*col(b) + cs*s2*col(b+1)
+      pz[b + 1 + 3 * ldz] = cs * s2;
       sg[b] = lam1 < 0.0 ? -1.0 : 1.0;
       sg[b + 1] = lam2 < 0.0 ? -1.0 : 1.0;
       neg += (lam1 < 0.0 ? 1 : 0) + (lam2 < 0.0 ? 1 : 0);
     }
   }
   __syncthreads();
-  for (int64_t e = tid; e < (int64_t)R * R; e += LDL_THREADS) {
-    const int a = (int)(e % R), b = (int)(e / R);
-    int c1i, c2i;
-    if (psz[b] == 0) { c1i = b - 1; c2i = b; }
-    else if (psz[b] == 2) { c1i = b; c2i = b + 1; }
-    else { c1i = b; c2i = -1; }
-    double v = (a <= c1i) ? Y[a + (int64_t)c1i * ld] * cf1[b] : 0.0;
-    if (c2i >= 0 && a <= c2i) v += Y[a + (int64_t)c2i * ld] * cf2[b];
-    K[perm[a] + (int64_t)b * ld] = v;
-  }
+  for (int b = tid; b < R; b += LDL_THREADS)
+    if ((int)pz[b + ldz] == 2) A[b + 1 + (int64_t)b * ld] = 0.0;
   double nv = (double)neg;
   for (int off = 32; off > 0; off >>= 1) nv += __shfl_xor(nv, off, 64);
   if (lane == 0) red[wave] = nv;
@@ -799,40 +718,79 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl(const int* __restrict__ clu
     double tot = 0.0;
     for (int w2 = 0; w2 < LDL_THREADS / 64; ++w2) tot += red[w2];
     atomicAdd(nu + s, (unsigned long long)(tot + 0.5));
-    if (s_bad) atomicOr(status + s, 1);
     if (bt.fc) atomicAdd(bt.fc, (unsigned long long)(2.0 / 3.0 * (double)R * R * R));
   }
 }
 
-// ------------------------------------------------------------ elimination
-// rows [row0, row0+nrows) x cols [0, R_i) of block (k, i) <- rows * K_i
-__global__ __launch_bounds__(256) void k_trsm(const TrsmItem* __restrict__ items, BufTab bt, SizeTab sz, int STRIP) {
-  extern __shared__ double sh[];
+// X = L^{-1} on the diagonal blocks of width INV_NB (unit lower L = strictly
+// lower part of A); block ib = blockIdx.x.  X lives in B_V (zeroed beforehand).
+constexpr int INV_NB = 128;
+
+__global__ void k_diag_inv(const int* __restrict__ clusters, const int* __restrict__ diag_blk, BufTab bt, SizeTab sz) {
   const int s = blockIdx.z;
-  const TrsmItem it = items[blockIdx.y];
-  const int Ri = sz.R[s * sz.N + it.cluster];
-  const int row0 = dev_eval(it.row0, sz, s), nrows = dev_eval(it.nrows, sz, s);
-  const int r0 = blockIdx.x * STRIP;
-  if (Ri <= 0 || r0 >= nrows) return;
-  const int nr = min(STRIP, nrows - r0);
+  const int i = clusters[blockIdx.y];
+  const int R = sz.R[s * sz.N + i];
+  const int r0 = blockIdx.x * INV_NB;
+  if (r0 >= R) return;
+  const int nb = min(INV_NB, R - r0);
   const int ld = bt.ld[B_S];
-  double* X = addr(bt, B_S, it.blk, s, row0 + r0, 0);
-  const double* K = addr(bt, B_G, it.cluster, s, 0, 0);
+  const double* A = addr(bt, B_S, diag_blk[i], s, 0, 0);
+  double* X = addr(bt, B_V, i, s, 0, 0);
+  const int ldx = bt.ld[B_V];
+  for (int c = threadIdx.x; c < nb; c += blockDim.x) {
+    const int gc = r0 + c;
+    X[gc + (int64_t)gc * ldx] = 1.0;
+    for (int a = c + 1; a < nb; ++a) {
+      const int ga = r0 + a;
+      double v = 0.0;
+      for (int b2 = c; b2 < a; ++b2) v -= A[ga + (int64_t)(r0 + b2) * ld] * X[r0 + b2 + (int64_t)gc * ldx];
+      X[ga + (int64_t)gc * ldx] = v;
+    }
+  }
+}
+
+// panel state for block row ib of the inversion: a0 = ib*INV_NB, a1 = its height (0 beyond R)
+__global__ void k_set_block(const int* __restrict__ clusters, SizeTab sz, int ib) {
+  const int s = blockIdx.z;
+  const int i = clusters[blockIdx.y];
+  const int N = sz.N;
+  if (threadIdx.x == 0) {
+    const int R = sz.R[s * N + i], a0 = ib * INV_NB;
+    sz.a0[s * N + i] = a0;
+    sz.a1[s * N + i] = a0 < R ? min(INV_NB, R - a0) : 0;
+  }
+}
+
+// K^T[b, perm[a]] = cf1[b] X[c1(b), a] + cf2[b] X[c2(b), a]  (K = Pi L^{-T} J |Lambda|^{-1/2})
+__global__ void k_kform(const int* __restrict__ clusters, BufTab bt, SizeTab sz) {
+  const int s = blockIdx.z;
+  const int i = clusters[blockIdx.y];
+  const int R = sz.R[s * sz.N + i];
+  const int ld = bt.ld[B_V];
+  const double* X = addr(bt, B_V, i, s, 0, 0);
+  const double* pz = addr(bt, B_Z, i, s, 0, 0);
+  const int ldz = bt.ld[B_Z];
+  double* KT = addr(bt, B_G, i, s, 0, 0);
   const int ldk = bt.ld[B_G];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < Ri * nr; e += 256) {
-    int r = e % nr, a = e / nr;
-    sh[a + r * Ri] = X[r + (int64_t)a * ld];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)R * R; e += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(e % R), a = (int)(e / R);
+    const int ps = (int)pz[b + ldz];
+    int c1i, c2i;
+    if (ps == 0) { c1i = b - 1; c2i = b; }
+    else if (ps == 2) { c1i = b; c2i = b + 1; }
+    else { c1i = b; c2i = -1; }
+    double v = X[c1i + (int64_t)a * ld] * pz[b + 2 * ldz];
+    if (c2i >= 0) v += X[c2i + (int64_t)a * ld] * pz[b + 3 * ldz];
+    KT[b + (int64_t)((int)pz[a]) * ldk] = v;
   }
-  __syncthreads();
-  for (int e = tid; e < Ri * nr; e += 256) {
-    int r = e % nr, b = e / nr;
-    const double* kc = K + (int64_t)b * ldk;
-    const double* xr = sh + r * Ri;
-    double acc = 0.0;
-    for (int a = 0; a < Ri; ++a) acc += xr[a] * kc[a];
-    X[r + (int64_t)b * ld] = acc;
-  }
+}
+
+__global__ void k_zero_clusters(const int* __restrict__ clusters, BufTab bt, int buf) {
+  const int s = blockIdx.z;
+  const int i = clusters[blockIdx.y];
+  double* p = addr(bt, buf, i, s, 0, 0);
+  const int64_t n = bt.bs[buf];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) p[e] = 0.0;
 }
 
 // ------------------------------------------------------------------- merge
@@ -1037,22 +995,33 @@ void launch_matsum(const SumItem* items, int nitems, const int* src, const BufTa
   }
 }
 
-void launch_pchol(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, double tau2, int cap, int nshift,
-                  hipStream_t st) {
+void launch_pchol_init(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st) {
   if (n <= 0) return;
-  size_t shmem = (size_t)cap * sizeof(double) + RT_THREADS * (sizeof(double) + sizeof(int)) + cap + 16;
-  hipLaunchKernelGGL(k_pchol, dim3(1, n, nshift), dim3(RT_THREADS), shmem, st, clusters, bt, sz, tau2);
+  hipLaunchKernelGGL(k_pchol_init, dim3(1, n, nshift), dim3(256), 0, st, clusters, bt, sz);
 }
 
-void launch_hqr(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st) {
+void launch_pchol_panel(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, double tau2, int* more, int cap,
+                        int nshift, hipStream_t st) {
   if (n <= 0) return;
-  size_t shmem = (size_t)(8 + HQR_NB + HQR_NB * HQR_NB + HQR_NB) * sizeof(double);
-  hipLaunchKernelGGL(k_hqr, dim3(1, n, nshift), dim3(RT_THREADS), shmem, st, clusters, bt, sz);
+  size_t shmem = (size_t)cap * sizeof(double) + RT_THREADS * (sizeof(double) + sizeof(int));
+  hipLaunchKernelGGL(k_pchol_panel, dim3(1, n, nshift), dim3(RT_THREADS), shmem, st, clusters, bt, sz, tau2, more);
 }
 
-void launch_tmat(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st) {
+void launch_pchol_finish(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_tmat, dim3(1, n, nshift), dim3(RT_THREADS), 0, st, clusters, bt, sz);
+  hipLaunchKernelGGL(k_pchol_finish, dim3(1, n, nshift), dim3(64), 0, st, clusters, bt, sz);
+}
+
+void launch_hqr_panel(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int it, int* more, int nshift,
+                      hipStream_t st) {
+  if (n <= 0) return;
+  size_t shmem = (size_t)(8 + HB + HB * HB + HB) * sizeof(double);
+  hipLaunchKernelGGL(k_hqr_panel, dim3(1, n, nshift), dim3(RT_THREADS), shmem, st, clusters, bt, sz, it, more);
+}
+
+void launch_set_panel(const int* clusters, int n, const SizeTab& sz, int it, int nshift, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_set_panel, dim3(1, n, nshift), dim3(64), 0, st, clusters, sz, it);
 }
 
 void launch_eye(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st) {
@@ -1061,32 +1030,47 @@ void launch_eye(const int* clusters, int n, const BufTab& bt, const SizeTab& sz,
                      bt, sz);
 }
 
-void launch_rotate(const RotItem* items, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st) {
+void launch_ldl_init(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st) {
   if (n <= 0) return;
-  const int strip = strip_for(cap);
-  size_t shmem = (size_t)cap * strip * sizeof(double);
-  for (int i0 = 0; i0 < n; i0 += 65535) {
-    int ni = std::min(65535, n - i0);
-    hipLaunchKernelGGL(k_rotate, dim3(cdiv(cap, strip), ni, nshift), dim3(256), shmem, st, items + i0, bt, sz, strip);
-  }
+  hipLaunchKernelGGL(k_ldl_init, dim3(1, n, nshift), dim3(256), 0, st, clusters, bt, sz);
 }
 
-void launch_ldl(const int* clusters, int n, const int* diag_blk, const BufTab& bt, const SizeTab& sz,
-                unsigned long long* nu, int* status, int cap, int nshift, hipStream_t st) {
+void launch_ldl_panel(const int* clusters, int n, const int* diag_blk, const BufTab& bt, const SizeTab& sz, int* status,
+                      int* more, int nshift, hipStream_t st) {
   if (n <= 0) return;
-  size_t shmem = 32 * sizeof(double) + (size_t)3 * cap * sizeof(double) + (size_t)2 * cap * sizeof(int);
-  hipLaunchKernelGGL(k_ldl, dim3(1, n, nshift), dim3(LDL_THREADS), shmem, st, clusters, diag_blk, bt, sz, nu, status);
+  hipLaunchKernelGGL(k_ldl_panel, dim3(1, n, nshift), dim3(LDL_THREADS), 0, st, clusters, diag_blk, bt, sz, status, more);
 }
 
-void launch_trsm(const TrsmItem* items, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st) {
+void launch_ldl_prep(const int* clusters, int n, const int* diag_blk, const BufTab& bt, const SizeTab& sz,
+                     unsigned long long* nu, int nshift, hipStream_t st) {
   if (n <= 0) return;
-  const int strip = strip_for(cap);
-  size_t shmem = (size_t)cap * strip * sizeof(double);
-  for (int i0 = 0; i0 < n; i0 += 65535) {
-    int ni = std::min(65535, n - i0);
-    hipLaunchKernelGGL(k_trsm, dim3(cdiv(cap, strip), ni, nshift), dim3(256), shmem, st, items + i0, bt, sz, strip);
-  }
+  hipLaunchKernelGGL(k_ldl_prep, dim3(1, n, nshift), dim3(LDL_THREADS), 0, st, clusters, diag_blk, bt, sz, nu);
 }
+
+void launch_diag_inv(const int* clusters, int n, const int* diag_blk, const BufTab& bt, const SizeTab& sz, int cap,
+                     int nshift, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_diag_inv, dim3(cdiv(cap, INV_NB), n, nshift), dim3(128), 0, st, clusters, diag_blk, bt, sz);
+}
+
+void launch_set_block(const int* clusters, int n, const SizeTab& sz, int ib, int nshift, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_set_block, dim3(1, n, nshift), dim3(64), 0, st, clusters, sz, ib);
+}
+
+void launch_kform(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_kform, dim3(std::max(1u, cdiv((int64_t)cap * cap, 256 * 4)), n, nshift), dim3(256), 0, st, clusters,
+                     bt, sz);
+}
+
+void launch_zero_clusters(const int* clusters, int n, const BufTab& bt, int buf, int cap, int nshift, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_zero_clusters, dim3(std::max(1u, cdiv((int64_t)cap * cap, 256 * 8)), n, nshift), dim3(256), 0, st,
+                     clusters, bt, buf);
+}
+
+int inv_block() { return INV_NB; }
 
 void launch_merge_sizes(const SizeTab& sz, int Np, int nshift, hipStream_t st) {
   hipLaunchKernelGGL(k_merge_sizes, dim3(cdiv(Np, 256), nshift), dim3(256), 0, st, sz, Np);

@@ -15,15 +15,25 @@ void launch_gemm(int kind, const GItem* items, int nitems, const GTerm* terms, c
 void launch_copyback(const CopyItem* items, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
 void launch_matsum(const SumItem* items, int nitems, const int* src, const BufTab& bt, const SizeTab& sz, int cap,
                    int nshift, hipStream_t st);
-void launch_pchol(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, double tau2, int cap, int nshift,
-                  hipStream_t st);
-void launch_hqr(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
-void launch_tmat(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st);
+void launch_pchol_init(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st);
+void launch_pchol_panel(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, double tau2, int* more, int cap,
+                        int nshift, hipStream_t st);
+void launch_pchol_finish(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st);
+void launch_hqr_panel(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int it, int* more, int nshift,
+                      hipStream_t st);
+void launch_set_panel(const int* clusters, int n, const SizeTab& sz, int it, int nshift, hipStream_t st);
 void launch_eye(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
-void launch_rotate(const RotItem* items, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
-void launch_ldl(const int* clusters, int n, const int* diag_blk, const BufTab& bt, const SizeTab& sz,
-                unsigned long long* nu, int* status, int cap, int nshift, hipStream_t st);
-void launch_trsm(const TrsmItem* items, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
+void launch_ldl_init(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st);
+void launch_ldl_panel(const int* clusters, int n, const int* diag_blk, const BufTab& bt, const SizeTab& sz, int* status,
+                      int* more, int nshift, hipStream_t st);
+void launch_ldl_prep(const int* clusters, int n, const int* diag_blk, const BufTab& bt, const SizeTab& sz,
+                     unsigned long long* nu, int nshift, hipStream_t st);
+void launch_diag_inv(const int* clusters, int n, const int* diag_blk, const BufTab& bt, const SizeTab& sz, int cap,
+                     int nshift, hipStream_t st);
+void launch_set_block(const int* clusters, int n, const SizeTab& sz, int ib, int nshift, hipStream_t st);
+void launch_kform(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
+void launch_zero_clusters(const int* clusters, int n, const BufTab& bt, int buf, int cap, int nshift, hipStream_t st);
+int inv_block();
 void launch_merge_sizes(const SizeTab& sz, int Np, int nshift, hipStream_t st);
 void launch_pmat(const BufTab& bt, const SizeTab& sz, const int* edim, int Np, int pcap, int nshift, hipStream_t st);
 void launch_gather(const GatherItem* items, int n, const BufTab& bt, const SizeTab& sz, int pcap, int nshift, hipStream_t st);

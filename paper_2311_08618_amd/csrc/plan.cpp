@@ -100,12 +100,38 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
       auto row0 = [&](int k) { return done(k) ? dx(DK_R, k) : dconst(0); };
       auto nrows = [&](int k) { return done(k) ? dx(DK_S, k) : dx(DK_M, k); };
       for (int i : cp.clusters) {
-        cp.rec_yty.add(item(ref(B_W, i), noref(), dx(DK_T, i), dx(DK_T, i), 1.0, 0.0),
-                       {term(ref(B_V, i), ref(B_V, i), dx(DK_RT, i))});
-        cp.rec_u.add(item(ref(B_Z, i), noref(), dx(DK_RT, i), dx(DK_T, i), 1.0, 0.0),
-                      {term(ref(B_V, i), ref(B_G, i), dx(DK_T, i))});
-        cp.rec_w.add(item(ref(B_W, i), noref(), dx(DK_RT, i), dx(DK_RT, i), -1.0, 1.0),
-                      {term(ref(B_Z, i), ref(B_V, i), dx(DK_T, i))});
+        const int a0 = dx(DK_A0, i), a1 = dx(DK_A1, i);
+        GItem g;
+        // pivoted Cholesky: G -= V[:, a0:t] V[:, a0:t]^T
+        g = item(ref(B_G, i), noref(), dx(DK_R, i), dx(DK_R, i), -1.0, 1.0);
+        g.guard = dx(DK_TMA0, i);
+        cp.pc_upd.add(g, {term(ref(B_V, i, 0, a0), ref(B_V, i, 0, a0), dx(DK_TMA0, i))});
+        // Householder QR trailing update
+        g = item(ref(B_W, i), noref(), a1, dx(DK_TREM, i), 1.0, 0.0);
+        g.guard = dx(DK_TREM, i);
+        cp.hq_z.add(g, {term(ref(B_V, i, 0, a0), ref(B_V, i, 0, a0, 0, a1), dx(DK_RTMA0, i))});
+        g = item(ref(B_V, i, 0, a0, 0, a1), noref(), dx(DK_RTMA0, i), dx(DK_TREM, i), -1.0, 1.0);
+        g.guard = dx(DK_TREM, i);
+        cp.hq_v.add(g, {term(ref(B_Z, i, 0, a0), ref(B_W, i), a1)});
+        // W <- W - (W Y_p)(Y_p T_p^T)^T
+        g = item(ref(B_G, i), noref(), dx(DK_RT, i), a1, 1.0, 0.0);
+        g.guard = a1;
+        cp.w_q.add(g, {term(ref(B_W, i), ref(B_V, i, 0, a0), dx(DK_RTMA0, i))});
+        g = item(ref(B_W, i), noref(), dx(DK_RT, i), dx(DK_RTMA0, i), -1.0, 1.0);
+        g.guard = a1;
+        cp.w_w.add(g, {term(ref(B_G, i), ref(B_Z, i, 0, a0), a1)});
+        // LDL trailing update A[k:R, k:R] -= L_p W_p^T, k = a0 + a1
+        const int db = lp.blk(i, i);
+        g = item(ref(B_S, db, a0, a0, a1, a1), noref(), dx(DK_RMK, i), dx(DK_RMK, i), -1.0, 1.0);
+        g.guard = a1;
+        cp.ldl_upd.add(g, {term(ref(B_S, db, a0, a0, a1, 0), ref(B_W, i, a0, 0, a1, 0), a1)});
+        // blocked L^{-1}: T = L[a0:a0+a1, 0:a0] X[0:a0, 0:a0] ; X[a0:a0+a1, 0:a0] = -X_ii T
+        g = item(ref(B_W, i), noref(), a1, a0, 1.0, 0.0);
+        g.guard = a1;
+        cp.inv_t.add(g, {term(ref(B_S, db, a0, 0), ref(B_V, i), a0)});
+        g = item(ref(B_V, i, a0, 0), noref(), a1, a0, -1.0, 0.0);
+        g.guard = a1;
+        cp.inv_x.add(g, {term(ref(B_V, i, a0, a0), ref(B_W, i), a1)});
       }
       // rotation by W (rows, then columns) and elimination by K, each as an
       // out-of-place product into a scratch slot followed by a copy back
@@ -127,6 +153,7 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
         for (int k : T.near[l][i]) {
           GItem g = item(ref(B_RS, -1), noref(), nrows(k), dx(DK_R, i), 1.0, 0.0);
           g.guard = dx(DK_R, i);
+          // operator stored transposed (K^T in B_G): NT product
           cp.trsm.add(g, {term(ref(B_S, lp.blk(k, i), row0(k), 0), ref(B_G, i), dx(DK_R, i))});
           CopyItem ct{ref(B_S, lp.blk(k, i), row0(k), 0), nrows(k), dx(DK_R, i), dx(DK_R, i)};
           cp.trsm_copy.push_back(ct);

@@ -28,12 +28,17 @@ struct SumList {
 
 struct ColourPlan {
   std::vector<int> clusters;
-  GList rec_yty;               // TN: Y^T Y (into B_W, before W exists)
-  GList rec_u;                 // NN: U = Y T
-  GList rec_w;                 // NT: W = I - U Y^T
+  GList pc_upd;                // NT: G -= L_p L_p^T after a pivoted-Cholesky panel
+  GList hq_z;                  // TN: Z = Y_p^T V_trail (into B_W)
+  GList hq_v;                  // NN: V_trail -= (Y_p T_p^T) Z
+  GList w_q;                   // NN: Q = W Y_p (into B_G)
+  GList w_w;                   // NT: W -= Q (Y_p T_p^T)^T
+  GList ldl_upd;               // NT: A_trail -= L_p W_p^T after an LDL panel
+  GList inv_t;                 // NN: T = L[rows of block ib, 0:a0] X[0:a0, 0:a0]
+  GList inv_x;                 // NN: X[block ib, 0:a0] = -X_ii T
   GList rot_rows, rot_cols;    // TN: RS = W^T X ; NN: RS = X W
   std::vector<CopyItem> rot_rows_copy, rot_cols_copy;
-  GList trsm;                  // NN: RS = X K
+  GList trsm;                  // NT: RS = X (K^T)^T, operator stored transposed
   std::vector<CopyItem> trsm_copy;
   GList schur;                 // NT, alpha -1
   GList gram_m;                // TN
