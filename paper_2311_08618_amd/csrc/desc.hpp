@@ -32,6 +32,7 @@ enum DimKind : int {
   DK_TREM = 12,  // t(c) - a0(c) - a1(c): columns to the right of the panel
   DK_RTMA0 = 13, // R(c) + t(c) - a0(c)
   DK_RMK = 14,   // R(c) - a0(c) - a1(c): trailing rows of a pivot block
+  DK_TN = 15,    // t(2c) + t(2c+1): new directions of the children of parent c (merge)
 };
 
 __host__ __device__ inline int dx(int kind, int arg) { return (kind << 24) | arg; }
@@ -49,9 +50,8 @@ enum BufId : int {
   B_P,        // per colour scratch: sums of Y^T Y
   B_T,        // per colour scratch: Y^R sign P
   B_SIGN,     // per cluster signs of the scaled pivots   [shift][cluster][mcap]
-  B_HAT,      // merge: children skeleton blocks          [shift][parent block][pcap^2]
-  B_PMAT,     // merge: parent basis per parent           [shift][parent][pcap^2]
-  B_TMP,      // merge: P^T Shat                          [shift][parent block][pcap^2]
+  B_HAT,      // merge: children skeleton blocks, permuted [shift][slot][pcap^2]
+  B_TMP,      // merge: old-old part times E_q             [shift][slot][emax^2]
   B_SN,       // next level near blocks
   B_FN,       // next level carried fill-in
   B_BRES,     // resident leaf near blocks (shift independent)
@@ -100,6 +100,7 @@ __host__ __device__ inline int dev_eval(int e, const SizeTab& z, int s) {
     case DK_TREM: return z.t[s * z.N + a] - z.a0[s * z.N + a] - z.a1[s * z.N + a];
     case DK_RTMA0: return z.R[s * z.N + a] + z.t[s * z.N + a] - z.a0[s * z.N + a];
     case DK_RMK: return z.R[s * z.N + a] - z.a0[s * z.N + a] - z.a1[s * z.N + a];
+    case DK_TN: return z.t[s * z.N + 2 * a] + z.t[s * z.N + 2 * a + 1];
   }
   return 0;
 }
@@ -154,9 +155,11 @@ struct TrsmItem {
   int row0, nrows;  // size expressions
 };
 
-// Merge gather: parent block (p, q) from the 2x2 children skeleton blocks.
+// Merge gather: parent block (p, q) from the 2x2 children skeleton blocks, in
+// the order [new c1 | new c2 | old c1 | old c2] for rows and columns.
 struct GatherItem {
-  int out_blk;              // in B_HAT
+  int out_blk;              // slot in B_HAT
+  int dst_buf, dst_blk;     // output block (B_SN or B_FN): receives the new-new part
   int p, q;                 // parent clusters
   int src_kind[4];          // 0 none, 1 near block (B_S), 2 carried fill-in (B_F)
   int src_blk[4];

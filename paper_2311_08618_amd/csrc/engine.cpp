@@ -112,7 +112,7 @@ struct DevColour {
 
 struct DevLevel {
   std::vector<DevColour> colours;
-  size_t diag_blk = 0, r0 = 0, pr0 = 0, edim = 0, gather = 0;
+  size_t diag_blk = 0, r0 = 0, pr0 = 0, gather = 0;
   int ngather = 0;
   DevList gram_init, fill, tr1, tr2;
 };
@@ -277,7 +277,6 @@ void upload_plan(h2_matrix A) {
     if (l >= 1) {
       const MergePlan& mp = lp.merge;
       dl.pr0 = b.put(mp.pr0);
-      dl.edim = b.put(mp.emat_dim);
       dl.gather = b.put(mp.gather);
       dl.ngather = (int)mp.gather.size();
       dl.fill = put_list(b, mp.fill);
@@ -368,12 +367,12 @@ void build_near_blocks(h2_matrix A) {
     GList g1, g2;
     for (int k = 0; k < nb; ++k) {
       int i = bi[b0 + k], j = bj[b0 + k];
-      Ref q{B_PMAT, i, 0, 0, 0, 0}, a{B_HAT, k, 0, 0, 0, 0}, t{B_TMP, k, 0, 0, 0, 0}, o{B_BRES, b0 + k, 0, 0, 0, 0};
+      Ref q{B_V, i, 0, 0, 0, 0}, a{B_HAT, k, 0, 0, 0, 0}, t{B_TMP, k, 0, 0, 0, 0}, o{B_BRES, b0 + k, 0, 0, 0, 0};
       Ref none{-1, 0, 0, 0, 0, 0};
       GItem it1{t, none, msz[i], msz[j], 0, 0, 1.0, 0.0, -1};
       g1.add(it1, {GTerm{q, a, msz[i], -1, 0}});
       GItem it2{o, none, msz[i], msz[j], 0, 0, 1.0, 0.0, -1};
-      g2.add(it2, {GTerm{t, Ref{B_PMAT, j, 0, 0, 0, 0}, msz[j], -1, 0}});
+      g2.add(it2, {GTerm{t, Ref{B_V, j, 0, 0, 0, 0}, msz[j], -1, 0}});
     }
     GItem *di1, *di2;
     GTerm *dt1, *dt2;
@@ -387,7 +386,7 @@ void build_near_blocks(h2_matrix A) {
     HIPCHK(hipMemcpy(dt2, g2.terms.data(), g2.terms.size() * sizeof(GTerm), hipMemcpyHostToDevice));
     BufTab bt{};
     for (int k = 0; k < NBUF; ++k) { bt.p[k] = nullptr; bt.ss[k] = 0; bt.bs[k] = (int64_t)bsz; bt.ld[k] = cap; }
-    bt.p[B_PMAT] = dQ;
+    bt.p[B_V] = dQ;   // leaf bases
     bt.p[B_HAT] = dA;
     bt.p[B_TMP] = dT;
     bt.p[B_BRES] = A->d_bres;
@@ -726,18 +725,17 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     double* dFN = dSN + nSN;
     const MergePlan& mp = lp.merge;
     const int nslot = std::max(1, std::min(mp.nhat, MERGE_CHUNK));
-    size_t nH = (size_t)S * nslot * pbsz, nPm = (size_t)S * Np * pbsz;
-    A->mrg.ensure((2 * nH + nPm) * 8 + 64, st);
+    const int emax = std::max(1, mp.emax);
+    const size_t ebsz = (size_t)emax * emax;
+    size_t nH = (size_t)S * nslot * pbsz, nTm = (size_t)S * nslot * ebsz;
+    A->mrg.ensure((nH + nTm) * 8 + 64, st);
     double* dH = (double*)A->mrg.p;
     double* dTm = dH + nH;
-    double* dPm = dTm + nH;
     setb(B_HAT, dH, (size_t)nslot * pbsz, pbsz, pcap);
-    setb(B_TMP, dTm, (size_t)nslot * pbsz, pbsz, pcap);
-    setb(B_PMAT, dPm, (size_t)Np * pbsz, pbsz, pcap);
+    setb(B_TMP, dTm, (size_t)nslot * ebsz, ebsz, emax);
     setb(B_SN, dSN, (size_t)pp.nblk() * pbsz, pbsz, pcap);
     setb(B_FN, dFN, (size_t)pp.nfblk() * pbsz, pbsz, pcap);
     setb(B_EMAT, A->d_emat[l - 1], 0, (size_t)A->emat_ld[l - 1] * A->emat_ld[l - 1], A->emat_ld[l - 1]);
-    run(PC_MERGE, [&] { launch_pmat(bt, sz, A->dp<int>(dl.edim), Np, pcap, S, st); });
     for (const MergeChunk& ch : mp.chunks) {
       run(PC_MERGE, [&] { launch_gather(A->dp<GatherItem>(dl.gather) + ch.g0, ch.g1 - ch.g0, bt, sz, pcap, S, st); });
       if (ch.f1 > ch.f0)
@@ -746,11 +744,11 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
                       pcap, pcap, S, st);
         });
       run(PC_MERGE, [&] {
-        launch_gemm(GEMM_TN, A->dp<GItem>(dl.tr1.items) + ch.a0, ch.a1 - ch.a0, A->dp<GTerm>(dl.tr1.terms), bt, sz, pcap,
-                    pcap, S, st);
+        launch_gemm(GEMM_NN, A->dp<GItem>(dl.tr1.items) + ch.a0, ch.a1 - ch.a0, A->dp<GTerm>(dl.tr1.terms), bt, sz, pcap,
+                    emax, S, st);
       });
       run(PC_MERGE, [&] {
-        launch_gemm(GEMM_NN, A->dp<GItem>(dl.tr2.items) + ch.b0, ch.b1 - ch.b0, A->dp<GTerm>(dl.tr2.terms), bt, sz, pcap,
+        launch_gemm(GEMM_TN, A->dp<GItem>(dl.tr2.items) + ch.b0, ch.b1 - ch.b0, A->dp<GTerm>(dl.tr2.terms), bt, sz, emax,
                     pcap, S, st);
       });
     }

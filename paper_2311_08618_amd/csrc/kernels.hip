@@ -807,34 +807,16 @@ __global__ void k_merge_sizes(SizeTab sz, int Np) {
   }
 }
 
-// P_p (m_p x m_p): parent coordinates [new c1 | new c2 | E^T (old c1, old c2)]
-__global__ void k_pmat(BufTab bt, SizeTab sz, const int* __restrict__ edim) {
-  const int s = blockIdx.z, p = blockIdx.y;
-  const int N = sz.N;
-  const int c1 = 2 * p, c2 = 2 * p + 1;
-  const int t1 = sz.t[s * N + c1], t2 = sz.t[s * N + c2];
-  const int s1 = sz.m[s * N + c1] - sz.R[s * N + c1];
-  const int r01 = sz.r0[c1];
-  const int mp = sz.pm[s * sz.Np + p];
-  const int ed = edim[p];
-  double* P = addr(bt, B_PMAT, p, s, 0, 0);
-  const int ld = bt.ld[B_PMAT];
-  const double* E = addr(bt, B_EMAT, p, 0, 0, 0);
-  const int lde = bt.ld[B_EMAT];
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)mp * mp; e += (int64_t)gridDim.x * blockDim.x) {
-    int row = (int)(e % mp), col = (int)(e / mp);
-    double v = 0.0;
-    if (col < t1) v = (row == col) ? 1.0 : 0.0;
-    else if (col < t1 + t2) v = (row == s1 + (col - t1)) ? 1.0 : 0.0;
-    else {
-      int o = -1;
-      if (row >= t1 && row < s1) o = row - t1;
-      else if (row >= s1 + t2) o = r01 + (row - s1 - t2);
-      int b = col - t1 - t2;
-      if (o >= 0 && o < ed && b < ed) v = E[o + (int64_t)b * lde];
-    }
-    P[row + (int64_t)col * ld] = v;
-  }
+// Children skeleton coordinate of parent-order position x for parent p:
+// [new c1 (t1) | new c2 (t2) | old c1 (r01) | old c2]; returns the child (0/1)
+// and its local skeleton index (new directions first, then old coordinates).
+__device__ inline int merge_pos(int x, int t1, int t2, int r01, int* loc) {
+  const int tn = t1 + t2;
+  if (x < t1) { *loc = x; return 0; }
+  if (x < tn) { *loc = x - t1; return 1; }
+  if (x < tn + r01) { *loc = t1 + (x - tn); return 0; }
+  *loc = t2 + (x - tn - r01);
+  return 1;
 }
 
 __global__ void k_gather(const GatherItem* __restrict__ items, BufTab bt, SizeTab sz) {
@@ -842,27 +824,33 @@ __global__ void k_gather(const GatherItem* __restrict__ items, BufTab bt, SizeTa
   const GatherItem g = items[blockIdx.y];
   const int N = sz.N;
   const int p = g.p, q = g.q;
-  const int sp1 = sz.m[s * N + 2 * p] - sz.R[s * N + 2 * p];
-  const int sq1 = sz.m[s * N + 2 * q] - sz.R[s * N + 2 * q];
+  const int tp1 = sz.t[s * N + 2 * p], tp2 = sz.t[s * N + 2 * p + 1];
+  const int tq1 = sz.t[s * N + 2 * q], tq2 = sz.t[s * N + 2 * q + 1];
+  const int rp1 = sz.r0[2 * p], rq1 = sz.r0[2 * q];
+  const int tnp = tp1 + tp2, tnq = tq1 + tq2;
   const int mp = sz.pm[s * sz.Np + p], mq = sz.pm[s * sz.Np + q];
   double* H = addr(bt, B_HAT, g.out_blk, s, 0, 0);
   const int ldh = bt.ld[B_HAT];
+  double* O = addr(bt, g.dst_buf, g.dst_blk, s, 0, 0);
+  const int ldo = bt.ld[g.dst_buf];
   const int ldc = bt.ld[B_CPL];
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)mp * mq; e += (int64_t)gridDim.x * blockDim.x) {
-    int row = (int)(e % mp), col = (int)(e / mp);
-    int a = row < sp1 ? 0 : 1, b = col < sq1 ? 0 : 1;
-    int c = 2 * p + a, d = 2 * q + b;
-    int rr = row - (a ? sp1 : 0), cc = col - (b ? sq1 : 0);
-    int slot = 2 * a + b;
-    int Rc = sz.R[s * N + c], Rd = sz.R[s * N + d];
+    const int row = (int)(e % mp), col = (int)(e / mp);
+    int rr, cc;
+    const int a = merge_pos(row, tp1, tp2, rp1, &rr);
+    const int b = merge_pos(col, tq1, tq2, rq1, &cc);
+    const int c = 2 * p + a, d = 2 * q + b;
+    const int slot = 2 * a + b;
+    const int Rc = sz.R[s * N + c], Rd = sz.R[s * N + d];
     double v = 0.0;
     if (g.src_kind[slot] == 1) v = addr(bt, B_S, g.src_blk[slot], s, Rc + rr, Rd + cc)[0];
     else if (g.src_kind[slot] == 2) v = addr(bt, B_F, g.src_blk[slot], s, Rc + rr, Rd + cc)[0];
     if (g.cpl_blk[slot] >= 0) {
-      int tc = sz.t[s * N + c], td = sz.t[s * N + d];
+      const int tc = sz.t[s * N + c], td = sz.t[s * N + d];
       if (rr >= tc && cc >= td) v += bt.p[B_CPL][(int64_t)g.cpl_blk[slot] * bt.bs[B_CPL] + (rr - tc) + (int64_t)(cc - td) * ldc];
     }
-    H[row + (int64_t)col * ldh] = v;
+    if (row < tnp && col < tnq) O[row + (int64_t)col * ldo] = v;
+    else H[row + (int64_t)col * ldh] = v;
   }
 }
 
@@ -1074,10 +1062,6 @@ int inv_block() { return INV_NB; }
 
 void launch_merge_sizes(const SizeTab& sz, int Np, int nshift, hipStream_t st) {
   hipLaunchKernelGGL(k_merge_sizes, dim3(cdiv(Np, 256), nshift), dim3(256), 0, st, sz, Np);
-}
-
-void launch_pmat(const BufTab& bt, const SizeTab& sz, const int* edim, int Np, int pcap, int nshift, hipStream_t st) {
-  hipLaunchKernelGGL(k_pmat, dim3(std::max(1u, cdiv((int64_t)pcap * pcap, 256 * 8)), Np, nshift), dim3(256), 0, st, bt, sz, edim);
 }
 
 void launch_gather(const GatherItem* items, int n, const BufTab& bt, const SizeTab& sz, int pcap, int nshift, hipStream_t st) {

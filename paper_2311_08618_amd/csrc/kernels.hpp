@@ -35,7 +35,6 @@ void launch_kform(const int* clusters, int n, const BufTab& bt, const SizeTab& s
 void launch_zero_clusters(const int* clusters, int n, const BufTab& bt, int buf, int cap, int nshift, hipStream_t st);
 int inv_block();
 void launch_merge_sizes(const SizeTab& sz, int Np, int nshift, hipStream_t st);
-void launch_pmat(const BufTab& bt, const SizeTab& sz, const int* edim, int Np, int pcap, int nshift, hipStream_t st);
 void launch_gather(const GatherItem* items, int n, const BufTab& bt, const SizeTab& sz, int pcap, int nshift, hipStream_t st);
 void launch_next_sizes(const SizeTab& sz, int nshift, hipStream_t st);
 void launch_leaf_init(const BufTab& bt, int nblk, const int* blk_diag_m, const double* sigma, int cap, int nshift,

@@ -257,10 +257,21 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
         mp.chunks.push_back(ch);
       }
       const int slot = h % MERGE_CHUNK;
+      // Parent coordinates [new c1 | new c2 | E^T (old c1, old c2)]: the new
+      // directions pass through, only the old skeleton coordinates meet E.
+      // The children block is gathered in the permuted order
+      // [new c1 | new c2 | old c1 | old c2]; its new-new part is final and
+      // goes straight to the output block, the rest to the slot in B_HAT.
+      const int obuf = is_near ? B_SN : B_FN;
+      const int oblk = is_near ? pp.blk(p, q) : pp.fblk(p, q);
+      const int tnp = dx(DK_TN, p), tnq = dx(DK_TN, q);
+      const int edp = mp.emat_dim[p], edq = mp.emat_dim[q];
       GatherItem g;
       g.out_blk = slot;
       g.p = p;
       g.q = q;
+      g.dst_buf = obuf;
+      g.dst_blk = oblk;
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
           int c = 2 * p + a, d = 2 * q + b, s = 2 * a + b;
@@ -276,21 +287,35 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
             std::set_intersection(T.near[l][c].begin(), T.near[l][c].end(), T.near[l][d].begin(),
                                   T.near[l][d].end(), std::back_inserter(cn));
             if (!cn.empty()) {
-              int offc = a ? dx(DK_S, 2 * p) : 0, offd = b ? dx(DK_S, 2 * q) : 0;
-              std::vector<GTerm> ts;
-              for (int i : cn)
-                ts.push_back(term(ref(B_S, lp.blk(c, i), dx(DK_R, c), 0), ref(B_S, lp.blk(d, i), dx(DK_R, d), 0),
-                                  dx(DK_R, i), B_SIGN, i));
-              mp.fill.add(item(ref(B_HAT, slot, offc, offd), noref(), dx(DK_S, c), dx(DK_S, d), -1.0, 1.0), ts);
+              const int rn = a ? dx(DK_T, 2 * p) : 0, ro = a ? dconst(B.r[l][2 * p]) : 0;
+              const int cnn = b ? dx(DK_T, 2 * q) : 0, co = b ? dconst(B.r[l][2 * q]) : 0;
+              for (int ra = 0; ra < 2; ++ra)
+                for (int cb = 0; cb < 2; ++cb) {
+                  // ra/cb = 0: new directions of c/d, 1: old skeleton coordinates
+                  std::vector<GTerm> ts;
+                  for (int i : cn)
+                    ts.push_back(term(ref(B_S, lp.blk(c, i), ra ? dx(DK_RT, c) : dx(DK_R, c), 0),
+                                      ref(B_S, lp.blk(d, i), cb ? dx(DK_RT, d) : dx(DK_R, d), 0), dx(DK_R, i), B_SIGN, i));
+                  Ref out = (ra == 0 && cb == 0) ? ref(obuf, oblk, rn, cnn)
+                                                 : ref(B_HAT, slot, ra ? tnp : rn, cb ? tnq : cnn, ra ? ro : 0, cb ? co : 0);
+                  GItem it = item(out, noref(), ra ? dconst(B.r[l][c]) : dx(DK_T, c),
+                                  cb ? dconst(B.r[l][d]) : dx(DK_T, d), -1.0, 1.0);
+                  mp.fill.add(it, ts);
+                }
             }
           }
         }
       mp.gather.push_back(g);
-      mp.tr1.add(item(ref(B_TMP, slot), noref(), dx(DK_PM, p), dx(DK_PM, q), 1.0, 0.0),
-                 {term(ref(B_PMAT, p), ref(B_HAT, slot), dx(DK_PM, p))});
-      Ref out = is_near ? ref(B_SN, pp.blk(p, q)) : ref(B_FN, pp.fblk(p, q));
-      mp.tr2.add(item(out, noref(), dx(DK_PM, p), dx(DK_PM, q), 1.0, 0.0),
-                 {term(ref(B_TMP, slot), ref(B_PMAT, q), dx(DK_PM, q))});
+      // new rows x old columns, and the old rows' right product, by E_q
+      mp.tr1.add(item(ref(obuf, oblk, 0, tnq), noref(), tnp, dconst(edq), 1.0, 0.0),
+                 {term(ref(B_HAT, slot, 0, tnq), ref(B_EMAT, q), dconst(edq))});
+      mp.tr1.add(item(ref(B_TMP, slot), noref(), dconst(edp), dconst(edq), 1.0, 0.0),
+                 {term(ref(B_HAT, slot, tnp, tnq), ref(B_EMAT, q), dconst(edq))});
+      // old rows: E_p^T on the left
+      mp.tr2.add(item(ref(obuf, oblk, tnp, 0), noref(), dconst(edp), tnq, 1.0, 0.0),
+                 {term(ref(B_EMAT, p), ref(B_HAT, slot, tnp, 0), dconst(edp))});
+      mp.tr2.add(item(ref(obuf, oblk, tnp, tnq), noref(), dconst(edp), dconst(edq), 1.0, 0.0),
+                 {term(ref(B_EMAT, p), ref(B_TMP, slot), dconst(edp))});
       MergeChunk& ch = mp.chunks.back();
       ch.g1 = (int)mp.gather.size();
       ch.f1 = (int)mp.fill.items.size();

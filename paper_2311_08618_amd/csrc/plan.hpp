@@ -61,9 +61,9 @@ struct MergePlan {
   int nhat = 0;
   std::vector<MergeChunk> chunks;
   std::vector<GatherItem> gather;
-  GList fill;                  // NT into B_HAT
-  GList tr1;                   // TN: TMP = P_p^T HAT
-  GList tr2;                   // NN: out = TMP P_q
+  GList fill;                  // NT into B_HAT / the output's new-new part
+  GList tr1;                   // NN: out[new, old] = HAT[new, old] E_q ; TMP = HAT[old, old] E_q
+  GList tr2;                   // TN: out[old, new] = E_p^T HAT[old, new] ; out[old, old] = E_p^T TMP
   std::vector<int> pr0;        // parent construction ranks
   std::vector<int> emat_dim;   // r0_c1 + r0_c2 per parent
   int emax = 0;
