@@ -102,7 +102,7 @@ struct DevList {
 struct DevColour {
   size_t clusters = 0;
   int ncl = 0;
-  DevList pc_upd, hq_z, hq_v, w_q, w_w, ldl_upd, inv_t, inv_x;
+  DevList pc_upd, hq_z, hq_v, ut_s, ut_t, ut_x, ut_u, ut_w, ldl_upd, inv_t, inv_x;
   DevList rot_rows, rot_cols, trsm;
   size_t rr_copy = 0, rc_copy = 0, tr_copy = 0;
   DevList schur, gm, gt, gg;
@@ -205,8 +205,8 @@ struct h2_matrix_s {
   h2_stats_t st{};
   int max_shifts = 0;
   Profiler prof;
-  int* d_more = nullptr;   // "more panels needed" counter of the blocked factorizations
-  int* h_more = nullptr;   // pinned host copy
+  int* d_more = nullptr;   // per-iteration "more panels needed" counters + colour maxima
+  int* h_more = nullptr;   // pinned host copy (2 ints)
 
   template <class T>
   const T* dp(size_t off) const { return reinterpret_cast<const T*>(d_plan + off); }
@@ -254,8 +254,11 @@ void upload_plan(h2_matrix A) {
       dc.pc_upd = put_list(b, cp.pc_upd);
       dc.hq_z = put_list(b, cp.hq_z);
       dc.hq_v = put_list(b, cp.hq_v);
-      dc.w_q = put_list(b, cp.w_q);
-      dc.w_w = put_list(b, cp.w_w);
+      dc.ut_s = put_list(b, cp.ut_s);
+      dc.ut_t = put_list(b, cp.ut_t);
+      dc.ut_x = put_list(b, cp.ut_x);
+      dc.ut_u = put_list(b, cp.ut_u);
+      dc.ut_w = put_list(b, cp.ut_w);
       dc.ldl_upd = put_list(b, cp.ldl_upd);
       dc.inv_t = put_list(b, cp.inv_t);
       dc.inv_x = put_list(b, cp.inv_x);
@@ -462,11 +465,15 @@ struct Work {
 
 inline int round_cap(int v) { return std::max(8, (v + 7) & ~7); }
 
-// Number of clusters that need another panel (read back synchronously).
-int read_more(h2_matrix A, hipStream_t st) {
-  HIPCHK(hipMemcpyAsync(A->h_more, A->d_more, sizeof(int), hipMemcpyDeviceToHost, st));
+// Counters of the blocked factorizations: one "more panels needed" slot per
+// iteration (zeroed once per loop, read back only every few iterations, so
+// that the host rarely waits for the device), then two slots for colour maxima.
+constexpr int MORE_SLOTS = 4096;
+
+// Read back n ints at d (synchronously).
+void read_back(h2_matrix A, const int* d, int n, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(A->h_more, d, n * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  return *A->h_more;
 }
 
 int debug_level() {
@@ -490,7 +497,10 @@ void debug_dump_level(int l, int N, int S, const Work& w, hipStream_t st) {
   int mmax = 0, tmax = 0;
   for (int v : m) mmax = std::max(mmax, v);
   for (int v : t) tmax = std::max(tmax, v);
-  std::fprintf(stderr, "[h2eig] level %d: nu[0]=%llu status[0]=%d max m %d max t %d\n", l, nu[0], stv[0], mmax, tmax);
+  double ms = 0, rs = 0, ts = 0;
+  for (int i = 0; i < N; ++i) { ms += m[i]; rs += R[i]; ts += t[i]; }
+  std::fprintf(stderr, "[h2eig] level %d: nu[0]=%llu status[0]=%d max m %d max t %d mean m %.1f R %.1f t %.1f\n", l,
+               nu[0], stv[0], mmax, tmax, ms / N, rs / N, ts / N);
   std::fprintf(stderr, "[h2eig]   m:");
   for (int i = 0; i < std::min(N, 32); ++i) std::fprintf(stderr, " %d", m[i]);
   std::fprintf(stderr, "\n[h2eig]   R:");
@@ -640,52 +650,67 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     for (size_t c = 0; c < dl.colours.size(); ++c) {
       const DevColour& dc = dl.colours[c];
       const int* cl = A->dp<int>(dc.clusters);
-      auto gl = [&](int cls, int kind, const DevList& L, int mcap = 0) {
-        const int mc = mcap > 0 ? mcap : cap;
-        if (L.n) run(cls, [&] { launch_gemm(kind, A->dp<GItem>(L.items), L.n, A->dp<GTerm>(L.terms), bt, sz, mc, cap, S, st); });
+      auto gl = [&](int cls, int kind, const DevList& L, int mcap = 0, int ncap = 0) {
+        const int mc = mcap > 0 ? mcap : cap, nc = ncap > 0 ? ncap : cap;
+        if (L.n) run(cls, [&] { launch_gemm(kind, A->dp<GItem>(L.items), L.n, A->dp<GTerm>(L.terms), bt, sz, mc, nc, S, st); });
       };
-      // pivoted Cholesky of the fill-in Gram, panel by panel
+      // pivoted Cholesky of the fill-in Gram, panel by panel (finished clusters
+      // make a panel a no-op, so the counters are read back every 4 panels)
       run(PC_PCHOL, [&] { launch_pchol_init(cl, dc.ncl, bt, sz, S, st); });
-      for (int it = 0; it <= cap / 32 + 2; ++it) {
-        HIPCHK(hipMemsetAsync(A->d_more, 0, sizeof(int), st));
-        run(PC_PCHOL, [&] { launch_pchol_panel(cl, dc.ncl, bt, sz, tau2, A->d_more, cap, S, st); });
-        gl(PC_PCHOL_UPD, GEMM_NT, dc.pc_upd);
-        if (read_more(A, st) == 0) break;
+      {
+        const int nit = std::min(MORE_SLOTS, cap / PCHOL_NB + 2);
+        HIPCHK(hipMemsetAsync(A->d_more, 0, nit * sizeof(int), st));
+        for (int it = 0; it < nit; ++it) {
+          run(PC_PCHOL, [&] { launch_pchol_panel(cl, dc.ncl, bt, sz, tau2, A->d_more + it, cap, S, st); });
+          gl(PC_PCHOL_UPD, GEMM_NT, dc.pc_upd);
+          if (it % 4 == 3 || it == nit - 1) {
+            read_back(A, A->d_more + it, 1, st);
+            if (A->h_more[0] == 0) break;
+          }
+        }
       }
       run(PC_PCHOL, [&] { launch_pchol_finish(cl, dc.ncl, bt, sz, S, st); });
+      // largest t and R of the class: exact launch counts from here on
+      int* dmx = A->d_more + MORE_SLOTS;
+      HIPCHK(hipMemsetAsync(dmx, 0, 2 * sizeof(int), st));
+      run(PC_PCHOL, [&] { launch_colour_max(cl, dc.ncl, sz, dmx, S, st); });
+      read_back(A, dmx, 2, st);
+      const int tmax = A->h_more[0], rmax = A->h_more[1];
       // Householder QR of the kept columns, panel by panel
-      int npanel = 0;
-      for (int it = 0; it <= cap / 32 + 2; ++it) {
-        HIPCHK(hipMemsetAsync(A->d_more, 0, sizeof(int), st));
-        run(PC_HQR, [&] { launch_hqr_panel(cl, dc.ncl, bt, sz, it, A->d_more, S, st); });
+      for (int it = 0; it * HQR_NB < tmax; ++it) {
+        run(PC_HQR, [&] { launch_hqr_panel(cl, dc.ncl, bt, sz, it, dmx, S, st); });
         gl(PC_HQR_UPD, GEMM_TN, dc.hq_z);
         gl(PC_HQR_UPD, GEMM_NN, dc.hq_v);
-        npanel = it + 1;
-        if (read_more(A, st) == 0) break;
       }
-      // W = prod_p (I - Y_p T_p Y_p^T)
-      run(PC_WFORM, [&] { launch_eye(cl, dc.ncl, bt, sz, cap, S, st); });
-      for (int it = 0; it < npanel; ++it) {
-        run(PC_WFORM, [&] { launch_set_panel(cl, dc.ncl, sz, it, S, st); });
-        gl(PC_WFORM, GEMM_NN, dc.w_q);
-        gl(PC_WFORM, GEMM_NT, dc.w_w);
+      // W = I - Y T Y^T (UT transform)
+      if (tmax > 0) {
+        gl(PC_WFORM, GEMM_TN, dc.ut_s);
+        run(PC_WFORM, [&] { launch_ut_prep(cl, dc.ncl, bt, sz, cap, S, st); });
+        run(PC_WFORM, [&] { launch_ut_diag_inv(cl, dc.ncl, bt, sz, cap, S, st); });
+        for (int ib = 1; ib * inv_block() < tmax; ++ib) {
+          run(PC_WFORM, [&] { launch_set_block(cl, dc.ncl, sz, ib, 1, S, st); });
+          gl(PC_WFORM, GEMM_NN, dc.ut_t, 0, inv_block());
+          gl(PC_WFORM, GEMM_NN, dc.ut_x, 0, inv_block());
+        }
+        gl(PC_WFORM, GEMM_NN, dc.ut_u);
+        run(PC_WFORM, [&] { launch_eye(cl, dc.ncl, bt, sz, cap, S, st); });
+        gl(PC_WFORM, GEMM_NT, dc.ut_w);
       }
       chunked(PC_ROTATE, GEMM_TN, dc.rot_rows, dc.rr_copy);
       chunked(PC_ROTATE, GEMM_NN, dc.rot_cols, dc.rc_copy);
-      // pivot LDL, panel by panel, then the elimination operator
+      // pivot LDL, panel by panel (each panel takes at least ldl_panel_min()
+      // pivots unless it reaches R), then the elimination operator
       run(PC_LDL, [&] { launch_ldl_init(cl, dc.ncl, bt, sz, S, st); });
-      for (int it = 0; it <= cap / 16 + 2; ++it) {
-        HIPCHK(hipMemsetAsync(A->d_more, 0, sizeof(int), st));
-        run(PC_LDL, [&] { launch_ldl_panel(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, w.status, A->d_more, S, st); });
+      for (int it = 0; it * ldl_panel_min(cap) < rmax; ++it) {
+        run(PC_LDL, [&] { launch_ldl_panel(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, w.status, dmx, S, st); });
         gl(PC_LDL_UPD, GEMM_NT, dc.ldl_upd);
-        if (read_more(A, st) == 0) break;
       }
       run(PC_LDL, [&] { launch_ldl_prep(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, w.nu, S, st); });
       // X = L^{-1}: diagonal blocks, then block rows by GEMMs
       run(PC_LDL, [&] { launch_zero_clusters(cl, dc.ncl, bt, B_V, cap, S, st); });
       run(PC_LDL, [&] { launch_diag_inv(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, cap, S, st); });
-      for (int ib = 1; ib * inv_block() < cap; ++ib) {
-        run(PC_LDL, [&] { launch_set_block(cl, dc.ncl, sz, ib, S, st); });
+      for (int ib = 1; ib * inv_block() < rmax; ++ib) {
+        run(PC_LDL, [&] { launch_set_block(cl, dc.ncl, sz, ib, 0, S, st); });
         gl(PC_LDL_INV, GEMM_NN, dc.inv_t, inv_block());
         gl(PC_LDL_INV, GEMM_NN, dc.inv_x, inv_block());
       }
@@ -867,8 +892,8 @@ h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern,
     A->leafcap = 0;
     for (int i = 0; i < (1 << L); ++i) A->leafcap = std::max<int>(A->leafcap, (int)A->T.size[L][i]);
     A->leafcap = round_cap(A->leafcap);
-    HIPCHK(hipMalloc(&A->d_more, sizeof(int)));
-    HIPCHK(hipHostMalloc(&A->h_more, sizeof(int)));
+    HIPCHK(hipMalloc(&A->d_more, (MORE_SLOTS + 2) * sizeof(int)));
+    HIPCHK(hipHostMalloc(&A->h_more, 2 * sizeof(int)));
     upload_plan(A);
     upload_resident(A);
     build_near_blocks(A);

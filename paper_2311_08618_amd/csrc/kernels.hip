@@ -208,8 +208,9 @@ __device__ inline void argmax_reduce(double* sv, int* si, int tid, int nthr) {
 // B_Z holds the remaining diagonal (column 0) during the Cholesky and the
 // columns Y_p T_p^T during the QR.
 constexpr int RT_THREADS = 256;
-constexpr int PC_NB = 32;
-constexpr int HB = 32;
+constexpr int INV_NB = 64;    // block size of the blocked triangular inverses
+constexpr int PC_NB = PCHOL_NB;
+constexpr int HB = HQR_NB;
 
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -243,14 +244,21 @@ __global__ void k_pchol_init(const int* __restrict__ clusters, BufTab bt, SizeTa
 }
 
 // One panel of at most PC_NB pivots.  G holds the Gram updated by all previous
-// panels; columns of this panel are formed from G and the panel's own columns.
-__global__ __launch_bounds__(RT_THREADS) void k_pchol_panel(const int* __restrict__ clusters, BufTab bt, SizeTab sz,
+// panels; columns of this panel are formed from G and the panel's own columns:
+// column t = (G[:, p] - V[:, t0:t] V[p, t0:t]^T) / sqrt(d_p), taken four rows
+// x eight columns of independent loads at a time.
+constexpr int PC_THREADS = 512;
+
+__global__ __launch_bounds__(PC_THREADS) void k_pchol_panel(const int* __restrict__ clusters, BufTab bt, SizeTab sz,
                                                             double tau2, int* __restrict__ more) {
   extern __shared__ double sh[];
+  __shared__ double vp[PC_NB];               // V[p, t0 + l], zero beyond the panel's columns
+  __shared__ double redv[PC_THREADS / 64];
+  __shared__ int redi[PC_THREADS / 64];
   const int s = blockIdx.z;
   const int i = clusters[blockIdx.y];
   const int N = sz.N;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (sz.a1[s * N + i] == 0) {                // finished: no new columns for the update
     if (tid == 0) sz.a0[s * N + i] = sz.t[s * N + i];
     return;
@@ -261,52 +269,81 @@ __global__ __launch_bounds__(RT_THREADS) void k_pchol_panel(const int* __restric
   double* V = addr(bt, B_V, i, s, 0, 0);
   double* dg = addr(bt, B_Z, i, s, 0, 0);
   double* d = sh;                             // [cap]
-  double* red = sh + ld;                      // [RT_THREADS]
-  int* redi = (int*)(red + RT_THREADS);       // [RT_THREADS]
-  __shared__ int s_stop;
-  for (int a = tid; a < R; a += RT_THREADS) d[a] = dg[a];
-  if (tid == 0) s_stop = 0;
+  for (int a = tid; a < R; a += PC_THREADS) d[a] = dg[a];
+  if (tid < PC_NB) vp[tid] = 0.0;
   __syncthreads();
   const int t0 = sz.t[s * N + i];
   int t = t0;
+  bool stop = false;
   for (int j = 0; j < PC_NB && t < R; ++j) {
+    // pivot: largest remaining diagonal, first index on ties
     double bv = -INFINITY;
     int bi = R;
-    for (int a = tid; a < R; a += RT_THREADS)
-      if (d[a] > bv || (d[a] == bv && a < bi)) { bv = d[a]; bi = a; }
-    red[tid] = bv;
-    redi[tid] = bi;
+    for (int a = tid; a < R; a += PC_THREADS)
+      if (d[a] > bv) { bv = d[a]; bi = a; }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { redv[wave] = bv; redi[wave] = bi; }
     __syncthreads();
-    argmax_reduce(red, redi, tid, RT_THREADS);
-    const double dmax = red[0];
-    const int p = redi[0];
-    __syncthreads();
+    double dmax = redv[0];
+    int p = redi[0];
+    for (int w2 = 1; w2 < PC_THREADS / 64; ++w2)
+      if (redv[w2] > dmax || (redv[w2] == dmax && redi[w2] < p)) { dmax = redv[w2]; p = redi[w2]; }
     if (!(dmax > tau2)) {
-      if (tid == 0) s_stop = 1;
+      stop = true;
       break;
     }
-    const double sq = sqrt(dmax), inv = 1.0 / sq;
-    for (int a = tid; a < R; a += RT_THREADS) {
-      double v = 0.0;
-      if (a == p) v = sq;
-      else if (d[a] != -INFINITY) {
-        v = G[a + (int64_t)p * ld];
-        for (int l = t0; l < t; ++l) v -= V[a + (int64_t)l * ld] * V[p + (int64_t)l * ld];
-        v *= inv;
-        d[a] -= v * v;
-      }
-      V[a + (int64_t)t * ld] = v;
-    }
+    const int jw = t - t0;
+    if (tid < jw) vp[tid] = V[p + (int64_t)(t0 + tid) * ld];
     __syncthreads();
-    if (tid == 0) d[p] = -INFINITY;
+    const double sq = sqrt(dmax), inv = 1.0 / sq;
+    for (int ab = tid; ab < R; ab += 4 * PC_THREADS) {
+      int ar[4];
+      bool live[4];
+      double acc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ar[u] = ab + u * PC_THREADS;
+        live[u] = ar[u] < R && ar[u] != p && d[ar[u]] != -INFINITY;
+        acc[u] = live[u] ? G[ar[u] + (int64_t)p * ld] : 0.0;
+      }
+      for (int l0 = 0; l0 < jw; l0 += 8) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int col = t0 + min(l0 + q, jw - 1);   // vp = 0 beyond jw
+          const double c = vp[min(l0 + q, PC_NB - 1)] * (l0 + q < jw ? 1.0 : 0.0);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (ar[u] < R) acc[u] -= V[ar[u] + (int64_t)col * ld] * c;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int a = ar[u];
+        if (a < R) {
+          double v = 0.0;
+          if (a == p) {
+            v = sq;
+            d[a] = -INFINITY;
+          } else if (live[u]) {
+            v = acc[u] * inv;
+            d[a] -= v * v;
+          }
+          V[a + (int64_t)t * ld] = v;
+        }
+      }
+    }
     __syncthreads();
     ++t;
   }
-  for (int a = tid; a < R; a += RT_THREADS) dg[a] = d[a];
+  for (int a = tid; a < R; a += PC_THREADS) dg[a] = d[a];
   if (tid == 0) {
     sz.t[s * N + i] = t;
     sz.a0[s * N + i] = t0;
-    const bool go = !s_stop && t < R;
+    const bool go = !stop && t < R;
     sz.a1[s * N + i] = go ? 1 : 0;
     if (go) atomicAdd(more, 1);
   }
@@ -323,16 +360,147 @@ __global__ void k_pchol_finish(const int* __restrict__ clusters, BufTab bt, Size
   }
 }
 
+constexpr int HQ_THREADS = 256;
+
+// Butterfly reduce-scatter of 64 per-lane values over a wave: afterwards lane L
+// holds the wave sum of v[L] in v[0] (63 exchanges instead of 64 x 6).
+template <int OFF>
+__device__ inline void rs_step(double (&v)[64], int lane) {
+  const bool up = (lane & OFF) != 0;
+#pragma unroll
+  for (int m = 0; m < OFF; ++m) {
+    const double keep = up ? v[m + OFF] : v[m];
+    const double send = up ? v[m] : v[m + OFF];
+    v[m] = keep + __shfl_xor(send, OFF, 64);
+  }
+}
+
+__device__ inline void wave_reduce_scatter64(double (&v)[64], int lane) {
+  rs_step<32>(v, lane);
+  rs_step<16>(v, lane);
+  rs_step<8>(v, lane);
+  rs_step<4>(v, lane);
+  rs_step<2>(v, lane);
+  rs_step<1>(v, lane);
+}
+
+template <bool FULL>
+__device__ inline void hqr_panel_body(double* __restrict__ V, double* __restrict__ Yt, double* __restrict__ beta, int ld,
+                                      int RT, int k0, int nb, double (*red)[64], double* sums, double* wv, double* rowp,
+                                      double* Tp, double* bp) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double v0prev = 0.0;
+  int pprev = -1;
+  for (int kk = 0; kk <= nb; ++kk) {
+    const int pcur = kk < nb ? RT - 1 - (k0 + kk) : -1;
+    const int plim = kk > 0 ? pprev : pcur;
+    const int kx = min(kk, nb - 1), ky = max(kk - 1, 0);
+    const double wk = kk < nb ? wv[kk] : 0.0;
+    double acc[64];   // [0, HB): x . V_j   [HB, 2HB): y_j . y_{kk-1}
+#pragma unroll
+    for (int jj = 0; jj < 64; ++jj) acc[jj] = 0.0;
+    for (int a = tid; a <= plim; a += HQ_THREADS) {
+      double ym = kk > 0 ? V[a + (int64_t)(k0 + ky) * ld] : 0.0;
+      if (a == pprev) ym = v0prev;
+      double xk = kk < nb && a <= pcur ? V[a + (int64_t)(k0 + kx) * ld] - ym * wk : 0.0;
+      const bool anchor = a == pcur;
+      // all loads of the row before any store: the stores go through the same
+      // pointer, so loads issued after them would be serialised behind them
+      double vals[HB];
+#pragma unroll
+      for (int jj = 0; jj < HB; ++jj) vals[jj] = (FULL || jj < nb) ? V[a + (int64_t)(k0 + jj) * ld] : 0.0;
+#pragma unroll
+      for (int jj = 0; jj < HB; ++jj) {
+        if (FULL || jj < nb) {
+          const double v = vals[jj] - ym * wv[jj];   // wv[jj] = 0 outside (kk-1, nb)
+          if (kk > 0) V[a + (int64_t)(k0 + jj) * ld] = v;
+          acc[jj] += xk * v;
+          acc[HB + jj] += ym * v;
+          if (anchor) rowp[jj] = v;
+        }
+      }
+    }
+    wave_reduce_scatter64(acc, lane);
+    red[wave][lane] = acc[0];
+    __syncthreads();
+    if (tid < 64) {
+      double v = 0.0;
+      for (int w2 = 0; w2 < HQ_THREADS / 64; ++w2) v += red[w2][tid];
+      sums[tid] = v;
+    }
+    __syncthreads();
+    if (kk > 0) {   // column kk-1 of T_p from g_m = y_m . y_{kk-1}
+      const int c = kk - 1;
+      if (tid < c) {
+        double v = 0.0;
+        for (int m = tid; m < c; ++m) v += Tp[tid + m * HB] * sums[HB + m];
+        Tp[tid + c * HB] = -bp[c] * v;
+      } else if (tid == c) {
+        Tp[c + c * HB] = bp[c];
+      }
+    }
+    double v0 = 0.0;
+    if (kk < nb) {
+      const double xn2 = sums[kk];
+      const double x0 = rowp[kk];
+      const double xn = sqrt(xn2);
+      const double alpha = -copysign(xn, x0 != 0.0 ? x0 : 1.0);
+      v0 = x0 - alpha;
+      const double vn = xn2 - x0 * x0 + v0 * v0;
+      const double bk = vn > 0.0 ? 2.0 / vn : 0.0;
+      __syncthreads();   // every thread has read wv / rowp of this step
+      if (tid < HB) wv[tid] = (tid > kk && tid < nb) ? bk * (sums[tid] - alpha * rowp[tid]) : 0.0;
+      if (tid == 0) {
+        V[pcur + (int64_t)(k0 + kk) * ld] = v0;
+        bp[kk] = bk;
+        beta[k0 + kk] = bk;
+      }
+    }
+    v0prev = v0;
+    pprev = pcur;
+    __syncthreads();
+  }
+  // Per row: the panel's reflectors are zeroed below their anchors (those rows
+  // hold R entries), then Yt = Y_p T_p^T (RT x nb) goes to B_Z columns k0..k0+nb-1
+  // (T_p is upper triangular and zero elsewhere, so every row sums over all b2).
+  for (int a = tid; a < RT; a += HQ_THREADS) {
+    double y[HB];
+#pragma unroll
+    for (int jj = 0; jj < HB; ++jj)
+      y[jj] = ((FULL || jj < nb) && a <= RT - 1 - (k0 + jj)) ? V[a + (int64_t)(k0 + jj) * ld] : 0.0;
+#pragma unroll
+    for (int jj = 0; jj < HB; ++jj)
+      if ((FULL || jj < nb) && a > RT - 1 - (k0 + jj)) V[a + (int64_t)(k0 + jj) * ld] = 0.0;
+#pragma unroll 1
+    for (int c = 0; c < nb; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int b2 = 0; b2 < HB; ++b2) v += y[b2] * Tp[c + b2 * HB];   // T^T[b2][c] = T[c][b2]
+      Yt[a + (int64_t)(k0 + c) * ld] = v;
+    }
+  }
+}
+
 // Panel `it` of the Householder QR: columns k0 = it*HB .. k0+nb-1 of V (RT x t).
-__global__ __launch_bounds__(RT_THREADS) void k_hqr_panel(const int* __restrict__ clusters, BufTab bt, SizeTab sz, int it,
+// One pass over the rows per column: it applies the previous reflector to the
+// panel and, on the updated values, accumulates the norm and the dot products
+// that define the next reflector together with y_j . y_{k-1} (a column of T_p,
+// T_p^{-1} = striu(Y_p^T Y_p) + diag(1/beta)); one block reduction per column.
+// beta goes to B_SIGN (used to form W afterwards).
+__global__ __launch_bounds__(HQ_THREADS) void k_hqr_panel(const int* __restrict__ clusters, BufTab bt, SizeTab sz, int it,
                                                           int* __restrict__ more) {
-  extern __shared__ double sh[];
+  __shared__ double red[HQ_THREADS / 64][64];
+  __shared__ double sums[64];
+  __shared__ double wv[HB];       // beta (y . V_j) of the current reflector, 0 outside the live columns
+  __shared__ double rowp[HB];     // anchor row of the next reflector, after the update
+  __shared__ double Tp[HB * HB];
+  __shared__ double bp[HB];
   const int s = blockIdx.z;
   const int i = clusters[blockIdx.y];
   const int N = sz.N;
   const int t = sz.t[s * N + i];
   const int k0 = it * HB;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   if (k0 >= t) {
     if (tid == 0) { sz.a0[s * N + i] = k0; sz.a1[s * N + i] = 0; }
     return;
@@ -347,78 +515,12 @@ __global__ __launch_bounds__(RT_THREADS) void k_hqr_panel(const int* __restrict_
   const int ld = bt.ld[B_V];
   double* V = addr(bt, B_V, i, s, 0, 0);
   double* Yt = addr(bt, B_Z, i, s, 0, 0);
-  double* red = sh;                 // [8]
-  double* wd = sh + 8;              // [HB]
-  double* Tp = sh + 8 + HB;         // [HB * HB]
-  double* bp = Tp + HB * HB;        // [HB]
-  for (int kk = 0; kk < nb; ++kk) {
-    const int k = k0 + kk;
-    const int p = RT - 1 - k;
-    double part = 0.0;
-    for (int a = tid; a <= p; a += RT_THREADS) {
-      double x = V[a + (int64_t)k * ld];
-      part += x * x;
-    }
-    const double xn2 = block_sum(part, red, tid);
-    const double x0 = V[p + (int64_t)k * ld];
-    const double xn = sqrt(xn2);
-    const double alpha = -copysign(xn, x0 != 0.0 ? x0 : 1.0);
-    const double v0 = x0 - alpha;
-    const double vn = xn2 - x0 * x0 + v0 * v0;
-    const double bk = vn > 0.0 ? 2.0 / vn : 0.0;
-    __syncthreads();
-    if (tid == 0) {
-      V[p + (int64_t)k * ld] = v0;
-      bp[kk] = bk;
-    }
-    __syncthreads();
-    for (int j = k + 1 + wave; j < k0 + nb; j += RT_THREADS / 64) {
-      double q = 0.0;
-      for (int a = lane; a <= p; a += 64) q += V[a + (int64_t)k * ld] * V[a + (int64_t)j * ld];
-      q = wave_sum(q);
-      if (lane == 0) wd[j - k0] = q * bk;
-    }
-    __syncthreads();
-    const int nj = k0 + nb - k - 1, nr = p + 1;
-    for (int64_t e = tid; e < (int64_t)nj * nr; e += RT_THREADS) {
-      int a = (int)(e % nr), j = k + 1 + (int)(e / nr);
-      V[a + (int64_t)j * ld] -= V[a + (int64_t)k * ld] * wd[j - k0];
-    }
-    __syncthreads();
-  }
-  // reflectors of the panel: zero below their anchors (those rows hold R entries)
-  for (int64_t e = tid; e < (int64_t)nb * RT; e += RT_THREADS) {
-    int a = (int)(e % RT), kk = (int)(e / RT);
-    if (a > RT - 1 - (k0 + kk)) V[a + (int64_t)(k0 + kk) * ld] = 0.0;
-  }
-  for (int e = tid; e < HB * HB; e += RT_THREADS) Tp[e] = 0.0;
+  double* beta = addr(bt, B_SIGN, 0, s, 0, 0) + (int64_t)i * bt.bs[B_SIGN];
+  for (int e = tid; e < HB * HB; e += HQ_THREADS) Tp[e] = 0.0;
+  if (tid < HB) { wv[tid] = 0.0; rowp[tid] = 0.0; bp[tid] = 0.0; }
   __syncthreads();
-  // T_p: T_kk = beta_k, T[0:kk, kk] = -beta_kk T[0:kk, 0:kk] (Y_p^T y_kk)
-  for (int kk = 0; kk < nb; ++kk) {
-    const int p = RT - 1 - (k0 + kk);
-    for (int j = wave; j < kk; j += RT_THREADS / 64) {
-      double q = 0.0;
-      for (int a = lane; a <= p; a += 64) q += V[a + (int64_t)(k0 + j) * ld] * V[a + (int64_t)(k0 + kk) * ld];
-      q = wave_sum(q);
-      if (lane == 0) wd[j] = q;
-    }
-    __syncthreads();
-    if (tid < kk) {
-      double v = 0.0;
-      for (int b2 = tid; b2 < kk; ++b2) v += Tp[tid + b2 * HB] * wd[b2];
-      Tp[tid + kk * HB] = -bp[kk] * v;
-    } else if (tid == kk) {
-      Tp[kk + kk * HB] = bp[kk];
-    }
-    __syncthreads();
-  }
-  // Yt = Y_p T_p^T  (RT x nb) into B_Z columns k0 .. k0+nb-1
-  for (int64_t e = tid; e < (int64_t)nb * RT; e += RT_THREADS) {
-    int a = (int)(e % RT), c = (int)(e / RT);
-    double v = 0.0;
-    for (int b2 = c; b2 < nb; ++b2) v += V[a + (int64_t)(k0 + b2) * ld] * Tp[c + b2 * HB];   // T^T[b2][c] = T[c][b2]
-    Yt[a + (int64_t)(k0 + c) * ld] = v;
-  }
+  if (nb == HB) hqr_panel_body<true>(V, Yt, beta, ld, RT, k0, nb, red, sums, wv, rowp, Tp, bp);
+  else hqr_panel_body<false>(V, Yt, beta, ld, RT, k0, nb, red, sums, wv, rowp, Tp, bp);
   if (tid == 0) {
     sz.a0[s * N + i] = k0;
     sz.a1[s * N + i] = nb;
@@ -426,16 +528,53 @@ __global__ __launch_bounds__(RT_THREADS) void k_hqr_panel(const int* __restrict_
   }
 }
 
-// panel state of step `it` for the accumulation of W (a0 = it*HB, a1 = panel width)
-__global__ void k_set_panel(const int* __restrict__ clusters, SizeTab sz, int it) {
+// ---- W = H_0 ... H_{t-1} = I - Y T Y^T by the UT transform: T^{-1} = S with
+// S = striu(Y^T Y) + diag(1/beta).  S (t x t, from a GEMM) is in B_G; T is
+// formed in B_Z by a blocked upper-triangular inverse (diagonal blocks here,
+// block columns by GEMMs), then U = Y T and W = I - U Y^T on the matrix cores.
+__global__ void k_ut_prep(const int* __restrict__ clusters, BufTab bt, SizeTab sz) {
   const int s = blockIdx.z;
   const int i = clusters[blockIdx.y];
-  const int N = sz.N;
-  if (threadIdx.x == 0) {
-    const int t = sz.t[s * N + i], k0 = it * HB;
-    sz.a0[s * N + i] = k0;
-    sz.a1[s * N + i] = k0 < t ? min(HB, t - k0) : 0;
+  const int t = sz.t[s * sz.N + i];
+  double* S = addr(bt, B_G, i, s, 0, 0);
+  double* T = addr(bt, B_Z, i, s, 0, 0);
+  const int ld = bt.ld[B_G], ldt = bt.ld[B_Z];
+  const double* beta = addr(bt, B_SIGN, 0, s, 0, 0) + (int64_t)i * bt.bs[B_SIGN];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)t * t; e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e % t), b = (int)(e / t);
+    if (a > b) S[a + (int64_t)b * ld] = 0.0;
+    else if (a == b) S[a + (int64_t)b * ld] = beta[a] != 0.0 ? 1.0 / beta[a] : 1.0;   // beta = 0: H = I, y = 0
+    T[a + (int64_t)b * ldt] = 0.0;
   }
+}
+
+__global__ __launch_bounds__(64) void k_ut_diag_inv(const int* __restrict__ clusters, BufTab bt, SizeTab sz) {
+  __shared__ double Ss[INV_NB][INV_NB + 1];
+  __shared__ double Ts[INV_NB][INV_NB + 1];
+  const int s = blockIdx.z;
+  const int i = clusters[blockIdx.y];
+  const int t = sz.t[s * sz.N + i];
+  const int r0 = blockIdx.x * INV_NB;
+  if (r0 >= t) return;
+  const int nb = min(INV_NB, t - r0);
+  const double* S = addr(bt, B_G, i, s, r0, r0);
+  double* T = addr(bt, B_Z, i, s, r0, r0);
+  const int ld = bt.ld[B_G], ldt = bt.ld[B_Z];
+  const int c = threadIdx.x;
+  for (int b2 = 0; b2 < nb; ++b2)
+    if (c < nb) { Ss[c][b2] = S[c + (int64_t)b2 * ld]; Ts[c][b2] = 0.0; }
+  __syncthreads();
+  if (c < nb) {   // column c of the upper inverse, by back substitution
+    Ts[c][c] = 1.0 / Ss[c][c];
+    for (int a = c - 1; a >= 0; --a) {
+      double v = 0.0;
+      for (int b2 = a + 1; b2 <= c; ++b2) v += Ss[a][b2] * Ts[b2][c];
+      Ts[a][c] = -v / Ss[a][a];
+    }
+  }
+  __syncthreads();
+  for (int b2 = 0; b2 < nb; ++b2)
+    if (c < nb) T[c + (int64_t)b2 * ldt] = Ts[c][b2];
 }
 
 // W = I on the first RT x RT entries of B_W (clusters with t > 0)
@@ -504,6 +643,35 @@ __device__ inline double block_argmax512(const double* x, int lo, int R, double*
   return r;
 }
 
+// out[a] = A[a, col] - sum_{c < jw} A[a, k0 + c] wr[c] for a in [lo, R): a column
+// brought up to date from the panel (wr = the pivot's row of W_p, in LDS), four
+// rows x eight columns of independent loads at a time.
+__device__ inline void ldl_lazy_col(const double* __restrict__ A, int ld, int col, int k0, int jw, int lo, int R,
+                                    double* __restrict__ out, const double* wr, int tid) {
+  for (int ab = lo + tid; ab < R; ab += 4 * LDL_THREADS) {
+    int ar[4];
+    double acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ar[u] = ab + u * LDL_THREADS;
+      acc[u] = ar[u] < R ? A[ar[u] + (int64_t)col * ld] : 0.0;
+    }
+    for (int l0 = 0; l0 < jw; l0 += 8) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int cidx = k0 + min(l0 + q, jw - 1);
+        const double c = l0 + q < jw ? wr[min(l0 + q, LDL_NB - 1)] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (ar[u] < R) acc[u] -= A[ar[u] + (int64_t)cidx * ld] * c;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (ar[u] < R) out[ar[u]] = acc[u];
+  }
+}
+
 __global__ void k_ldl_init(const int* __restrict__ clusters, BufTab bt, SizeTab sz) {
   const int s = blockIdx.z;
   const int i = clusters[blockIdx.y];
@@ -542,6 +710,7 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl_panel(const int* __restrict
   __shared__ double red[16];
   __shared__ int redi[16];
   __shared__ int s_bad;
+  __shared__ double wr[LDL_NB];
   const double alpha = (1.0 + sqrt(17.0)) / 8.0;
   const int NB = min(LDL_NB, cap - 2);
   if (tid == 0) s_bad = 0;
@@ -551,11 +720,9 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl_panel(const int* __restrict
   while (jw < NB && k < R) {
     double* w = Wp + (int64_t)jw * ld;
     double* u = Wp + (int64_t)(jw + 1) * ld;
-    for (int a = k + tid; a < R; a += LDL_THREADS) {
-      double v = A[a + (int64_t)k * ld];
-      for (int c = 0; c < jw; ++c) v -= A[a + (int64_t)(k0 + c) * ld] * Wp[k + (int64_t)c * ld];
-      w[a] = v;
-    }
+    if (tid < jw) wr[tid] = Wp[k + (int64_t)tid * ld];
+    __syncthreads();
+    ldl_lazy_col(A, ld, k, k0, jw, k, R, w, wr, tid);
     __syncthreads();
     int imax = R;
     const double colmax0 = block_argmax512(w, k + 1, R, red, redi, tid, &imax);
@@ -566,11 +733,9 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl_panel(const int* __restrict
     if (fmax(absakk, colmax) == 0.0 || !(absakk == absakk)) {
       if (tid == 0) s_bad = 1;
     } else if (absakk < alpha * colmax) {
-      for (int a = k + tid; a < R; a += LDL_THREADS) {
-        double v = A[a + (int64_t)imax * ld];
-        for (int c = 0; c < jw; ++c) v -= A[a + (int64_t)(k0 + c) * ld] * Wp[imax + (int64_t)c * ld];
-        u[a] = v;
-      }
+      if (tid < jw) wr[tid] = Wp[imax + (int64_t)tid * ld];
+      __syncthreads();
+      ldl_lazy_col(A, ld, imax, k0, jw, k, R, u, wr, tid);
       __syncthreads();
       double rv = 0.0;
       for (int a = k + tid; a < R; a += LDL_THREADS)
@@ -724,9 +889,11 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl_prep(const int* __restrict_
 
 // X = L^{-1} on the diagonal blocks of width INV_NB (unit lower L = strictly
 // lower part of A); block ib = blockIdx.x.  X lives in B_V (zeroed beforehand).
-constexpr int INV_NB = 128;
 
-__global__ void k_diag_inv(const int* __restrict__ clusters, const int* __restrict__ diag_blk, BufTab bt, SizeTab sz) {
+__global__ __launch_bounds__(64) void k_diag_inv(const int* __restrict__ clusters, const int* __restrict__ diag_blk,
+                                                 BufTab bt, SizeTab sz) {
+  __shared__ double Ls[INV_NB][INV_NB + 1];
+  __shared__ double Xs[INV_NB][INV_NB + 1];
   const int s = blockIdx.z;
   const int i = clusters[blockIdx.y];
   const int R = sz.R[s * sz.N + i];
@@ -734,28 +901,33 @@ __global__ void k_diag_inv(const int* __restrict__ clusters, const int* __restri
   if (r0 >= R) return;
   const int nb = min(INV_NB, R - r0);
   const int ld = bt.ld[B_S];
-  const double* A = addr(bt, B_S, diag_blk[i], s, 0, 0);
-  double* X = addr(bt, B_V, i, s, 0, 0);
+  const double* A = addr(bt, B_S, diag_blk[i], s, r0, r0);
+  double* X = addr(bt, B_V, i, s, r0, r0);
   const int ldx = bt.ld[B_V];
-  for (int c = threadIdx.x; c < nb; c += blockDim.x) {
-    const int gc = r0 + c;
-    X[gc + (int64_t)gc * ldx] = 1.0;
+  const int c = threadIdx.x;
+  for (int b2 = 0; b2 < nb; ++b2)
+    if (c < nb) { Ls[c][b2] = A[c + (int64_t)b2 * ld]; Xs[c][b2] = 0.0; }
+  __syncthreads();
+  if (c < nb) {   // column c of the unit lower inverse, by forward substitution
+    Xs[c][c] = 1.0;
     for (int a = c + 1; a < nb; ++a) {
-      const int ga = r0 + a;
       double v = 0.0;
-      for (int b2 = c; b2 < a; ++b2) v -= A[ga + (int64_t)(r0 + b2) * ld] * X[r0 + b2 + (int64_t)gc * ldx];
-      X[ga + (int64_t)gc * ldx] = v;
+      for (int b2 = c; b2 < a; ++b2) v -= Ls[a][b2] * Xs[b2][c];
+      Xs[a][c] = v;
     }
   }
+  __syncthreads();
+  for (int b2 = 0; b2 < nb; ++b2)
+    if (c < nb) X[c + (int64_t)b2 * ldx] = Xs[c][b2];
 }
 
-// panel state for block row ib of the inversion: a0 = ib*INV_NB, a1 = its height (0 beyond R)
-__global__ void k_set_block(const int* __restrict__ clusters, SizeTab sz, int ib) {
+// panel state for block ib of a blocked inverse: a0 = ib*INV_NB, a1 = its width (0 beyond R, or t)
+__global__ void k_set_block(const int* __restrict__ clusters, SizeTab sz, int ib, int use_t) {
   const int s = blockIdx.z;
   const int i = clusters[blockIdx.y];
   const int N = sz.N;
   if (threadIdx.x == 0) {
-    const int R = sz.R[s * N + i], a0 = ib * INV_NB;
+    const int R = use_t ? sz.t[s * N + i] : sz.R[s * N + i], a0 = ib * INV_NB;
     sz.a0[s * N + i] = a0;
     sz.a1[s * N + i] = a0 < R ? min(INV_NB, R - a0) : 0;
   }
@@ -991,8 +1163,8 @@ void launch_pchol_init(const int* clusters, int n, const BufTab& bt, const SizeT
 void launch_pchol_panel(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, double tau2, int* more, int cap,
                         int nshift, hipStream_t st) {
   if (n <= 0) return;
-  size_t shmem = (size_t)cap * sizeof(double) + RT_THREADS * (sizeof(double) + sizeof(int));
-  hipLaunchKernelGGL(k_pchol_panel, dim3(1, n, nshift), dim3(RT_THREADS), shmem, st, clusters, bt, sz, tau2, more);
+  size_t shmem = (size_t)cap * sizeof(double);
+  hipLaunchKernelGGL(k_pchol_panel, dim3(1, n, nshift), dim3(PC_THREADS), shmem, st, clusters, bt, sz, tau2, more);
 }
 
 void launch_pchol_finish(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st) {
@@ -1003,13 +1175,7 @@ void launch_pchol_finish(const int* clusters, int n, const BufTab& bt, const Siz
 void launch_hqr_panel(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int it, int* more, int nshift,
                       hipStream_t st) {
   if (n <= 0) return;
-  size_t shmem = (size_t)(8 + HB + HB * HB + HB) * sizeof(double);
-  hipLaunchKernelGGL(k_hqr_panel, dim3(1, n, nshift), dim3(RT_THREADS), shmem, st, clusters, bt, sz, it, more);
-}
-
-void launch_set_panel(const int* clusters, int n, const SizeTab& sz, int it, int nshift, hipStream_t st) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_set_panel, dim3(1, n, nshift), dim3(64), 0, st, clusters, sz, it);
+  hipLaunchKernelGGL(k_hqr_panel, dim3(1, n, nshift), dim3(HQ_THREADS), 0, st, clusters, bt, sz, it, more);
 }
 
 void launch_eye(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st) {
@@ -1038,12 +1204,24 @@ void launch_ldl_prep(const int* clusters, int n, const int* diag_blk, const BufT
 void launch_diag_inv(const int* clusters, int n, const int* diag_blk, const BufTab& bt, const SizeTab& sz, int cap,
                      int nshift, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_diag_inv, dim3(cdiv(cap, INV_NB), n, nshift), dim3(128), 0, st, clusters, diag_blk, bt, sz);
+  hipLaunchKernelGGL(k_diag_inv, dim3(cdiv(cap, INV_NB), n, nshift), dim3(64), 0, st, clusters, diag_blk, bt, sz);
 }
 
-void launch_set_block(const int* clusters, int n, const SizeTab& sz, int ib, int nshift, hipStream_t st) {
+void launch_set_block(const int* clusters, int n, const SizeTab& sz, int ib, int use_t, int nshift, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_set_block, dim3(1, n, nshift), dim3(64), 0, st, clusters, sz, ib);
+  hipLaunchKernelGGL(k_set_block, dim3(1, n, nshift), dim3(64), 0, st, clusters, sz, ib, use_t);
+}
+
+void launch_ut_prep(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_ut_prep, dim3(std::max(1u, cdiv((int64_t)cap * cap, 256 * 8)), n, nshift), dim3(256), 0, st,
+                     clusters, bt, sz);
+}
+
+void launch_ut_diag_inv(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift,
+                        hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_ut_diag_inv, dim3(cdiv(cap, INV_NB), n, nshift), dim3(64), 0, st, clusters, bt, sz);
 }
 
 void launch_kform(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st) {
@@ -1059,6 +1237,24 @@ void launch_zero_clusters(const int* clusters, int n, const BufTab& bt, int buf,
 }
 
 int inv_block() { return INV_NB; }
+int ldl_panel_min(int cap) { return std::max(1, std::min(LDL_NB, cap - 2)); }
+
+__global__ void k_colour_max(const int* __restrict__ clusters, int n, SizeTab sz, int* __restrict__ out) {
+  const int s = blockIdx.y;
+  int tm = 0, rm = 0;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int i = clusters[c];
+    tm = max(tm, sz.t[s * sz.N + i]);
+    rm = max(rm, sz.R[s * sz.N + i]);
+  }
+  atomicMax(out, tm);
+  atomicMax(out + 1, rm);
+}
+
+void launch_colour_max(const int* clusters, int n, const SizeTab& sz, int* out, int nshift, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_colour_max, dim3(1, nshift), dim3(256), 0, st, clusters, n, sz, out);
+}
 
 void launch_merge_sizes(const SizeTab& sz, int Np, int nshift, hipStream_t st) {
   hipLaunchKernelGGL(k_merge_sizes, dim3(cdiv(Np, 256), nshift), dim3(256), 0, st, sz, Np);

@@ -21,7 +21,6 @@ void launch_pchol_panel(const int* clusters, int n, const BufTab& bt, const Size
 void launch_pchol_finish(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st);
 void launch_hqr_panel(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int it, int* more, int nshift,
                       hipStream_t st);
-void launch_set_panel(const int* clusters, int n, const SizeTab& sz, int it, int nshift, hipStream_t st);
 void launch_eye(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
 void launch_ldl_init(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st);
 void launch_ldl_panel(const int* clusters, int n, const int* diag_blk, const BufTab& bt, const SizeTab& sz, int* status,
@@ -30,10 +29,17 @@ void launch_ldl_prep(const int* clusters, int n, const int* diag_blk, const BufT
                      unsigned long long* nu, int nshift, hipStream_t st);
 void launch_diag_inv(const int* clusters, int n, const int* diag_blk, const BufTab& bt, const SizeTab& sz, int cap,
                      int nshift, hipStream_t st);
-void launch_set_block(const int* clusters, int n, const SizeTab& sz, int ib, int nshift, hipStream_t st);
+void launch_set_block(const int* clusters, int n, const SizeTab& sz, int ib, int use_t, int nshift, hipStream_t st);
+void launch_ut_prep(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
+void launch_ut_diag_inv(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift,
+                        hipStream_t st);
 void launch_kform(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
 void launch_zero_clusters(const int* clusters, int n, const BufTab& bt, int buf, int cap, int nshift, hipStream_t st);
 int inv_block();
+int ldl_panel_min(int cap);      // fewest pivots an LDL panel takes unless it reaches R
+void launch_colour_max(const int* clusters, int n, const SizeTab& sz, int* out, int nshift, hipStream_t st);
+constexpr int PCHOL_NB = 32;     // pivots per pivoted-Cholesky panel
+constexpr int HQR_NB = 32;       // columns per Householder panel
 void launch_merge_sizes(const SizeTab& sz, int Np, int nshift, hipStream_t st);
 void launch_gather(const GatherItem* items, int n, const BufTab& bt, const SizeTab& sz, int pcap, int nshift, hipStream_t st);
 void launch_next_sizes(const SizeTab& sz, int nshift, hipStream_t st);

@@ -113,13 +113,23 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
         g = item(ref(B_V, i, 0, a0, 0, a1), noref(), dx(DK_RTMA0, i), dx(DK_TREM, i), -1.0, 1.0);
         g.guard = dx(DK_TREM, i);
         cp.hq_v.add(g, {term(ref(B_Z, i, 0, a0), ref(B_W, i), a1)});
-        // W <- W - (W Y_p)(Y_p T_p^T)^T
-        g = item(ref(B_G, i), noref(), dx(DK_RT, i), a1, 1.0, 0.0);
+        // W = I - Y T Y^T with T^{-1} = striu(Y^T Y) + diag(1/beta)
+        const int ti = dx(DK_T, i), rti = dx(DK_RT, i);
+        g = item(ref(B_G, i), noref(), ti, ti, 1.0, 0.0);
+        g.guard = ti;
+        cp.ut_s.add(g, {term(ref(B_V, i), ref(B_V, i), rti)});
+        g = item(ref(B_W, i), noref(), a0, a1, 1.0, 0.0);
         g.guard = a1;
-        cp.w_q.add(g, {term(ref(B_W, i), ref(B_V, i, 0, a0), dx(DK_RTMA0, i))});
-        g = item(ref(B_W, i), noref(), dx(DK_RT, i), dx(DK_RTMA0, i), -1.0, 1.0);
+        cp.ut_t.add(g, {term(ref(B_Z, i), ref(B_G, i, 0, a0), a0)});
+        g = item(ref(B_Z, i, 0, a0), noref(), a0, a1, -1.0, 0.0);
         g.guard = a1;
-        cp.w_w.add(g, {term(ref(B_G, i), ref(B_Z, i, 0, a0), a1)});
+        cp.ut_x.add(g, {term(ref(B_W, i), ref(B_Z, i, a0, a0), a1)});
+        g = item(ref(B_G, i), noref(), rti, ti, 1.0, 0.0);
+        g.guard = ti;
+        cp.ut_u.add(g, {term(ref(B_V, i), ref(B_Z, i), ti)});
+        g = item(ref(B_W, i), noref(), rti, rti, -1.0, 1.0);
+        g.guard = ti;
+        cp.ut_w.add(g, {term(ref(B_G, i), ref(B_V, i), ti)});
         // LDL trailing update A[k:R, k:R] -= L_p W_p^T, k = a0 + a1
         const int db = lp.blk(i, i);
         g = item(ref(B_S, db, a0, a0, a1, a1), noref(), dx(DK_RMK, i), dx(DK_RMK, i), -1.0, 1.0);

@@ -31,8 +31,11 @@ struct ColourPlan {
   GList pc_upd;                // NT: G -= L_p L_p^T after a pivoted-Cholesky panel
   GList hq_z;                  // TN: Z = Y_p^T V_trail (into B_W)
   GList hq_v;                  // NN: V_trail -= (Y_p T_p^T) Z
-  GList w_q;                   // NN: Q = W Y_p (into B_G)
-  GList w_w;                   // NT: W -= Q (Y_p T_p^T)^T
+  GList ut_s;                  // TN: S = Y^T Y (into B_G)
+  GList ut_t;                  // NN: B_W = T[0:a0, 0:a0] S[0:a0, block]
+  GList ut_x;                  // NN: T[0:a0, block] = -B_W T_block
+  GList ut_u;                  // NN: U = Y T (into B_G)
+  GList ut_w;                  // NT: W -= U Y^T
   GList ldl_upd;               // NT: A_trail -= L_p W_p^T after an LDL panel
   GList inv_t;                 // NN: T = L[rows of block ib, 0:a0] X[0:a0, 0:a0]
   GList inv_x;                 // NN: X[block ib, 0:a0] = -X_ii T
