@@ -102,7 +102,7 @@ struct DevList {
 struct DevColour {
   size_t clusters = 0;
   int ncl = 0;
-  DevList pc_upd, hq_z, hq_v, ut_s, ut_t, ut_x, ut_u, ut_w, ldl_upd, inv_t, inv_x;
+  DevList pc_upd, ut_s, ut_t, ut_x, ut_u, ut_w, ldl_upd, inv_t, inv_x;
   DevList rot_rows, rot_cols, trsm;
   size_t rr_copy = 0, rc_copy = 0, tr_copy = 0;
   DevList schur, gm, gt, gg;
@@ -206,7 +206,7 @@ struct h2_matrix_s {
   int max_shifts = 0;
   Profiler prof;
   int* d_more = nullptr;   // per-iteration "more panels needed" counters + colour maxima
-  int* h_more = nullptr;   // pinned host copy (2 ints)
+  int* h_more = nullptr;   // pinned host copy (4 ints)
 
   template <class T>
   const T* dp(size_t off) const { return reinterpret_cast<const T*>(d_plan + off); }
@@ -252,8 +252,6 @@ void upload_plan(h2_matrix A) {
       dc.clusters = b.put(cp.clusters);
       dc.ncl = (int)cp.clusters.size();
       dc.pc_upd = put_list(b, cp.pc_upd);
-      dc.hq_z = put_list(b, cp.hq_z);
-      dc.hq_v = put_list(b, cp.hq_v);
       dc.ut_s = put_list(b, cp.ut_s);
       dc.ut_t = put_list(b, cp.ut_t);
       dc.ut_x = put_list(b, cp.ut_x);
@@ -549,6 +547,9 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     const LevelPlan& lp = A->plan[l];
     const DevLevel& dl = A->dlev[l];
     const int N = lp.N;
+    if (cap > hqr_max_rows())
+      throw NoMem{"cluster dimension " + std::to_string(cap) + " exceeds the supported maximum " +
+                  std::to_string(hqr_max_rows())};
     const size_t bsz = (size_t)cap * cap;
     // level buffers
     size_t nS = (size_t)S * lp.nblk() * bsz, nF = (size_t)S * lp.nfblk() * bsz;
@@ -672,15 +673,14 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
       run(PC_PCHOL, [&] { launch_pchol_finish(cl, dc.ncl, bt, sz, S, st); });
       // largest t and R of the class: exact launch counts from here on
       int* dmx = A->d_more + MORE_SLOTS;
-      HIPCHK(hipMemsetAsync(dmx, 0, 2 * sizeof(int), st));
+      HIPCHK(hipMemsetAsync(dmx, 0, 3 * sizeof(int), st));
       run(PC_PCHOL, [&] { launch_colour_max(cl, dc.ncl, sz, dmx, S, st); });
-      read_back(A, dmx, 2, st);
-      const int tmax = A->h_more[0], rmax = A->h_more[1];
-      // Householder QR of the kept columns, panel by panel
-      for (int it = 0; it * HQR_NB < tmax; ++it) {
+      read_back(A, dmx, 3, st);
+      const int tmax = A->h_more[0], rmax = A->h_more[1], nhqr = A->h_more[2];
+      // Householder QR of the kept columns, panel by panel (LDS-resident panels)
+      for (int it = 0; it < nhqr; ++it) {
         run(PC_HQR, [&] { launch_hqr_panel(cl, dc.ncl, bt, sz, it, dmx, S, st); });
-        gl(PC_HQR_UPD, GEMM_TN, dc.hq_z);
-        gl(PC_HQR_UPD, GEMM_NN, dc.hq_v);
+        run(PC_HQR_UPD, [&] { launch_hqr_apply(cl, dc.ncl, bt, sz, tmax, S, st); });
       }
       // W = I - Y T Y^T (UT transform)
       if (tmax > 0) {
@@ -892,8 +892,8 @@ h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern,
     A->leafcap = 0;
     for (int i = 0; i < (1 << L); ++i) A->leafcap = std::max<int>(A->leafcap, (int)A->T.size[L][i]);
     A->leafcap = round_cap(A->leafcap);
-    HIPCHK(hipMalloc(&A->d_more, (MORE_SLOTS + 2) * sizeof(int)));
-    HIPCHK(hipHostMalloc(&A->h_more, 2 * sizeof(int)));
+    HIPCHK(hipMalloc(&A->d_more, (MORE_SLOTS + 4) * sizeof(int)));
+    HIPCHK(hipHostMalloc(&A->h_more, 4 * sizeof(int)));
     upload_plan(A);
     upload_resident(A);
     build_near_blocks(A);

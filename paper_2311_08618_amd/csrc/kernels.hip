@@ -217,6 +217,28 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Butterfly reduce-scatter of 64 per-lane values over a wave: afterwards lane L
+// holds the wave sum of v[L] in v[0] (63 exchanges instead of 64 x 6).
+template <int OFF>
+__device__ inline void rs_step(double (&v)[64], int lane) {
+  const bool up = (lane & OFF) != 0;
+#pragma unroll
+  for (int m = 0; m < OFF; ++m) {
+    const double keep = up ? v[m + OFF] : v[m];
+    const double send = up ? v[m] : v[m + OFF];
+    v[m] = keep + __shfl_xor(send, OFF, 64);
+  }
+}
+
+__device__ inline void wave_reduce_scatter64(double (&v)[64], int lane) {
+  rs_step<32>(v, lane);
+  rs_step<16>(v, lane);
+  rs_step<8>(v, lane);
+  rs_step<4>(v, lane);
+  rs_step<2>(v, lane);
+  rs_step<1>(v, lane);
+}
+
 // block-wide sum over RT_THREADS threads (4 waves); red has >= 4 slots
 __device__ inline double block_sum(double v, double* red, int tid) {
   v = wave_sum(v);
@@ -356,74 +378,80 @@ __global__ void k_pchol_finish(const int* __restrict__ clusters, BufTab bt, Size
   if (threadIdx.x == 0) {
     const int R = sz.R[s * N + i], t = sz.t[s * N + i];
     sz.R[s * N + i] = R - t;
+    sz.a0[s * N + i] = 0;   // panel state of the Householder QR that follows
+    sz.a1[s * N + i] = 0;
     if (bt.fc) atomicAdd(bt.fc, (unsigned long long)R * (unsigned long long)t * (unsigned long long)(t > 0 ? t - 1 : 0));
   }
 }
 
 constexpr int HQ_THREADS = 256;
+constexpr int HQ_LDS = 16384;   // doubles of LDS holding the panel (RT x width)
 
-// Butterfly reduce-scatter of 64 per-lane values over a wave: afterwards lane L
-// holds the wave sum of v[L] in v[0] (63 exchanges instead of 64 x 6).
-template <int OFF>
-__device__ inline void rs_step(double (&v)[64], int lane) {
-  const bool up = (lane & OFF) != 0;
-#pragma unroll
-  for (int m = 0; m < OFF; ++m) {
-    const double keep = up ? v[m + OFF] : v[m];
-    const double send = up ? v[m] : v[m + OFF];
-    v[m] = keep + __shfl_xor(send, OFF, 64);
-  }
-}
+// Panel width by the number of rows, so that the panel fits in LDS.
+__host__ __device__ inline int hqr_width(int RT) { return RT <= 2048 ? 8 : RT <= 4096 ? 4 : RT <= 8192 ? 2 : 1; }
 
-__device__ inline void wave_reduce_scatter64(double (&v)[64], int lane) {
-  rs_step<32>(v, lane);
-  rs_step<16>(v, lane);
-  rs_step<8>(v, lane);
-  rs_step<4>(v, lane);
-  rs_step<2>(v, lane);
-  rs_step<1>(v, lane);
-}
-
-template <bool FULL>
-__device__ inline void hqr_panel_body(double* __restrict__ V, double* __restrict__ Yt, double* __restrict__ beta, int ld,
-                                      int RT, int k0, int nb, double (*red)[64], double* sums, double* wv, double* rowp,
-                                      double* Tp, double* bp) {
+// One Householder panel of HW columns held in LDS (Ys, column j at Ys + j*LR,
+// rows 0..P0 = RT-1-k0: everything the panel's reflectors touch).  One pass
+// over the rows per column: it applies the previous reflector and, on the
+// updated values, accumulates the norm and the dot products defining the next
+// reflector together with y_j . y_{k-1} (a column of T_p, the UT transform
+// T_p^{-1} = striu(Y_p^T Y_p) + diag(1/beta)); one block reduction per column.
+template <int HW>
+__device__ void hqr_lds_panel(double* __restrict__ V, double* __restrict__ Yt, double* __restrict__ beta, int ld, int RT,
+                              int k0, int nb, double* Ys, double (*red)[64], double* sums, double* wv, double* rowp,
+                              double* Tp, double* bp) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int P0 = RT - 1 - k0, LR = P0 + 1;
+  for (int e0 = 0; e0 < nb * LR; e0 += 8 * HQ_THREADS) {   // eight independent loads in flight per thread
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * HQ_THREADS + tid;
+      const int j = e / LR, a = e - j * LR;
+      x[u] = e < nb * LR ? V[a + (int64_t)(k0 + j) * ld] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * HQ_THREADS + tid;
+      if (e < nb * LR) Ys[e] = x[u];
+    }
+  }
+  __syncthreads();
   double v0prev = 0.0;
   int pprev = -1;
   for (int kk = 0; kk <= nb; ++kk) {
-    const int pcur = kk < nb ? RT - 1 - (k0 + kk) : -1;
+    const int pcur = kk < nb ? P0 - kk : -1;
     const int plim = kk > 0 ? pprev : pcur;
-    const int kx = min(kk, nb - 1), ky = max(kk - 1, 0);
     const double wk = kk < nb ? wv[kk] : 0.0;
-    double acc[64];   // [0, HB): x . V_j   [HB, 2HB): y_j . y_{kk-1}
+    double acc[2 * HW];   // [0, HW): x . V_j    [HW, 2HW): y_j . y_{kk-1}
 #pragma unroll
-    for (int jj = 0; jj < 64; ++jj) acc[jj] = 0.0;
+    for (int jj = 0; jj < 2 * HW; ++jj) acc[jj] = 0.0;
     for (int a = tid; a <= plim; a += HQ_THREADS) {
-      double ym = kk > 0 ? V[a + (int64_t)(k0 + ky) * ld] : 0.0;
+      double vals[HW];
+#pragma unroll
+      for (int jj = 0; jj < HW; ++jj) vals[jj] = jj < nb ? Ys[jj * LR + a] : 0.0;
+      double ym = kk > 0 ? Ys[(kk - 1) * LR + a] : 0.0;
       if (a == pprev) ym = v0prev;
-      double xk = kk < nb && a <= pcur ? V[a + (int64_t)(k0 + kx) * ld] - ym * wk : 0.0;
+      const double xk = (kk < nb && a <= pcur) ? Ys[kk * LR + a] - ym * wk : 0.0;
       const bool anchor = a == pcur;
-      // all loads of the row before any store: the stores go through the same
-      // pointer, so loads issued after them would be serialised behind them
-      double vals[HB];
 #pragma unroll
-      for (int jj = 0; jj < HB; ++jj) vals[jj] = (FULL || jj < nb) ? V[a + (int64_t)(k0 + jj) * ld] : 0.0;
-#pragma unroll
-      for (int jj = 0; jj < HB; ++jj) {
-        if (FULL || jj < nb) {
+      for (int jj = 0; jj < HW; ++jj) {
+        if (jj < nb) {
           const double v = vals[jj] - ym * wv[jj];   // wv[jj] = 0 outside (kk-1, nb)
-          if (kk > 0) V[a + (int64_t)(k0 + jj) * ld] = v;
+          if (kk > 0) Ys[jj * LR + a] = v;
           acc[jj] += xk * v;
-          acc[HB + jj] += ym * v;
+          acc[HW + jj] += ym * v;
           if (anchor) rowp[jj] = v;
         }
       }
     }
-    wave_reduce_scatter64(acc, lane);
-    red[wave][lane] = acc[0];
+#pragma unroll
+    for (int jj = 0; jj < 2 * HW; ++jj) {
+      const double v = wave_sum(acc[jj]);
+      if (lane == 0) red[wave][jj] = v;
+    }
     __syncthreads();
-    if (tid < 64) {
+    if (tid < 2 * HW) {
       double v = 0.0;
       for (int w2 = 0; w2 < HQ_THREADS / 64; ++w2) v += red[w2][tid];
       sums[tid] = v;
@@ -433,7 +461,7 @@ __device__ inline void hqr_panel_body(double* __restrict__ V, double* __restrict
       const int c = kk - 1;
       if (tid < c) {
         double v = 0.0;
-        for (int m = tid; m < c; ++m) v += Tp[tid + m * HB] * sums[HB + m];
+        for (int m = tid; m < c; ++m) v += Tp[tid + m * HB] * sums[HW + m];
         Tp[tid + c * HB] = -bp[c] * v;
       } else if (tid == c) {
         Tp[c + c * HB] = bp[c];
@@ -449,9 +477,9 @@ __device__ inline void hqr_panel_body(double* __restrict__ V, double* __restrict
       const double vn = xn2 - x0 * x0 + v0 * v0;
       const double bk = vn > 0.0 ? 2.0 / vn : 0.0;
       __syncthreads();   // every thread has read wv / rowp of this step
-      if (tid < HB) wv[tid] = (tid > kk && tid < nb) ? bk * (sums[tid] - alpha * rowp[tid]) : 0.0;
+      if (tid < HW) wv[tid] = (tid > kk && tid < nb) ? bk * (sums[tid] - alpha * rowp[tid]) : 0.0;
       if (tid == 0) {
-        V[pcur + (int64_t)(k0 + kk) * ld] = v0;
+        Ys[kk * LR + pcur] = v0;
         bp[kk] = bk;
         beta[k0 + kk] = bk;
       }
@@ -460,53 +488,53 @@ __device__ inline void hqr_panel_body(double* __restrict__ V, double* __restrict
     pprev = pcur;
     __syncthreads();
   }
-  // Per row: the panel's reflectors are zeroed below their anchors (those rows
-  // hold R entries), then Yt = Y_p T_p^T (RT x nb) goes to B_Z columns k0..k0+nb-1
-  // (T_p is upper triangular and zero elsewhere, so every row sums over all b2).
+  // the reflectors back to V (zero below their anchors: those rows hold R
+  // entries), and Yt = Y_p T_p^T (RT x nb) to B_Z columns k0 .. k0+nb-1
   for (int a = tid; a < RT; a += HQ_THREADS) {
-    double y[HB];
+    double y[HW];
 #pragma unroll
-    for (int jj = 0; jj < HB; ++jj)
-      y[jj] = ((FULL || jj < nb) && a <= RT - 1 - (k0 + jj)) ? V[a + (int64_t)(k0 + jj) * ld] : 0.0;
+    for (int jj = 0; jj < HW; ++jj) y[jj] = (jj < nb && a <= P0 - jj) ? Ys[jj * LR + a] : 0.0;
 #pragma unroll
-    for (int jj = 0; jj < HB; ++jj)
-      if ((FULL || jj < nb) && a > RT - 1 - (k0 + jj)) V[a + (int64_t)(k0 + jj) * ld] = 0.0;
-#pragma unroll 1
-    for (int c = 0; c < nb; ++c) {
-      double v = 0.0;
+    for (int jj = 0; jj < HW; ++jj)
+      if (jj < nb) V[a + (int64_t)(k0 + jj) * ld] = y[jj];
 #pragma unroll
-      for (int b2 = 0; b2 < HB; ++b2) v += y[b2] * Tp[c + b2 * HB];   // T^T[b2][c] = T[c][b2]
-      Yt[a + (int64_t)(k0 + c) * ld] = v;
+    for (int c = 0; c < HW; ++c) {
+      if (c < nb) {
+        double v = 0.0;
+#pragma unroll
+        for (int b2 = c; b2 < HW; ++b2) v += y[b2] * Tp[c + b2 * HB];   // T^T[b2][c] = T[c][b2]
+        Yt[a + (int64_t)(k0 + c) * ld] = v;
+      }
     }
   }
 }
 
-// Panel `it` of the Householder QR: columns k0 = it*HB .. k0+nb-1 of V (RT x t).
-// One pass over the rows per column: it applies the previous reflector to the
-// panel and, on the updated values, accumulates the norm and the dot products
-// that define the next reflector together with y_j . y_{k-1} (a column of T_p,
-// T_p^{-1} = striu(Y_p^T Y_p) + diag(1/beta)); one block reduction per column.
-// beta goes to B_SIGN (used to form W afterwards).
+// Next Householder panel of every cluster of a colour class: columns
+// k0 = a0 + a1 .. k0 + nb - 1 of V (RT x t), nb = hqr_width(RT) or what is left.
+// Sets a0 = k0, a1 = nb for the trailing update (a1 = 0 when done); beta goes
+// to B_SIGN (used to form W afterwards).
 __global__ __launch_bounds__(HQ_THREADS) void k_hqr_panel(const int* __restrict__ clusters, BufTab bt, SizeTab sz, int it,
                                                           int* __restrict__ more) {
+  __shared__ double Ys[HQ_LDS];
   __shared__ double red[HQ_THREADS / 64][64];
   __shared__ double sums[64];
-  __shared__ double wv[HB];       // beta (y . V_j) of the current reflector, 0 outside the live columns
-  __shared__ double rowp[HB];     // anchor row of the next reflector, after the update
+  __shared__ double wv[HB];
+  __shared__ double rowp[HB];
   __shared__ double Tp[HB * HB];
   __shared__ double bp[HB];
   const int s = blockIdx.z;
   const int i = clusters[blockIdx.y];
   const int N = sz.N;
   const int t = sz.t[s * N + i];
-  const int k0 = it * HB;
+  const int k0 = sz.a0[s * N + i] + sz.a1[s * N + i];
   const int tid = threadIdx.x;
   if (k0 >= t) {
     if (tid == 0) { sz.a0[s * N + i] = k0; sz.a1[s * N + i] = 0; }
     return;
   }
-  const int nb = min(HB, t - k0);
   const int RT = sz.R[s * N + i] + t;
+  const int hw = hqr_width(RT);
+  const int nb = min(hw, t - k0);
   if (bt.fc && tid == 0) {   // Householder QR flops of this panel's columns
     double f = 0.0;
     for (int k = k0; k < k0 + nb; ++k) f += 4.0 * (double)(RT - k) * (double)(t - k);
@@ -519,12 +547,81 @@ __global__ __launch_bounds__(HQ_THREADS) void k_hqr_panel(const int* __restrict_
   for (int e = tid; e < HB * HB; e += HQ_THREADS) Tp[e] = 0.0;
   if (tid < HB) { wv[tid] = 0.0; rowp[tid] = 0.0; bp[tid] = 0.0; }
   __syncthreads();
-  if (nb == HB) hqr_panel_body<true>(V, Yt, beta, ld, RT, k0, nb, red, sums, wv, rowp, Tp, bp);
-  else hqr_panel_body<false>(V, Yt, beta, ld, RT, k0, nb, red, sums, wv, rowp, Tp, bp);
+  if (RT <= HQ_LDS) {
+    if (hw == 8) hqr_lds_panel<8>(V, Yt, beta, ld, RT, k0, nb, Ys, red, sums, wv, rowp, Tp, bp);
+    else if (hw == 4) hqr_lds_panel<4>(V, Yt, beta, ld, RT, k0, nb, Ys, red, sums, wv, rowp, Tp, bp);
+    else if (hw == 2) hqr_lds_panel<2>(V, Yt, beta, ld, RT, k0, nb, Ys, red, sums, wv, rowp, Tp, bp);
+    else hqr_lds_panel<1>(V, Yt, beta, ld, RT, k0, nb, Ys, red, sums, wv, rowp, Tp, bp);
+  }
+  __syncthreads();
   if (tid == 0) {
     sz.a0[s * N + i] = k0;
     sz.a1[s * N + i] = nb;
     if (k0 + nb < t) atomicAdd(more, 1);
+  }
+}
+
+// Trailing update after a Householder panel: V[:, a0+a1 : t] <- H_p^T V (H_p
+// the panel's block reflector I - Y_p T_p Y_p^T), i.e. V -= Yt (Y_p^T V) with
+// Yt = Y_p T_p^T in B_Z.  A workgroup owns HQA_CW trailing columns: one pass over
+// the rows for Z = Y_p^T V (butterfly reduction), one pass for V -= Yt Z.  Rows
+// below RT-1-a0 are outside the panel's reflectors and untouched.
+constexpr int HQA_CW = 8;
+
+__global__ __launch_bounds__(256) void k_hqr_apply(const int* __restrict__ clusters, BufTab bt, SizeTab sz) {
+  __shared__ double red[4][64];
+  __shared__ double Zs[64];
+  const int s = blockIdx.z;
+  const int i = clusters[blockIdx.y];
+  const int N = sz.N;
+  const int a1 = sz.a1[s * N + i];
+  if (a1 == 0) return;
+  const int t = sz.t[s * N + i], a0 = sz.a0[s * N + i];
+  const int j0 = a0 + a1 + blockIdx.x * HQA_CW;
+  if (j0 >= t) return;
+  const int cw = min(HQA_CW, t - j0);
+  const int RT = sz.R[s * N + i] + t;
+  const int P = RT - 1 - a0;
+  const int ld = bt.ld[B_V];
+  double* V = addr(bt, B_V, i, s, 0, 0);
+  const double* Yt = addr(bt, B_Z, i, s, 0, 0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double acc[64];   // acc[k*8 + j] = sum_a Y[a, a0+k] V[a, j0+j]
+#pragma unroll
+  for (int q = 0; q < 64; ++q) acc[q] = 0.0;
+  for (int a = tid; a <= P; a += 256) {
+    double y[8], v[8];
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) y[k2] = k2 < a1 ? V[a + (int64_t)(a0 + k2) * ld] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = j < cw ? V[a + (int64_t)(j0 + j) * ld] : 0.0;
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[k2 * 8 + j] += y[k2] * v[j];
+  }
+  wave_reduce_scatter64(acc, lane);
+  red[wave][lane] = acc[0];
+  __syncthreads();
+  if (tid < 64) Zs[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+  __syncthreads();
+  for (int a = tid; a <= P; a += 256) {
+    double yt[8], v[8];
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) yt[k2] = k2 < a1 ? Yt[a + (int64_t)(a0 + k2) * ld] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = j < cw ? V[a + (int64_t)(j0 + j) * ld] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      double d = 0.0;
+#pragma unroll
+      for (int k2 = 0; k2 < 8; ++k2) d += yt[k2] * Zs[k2 * 8 + j];
+      if (j < cw) V[a + (int64_t)(j0 + j) * ld] = v[j] - d;
+    }
+  }
+  if (bt.fc && blockIdx.x == 0 && tid == 0) {
+    const double ntr = (double)(t - a0 - a1);
+    atomicAdd(bt.fc, (unsigned long long)(4.0 * (double)(P + 1) * (double)a1 * ntr));
   }
 }
 
@@ -1237,18 +1334,28 @@ void launch_zero_clusters(const int* clusters, int n, const BufTab& bt, int buf,
 }
 
 int inv_block() { return INV_NB; }
+
+void launch_hqr_apply(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int tmax, int nshift, hipStream_t st) {
+  if (n <= 0 || tmax <= 0) return;
+  hipLaunchKernelGGL(k_hqr_apply, dim3(cdiv(tmax, HQA_CW), n, nshift), dim3(256), 0, st, clusters, bt, sz);
+}
+int hqr_max_rows() { return HQ_LDS; }
 int ldl_panel_min(int cap) { return std::max(1, std::min(LDL_NB, cap - 2)); }
 
 __global__ void k_colour_max(const int* __restrict__ clusters, int n, SizeTab sz, int* __restrict__ out) {
   const int s = blockIdx.y;
-  int tm = 0, rm = 0;
+  int tm = 0, rm = 0, pm = 0;
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     const int i = clusters[c];
-    tm = max(tm, sz.t[s * sz.N + i]);
-    rm = max(rm, sz.R[s * sz.N + i]);
+    const int t = sz.t[s * sz.N + i], R = sz.R[s * sz.N + i];
+    tm = max(tm, t);
+    rm = max(rm, R);
+    const int hw = hqr_width(R + t);
+    pm = max(pm, (t + hw - 1) / hw);
   }
   atomicMax(out, tm);
   atomicMax(out + 1, rm);
+  atomicMax(out + 2, pm);
 }
 
 void launch_colour_max(const int* clusters, int n, const SizeTab& sz, int* out, int nshift, hipStream_t st) {

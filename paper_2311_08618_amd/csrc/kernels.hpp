@@ -36,10 +36,12 @@ void launch_ut_diag_inv(const int* clusters, int n, const BufTab& bt, const Size
 void launch_kform(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
 void launch_zero_clusters(const int* clusters, int n, const BufTab& bt, int buf, int cap, int nshift, hipStream_t st);
 int inv_block();
+void launch_hqr_apply(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int tmax, int nshift, hipStream_t st);
+int hqr_max_rows();              // largest cluster dimension the LDS-resident Householder panel takes
 int ldl_panel_min(int cap);      // fewest pivots an LDL panel takes unless it reaches R
 void launch_colour_max(const int* clusters, int n, const SizeTab& sz, int* out, int nshift, hipStream_t st);
 constexpr int PCHOL_NB = 32;     // pivots per pivoted-Cholesky panel
-constexpr int HQR_NB = 32;       // columns per Householder panel
+constexpr int HQR_NB = 8;        // widest Householder panel (columns held in LDS)
 void launch_merge_sizes(const SizeTab& sz, int Np, int nshift, hipStream_t st);
 void launch_gather(const GatherItem* items, int n, const BufTab& bt, const SizeTab& sz, int pcap, int nshift, hipStream_t st);
 void launch_next_sizes(const SizeTab& sz, int nshift, hipStream_t st);

@@ -106,13 +106,6 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
         g = item(ref(B_G, i), noref(), dx(DK_R, i), dx(DK_R, i), -1.0, 1.0);
         g.guard = dx(DK_TMA0, i);
         cp.pc_upd.add(g, {term(ref(B_V, i, 0, a0), ref(B_V, i, 0, a0), dx(DK_TMA0, i))});
-        // Householder QR trailing update
-        g = item(ref(B_W, i), noref(), a1, dx(DK_TREM, i), 1.0, 0.0);
-        g.guard = dx(DK_TREM, i);
-        cp.hq_z.add(g, {term(ref(B_V, i, 0, a0), ref(B_V, i, 0, a0, 0, a1), dx(DK_RTMA0, i))});
-        g = item(ref(B_V, i, 0, a0, 0, a1), noref(), dx(DK_RTMA0, i), dx(DK_TREM, i), -1.0, 1.0);
-        g.guard = dx(DK_TREM, i);
-        cp.hq_v.add(g, {term(ref(B_Z, i, 0, a0), ref(B_W, i), a1)});
         // W = I - Y T Y^T with T^{-1} = striu(Y^T Y) + diag(1/beta)
         const int ti = dx(DK_T, i), rti = dx(DK_RT, i);
         g = item(ref(B_G, i), noref(), ti, ti, 1.0, 0.0);

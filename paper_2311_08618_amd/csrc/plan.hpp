@@ -29,8 +29,6 @@ struct SumList {
 struct ColourPlan {
   std::vector<int> clusters;
   GList pc_upd;                // NT: G -= L_p L_p^T after a pivoted-Cholesky panel
-  GList hq_z;                  // TN: Z = Y_p^T V_trail (into B_W)
-  GList hq_v;                  // NN: V_trail -= (Y_p T_p^T) Z
   GList ut_s;                  // TN: S = Y^T Y (into B_G)
   GList ut_t;                  // NN: B_W = T[0:a0, 0:a0] S[0:a0, block]
   GList ut_x;                  // NN: T[0:a0, block] = -B_W T_block
