@@ -36,6 +36,9 @@ __global__ void k_fill_int(int* p, int64_t n, int v) {
 // ------------------------------------------------------------- GEMM (FP64 MFMA)
 // C[M x N] = beta*C + alpha * sum_t op(A_t) diag(w_t) op(B_t), 64x64 tiles,
 // 256 threads = 4 waves in 2x2, each wave 32x32 = 2x2 MFMA 16x16x4 f64 tiles.
+// K runs in steps of GK through two LDS buffers: the next step's tiles are
+// fetched into registers while the current step is multiplied (one barrier
+// per step).
 // op(A): TA ? A^T (A stored K x M) : A (M x K);  op(B): TB ? B^T (B stored N x K) : B (K x N).
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -56,8 +59,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, c
     for (int tt = 0; tt < it.nt; ++tt) kk += (unsigned long long)max(0, dev_eval(terms[it.t0 + tt].K, sz, s));
     atomicAdd(bt.fc, 2ull * (unsigned long long)M * (unsigned long long)N * kk);
   }
-  __shared__ double As[GK][GT + 1];
-  __shared__ double Bs[GK][GT + 1];
+  __shared__ double As[2][GK][GT + 1];
+  __shared__ double Bs[2][GK][GT + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   v4d acc[2][2];
@@ -75,41 +78,60 @@ __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, c
     const double* B = addr(bt, tm.b.buf, tm.b.blk, s, br, bc);
     const int lda = bt.ld[tm.a.buf], ldb = bt.ld[tm.b.buf];
     const double* w = tm.wbuf >= 0 ? addr(bt, tm.wbuf, 0, s, 0, 0) + (int64_t)tm.wblk * bt.bs[tm.wbuf] : nullptr;
-    for (int k0 = 0; k0 < K; k0 += GK) {
-      // A tile: GT (m) x GK (k)
-      for (int e = tid; e < GT * GK; e += 256) {
+    const int nk = (K + GK - 1) / GK;
+    // this thread's four elements of each tile: A as (mm, kk), B as (kk, nn)
+    double ra[4], rb[4];
+    auto gload = [&](int kt) {
+      const int k0 = kt * GK;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int e = tid + 256 * r;
         int mm, kk;
         if (TA) { kk = e % GK; mm = e / GK; } else { mm = e % GT; kk = e / GT; }
-        int gm = m0 + mm, gk = k0 + kk;
+        const int gm = m0 + mm, gk = k0 + kk;
         double v = 0.0;
         if (gm < M && gk < K) {
           v = TA ? A[gk + (int64_t)gm * lda] : A[gm + (int64_t)gk * lda];
           if (w) v *= w[gk];
         }
-        As[kk][mm] = v;
+        ra[r] = v;
+        int nn, kb;
+        if (TB) { nn = e % GT; kb = e / GT; } else { kb = e % GK; nn = e / GK; }
+        const int gn = n0 + nn, gkb = k0 + kb;
+        rb[r] = (gn < N && gkb < K) ? (TB ? B[gn + (int64_t)gkb * ldb] : B[gkb + (int64_t)gn * ldb]) : 0.0;
       }
-      // B tile: GK (k) x GT (n)
-      for (int e = tid; e < GT * GK; e += 256) {
-        int nn, kk;
-        if (TB) { nn = e % GT; kk = e / GT; } else { kk = e % GK; nn = e / GK; }
-        int gn = n0 + nn, gk = k0 + kk;
-        double v = 0.0;
-        if (gn < N && gk < K) v = TB ? B[gn + (int64_t)gk * ldb] : B[gk + (int64_t)gn * ldb];
-        Bs[kk][nn] = v;
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int e = tid + 256 * r;
+        int mm, kk;
+        if (TA) { kk = e % GK; mm = e / GK; } else { mm = e % GT; kk = e / GT; }
+        As[buf][kk][mm] = ra[r];
+        int nn, kb;
+        if (TB) { nn = e % GT; kb = e / GT; } else { kb = e % GK; nn = e / GK; }
+        Bs[buf][kb][nn] = rb[r];
       }
-      __syncthreads();
+    };
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int cur = kt & 1;
+      if (kt + 1 < nk) gload(kt + 1);   // next tiles in flight during the products
 #pragma unroll
       for (int kk = 0; kk < GK; kk += 4) {
         const int kr = kk + (lane >> 4);
-        double a0 = As[kr][wm * 32 + (lane & 15)];
-        double a1 = As[kr][wm * 32 + 16 + (lane & 15)];
-        double b0 = Bs[kr][wn * 32 + (lane & 15)];
-        double b1 = Bs[kr][wn * 32 + 16 + (lane & 15)];
+        const double a0 = As[cur][kr][wm * 32 + (lane & 15)];
+        const double a1 = As[cur][kr][wm * 32 + 16 + (lane & 15)];
+        const double b0 = Bs[cur][kr][wn * 32 + (lane & 15)];
+        const double b1 = Bs[cur][kr][wn * 32 + 16 + (lane & 15)];
         acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
         acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
       }
+      if (kt + 1 < nk) sstore(cur ^ 1);
       __syncthreads();
     }
   }
