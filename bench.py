@@ -29,7 +29,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
 HBM_PEAK_GBS = 8000.0
-GEMM_CLASSES = {"recompress_w", "rotate", "elimination", "schur", "fillin_gram", "merge"}
+GEMM_CLASSES = {"recompress_w", "rotate", "elimination", "schur", "fillin_gram", "merge_fillin", "merge_transfer",
+                "pivot_ldl_inverse", "recompress_pchol_update", "pivot_ldl_update"}
 
 
 def cpu_baseline(n_sample: int = 4096, shifts: int = 4, n_target: int = 262144) -> dict:

@@ -120,12 +120,18 @@ struct GTerm {
 
 // One output block: C = beta*C + alpha * sum_t op(A_t) diag(w_t) op(B_t)
 // optional C2 = beta*C2 + alpha*(...)^T (the transposed twin of a symmetric pair)
+// Segmented output (c2.buf == SEG_OUT): rows [0, rsplit) go to the origin of c,
+// rows [rsplit, M) to the row origin c2.r0 + c2.r1; columns likewise with
+// csplit and c2.c0 + c2.c1 (same buffer and block as c).
+constexpr int SEG_OUT = -2;
+
 struct GItem {
   Ref c, c2;        // c2.buf = -1 when absent; c.blk = -1: scratch slot of the item
   int M, N;         // size expressions
   int t0, nt;       // term range
   double alpha, beta;
   int guard;        // size expression; the item is skipped when it evaluates to 0 (-1: none)
+  int rsplit, csplit;  // size expressions of a segmented output
 };
 
 // Copy of a scratch slot back into a block: X[r0 + a][c0 + b] = RS[slot][a][b]

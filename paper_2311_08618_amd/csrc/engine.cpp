@@ -119,13 +119,14 @@ struct DevLevel {
 
 // Kernel classes of the level engine, for the diagnostic profiler.
 enum ProfClass {
-  PC_INIT = 0, PC_PCHOL, PC_PCHOL_UPD, PC_HQR, PC_HQR_UPD, PC_WFORM, PC_ROTATE, PC_LDL, PC_LDL_UPD, PC_LDL_INV, PC_ELIM,
-  PC_COPY, PC_SCHUR, PC_GRAM, PC_MERGE, PC_N
+  PC_INIT = 0, PC_PCHOL, PC_PCHOL_UPD, PC_HQR, PC_HQR_UPD, PC_WFORM, PC_ROTATE, PC_LDL, PC_LDL_UPD, PC_LDL_INV,
+  PC_LDL_OP, PC_ELIM, PC_COPY, PC_SCHUR, PC_GRAM, PC_MERGE, PC_MERGE_FILL, PC_MERGE_E, PC_N
 };
 const char* const kProfNames[PC_N] = {"init", "recompress_pchol", "recompress_pchol_update", "recompress_hqr",
                                       "recompress_hqr_update", "recompress_w", "rotate", "pivot_ldl",
-                                      "pivot_ldl_update", "pivot_ldl_inverse", "elimination", "copyback", "schur",
-                                      "fillin_gram", "merge"};
+                                      "pivot_ldl_update", "pivot_ldl_inverse", "pivot_ldl_operator", "elimination",
+                                      "copyback", "schur", "fillin_gram", "merge_gather", "merge_fillin",
+                                      "merge_transfer"};
 
 // Brackets kernel launches with HIP events on the handle's stream and keeps a
 // device array of per-class algorithmic flop counters.
@@ -705,16 +706,16 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
         run(PC_LDL, [&] { launch_ldl_panel(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, w.status, dmx, S, st); });
         gl(PC_LDL_UPD, GEMM_NT, dc.ldl_upd);
       }
-      run(PC_LDL, [&] { launch_ldl_prep(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, w.nu, S, st); });
+      run(PC_LDL_OP, [&] { launch_ldl_prep(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, w.nu, S, st); });
       // X = L^{-1}: diagonal blocks, then block rows by GEMMs
-      run(PC_LDL, [&] { launch_zero_clusters(cl, dc.ncl, bt, B_V, cap, S, st); });
-      run(PC_LDL, [&] { launch_diag_inv(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, cap, S, st); });
+      run(PC_LDL_OP, [&] { launch_zero_clusters(cl, dc.ncl, bt, B_V, cap, S, st); });
+      run(PC_LDL_OP, [&] { launch_diag_inv(cl, dc.ncl, A->dp<int>(dl.diag_blk), bt, sz, cap, S, st); });
       for (int ib = 1; ib * inv_block() < rmax; ++ib) {
-        run(PC_LDL, [&] { launch_set_block(cl, dc.ncl, sz, ib, 0, S, st); });
+        run(PC_LDL_OP, [&] { launch_set_block(cl, dc.ncl, sz, ib, 0, S, st); });
         gl(PC_LDL_INV, GEMM_NN, dc.inv_t, inv_block());
         gl(PC_LDL_INV, GEMM_NN, dc.inv_x, inv_block());
       }
-      run(PC_LDL, [&] { launch_kform(cl, dc.ncl, bt, sz, cap, S, st); });
+      run(PC_LDL_OP, [&] { launch_kform(cl, dc.ncl, bt, sz, cap, S, st); });
       chunked(PC_ELIM, GEMM_NT, dc.trsm, dc.tr_copy);
       gl(PC_SCHUR, GEMM_NT, dc.schur);
       gl(PC_GRAM, GEMM_TN, dc.gm);
@@ -764,15 +765,16 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     for (const MergeChunk& ch : mp.chunks) {
       run(PC_MERGE, [&] { launch_gather(A->dp<GatherItem>(dl.gather) + ch.g0, ch.g1 - ch.g0, bt, sz, pcap, S, st); });
       if (ch.f1 > ch.f0)
-        run(PC_MERGE, [&] {
+        run(PC_MERGE_FILL, [&] {
           launch_gemm(GEMM_NT, A->dp<GItem>(dl.fill.items) + ch.f0, ch.f1 - ch.f0, A->dp<GTerm>(dl.fill.terms), bt, sz,
                       pcap, pcap, S, st);
         });
-      run(PC_MERGE, [&] {
+      run(PC_MERGE, [&] { launch_merge_nn(A->dp<GatherItem>(dl.gather) + ch.g0, ch.g1 - ch.g0, bt, sz, pcap, S, st); });
+      run(PC_MERGE_E, [&] {
         launch_gemm(GEMM_NN, A->dp<GItem>(dl.tr1.items) + ch.a0, ch.a1 - ch.a0, A->dp<GTerm>(dl.tr1.terms), bt, sz, pcap,
                     emax, S, st);
       });
-      run(PC_MERGE, [&] {
+      run(PC_MERGE_E, [&] {
         launch_gemm(GEMM_TN, A->dp<GItem>(dl.tr2.items) + ch.b0, ch.b1 - ch.b0, A->dp<GTerm>(dl.tr2.terms), bt, sz, emax,
                     pcap, S, st);
       });

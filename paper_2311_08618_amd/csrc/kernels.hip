@@ -137,11 +137,17 @@ __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, c
   }
   int cr, cc;
   ref_origin(it.c, sz, s, &cr, &cc);
-  double* C = addr(bt, it.c.buf, it.c.blk >= 0 ? it.c.blk : (int)blockIdx.y + slot_base, s, cr, cc);
+  double* C = addr(bt, it.c.buf, it.c.blk >= 0 ? it.c.blk : (int)blockIdx.y + slot_base, s, 0, 0);
   const int ldc = bt.ld[it.c.buf];
   double* C2 = nullptr;
   int ldc2 = 0;
-  if (it.c2.buf >= 0) {
+  const bool seg = it.c2.buf == SEG_OUT;
+  int rs = M, cs = N, r2o = 0, c2o = 0;
+  if (seg) {
+    rs = dev_eval(it.rsplit, sz, s);
+    cs = dev_eval(it.csplit, sz, s);
+    ref_origin(it.c2, sz, s, &r2o, &c2o);
+  } else if (it.c2.buf >= 0) {
     int r2, c2;
     ref_origin(it.c2, sz, s, &r2, &c2);
     C2 = addr(bt, it.c2.buf, it.c2.blk, s, r2, c2);
@@ -154,7 +160,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, c
         int c = n0 + wn * 32 + j * 16 + (lane & 15);
         if (r < M && c < N) {
           double x = it.alpha * acc[i][j][v];
-          double* p = C + r + (int64_t)c * ldc;
+          const int dr = r < rs ? cr + r : r2o + (r - rs), dcol = c < cs ? cc + c : c2o + (c - cs);
+          double* p = C + dr + (int64_t)dcol * ldc;
           *p = it.beta != 0.0 ? it.beta * *p + x : x;
           if (C2) {
             double* q = C2 + c + (int64_t)r * ldc2;
@@ -1118,12 +1125,9 @@ __global__ void k_gather(const GatherItem* __restrict__ items, BufTab bt, SizeTa
   const int tp1 = sz.t[s * N + 2 * p], tp2 = sz.t[s * N + 2 * p + 1];
   const int tq1 = sz.t[s * N + 2 * q], tq2 = sz.t[s * N + 2 * q + 1];
   const int rp1 = sz.r0[2 * p], rq1 = sz.r0[2 * q];
-  const int tnp = tp1 + tp2, tnq = tq1 + tq2;
   const int mp = sz.pm[s * sz.Np + p], mq = sz.pm[s * sz.Np + q];
   double* H = addr(bt, B_HAT, g.out_blk, s, 0, 0);
   const int ldh = bt.ld[B_HAT];
-  double* O = addr(bt, g.dst_buf, g.dst_blk, s, 0, 0);
-  const int ldo = bt.ld[g.dst_buf];
   const int ldc = bt.ld[B_CPL];
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)mp * mq; e += (int64_t)gridDim.x * blockDim.x) {
     const int row = (int)(e % mp), col = (int)(e / mp);
@@ -1140,8 +1144,25 @@ __global__ void k_gather(const GatherItem* __restrict__ items, BufTab bt, SizeTa
       const int tc = sz.t[s * N + c], td = sz.t[s * N + d];
       if (rr >= tc && cc >= td) v += bt.p[B_CPL][(int64_t)g.cpl_blk[slot] * bt.bs[B_CPL] + (rr - tc) + (int64_t)(cc - td) * ldc];
     }
-    if (row < tnp && col < tnq) O[row + (int64_t)col * ldo] = v;
-    else H[row + (int64_t)col * ldh] = v;
+    H[row + (int64_t)col * ldh] = v;
+  }
+}
+
+// The new-new part of a merged parent block is final once the fill-in is in:
+// out[0:tn_p, 0:tn_q] = HAT[0:tn_p, 0:tn_q].
+__global__ void k_merge_nn(const GatherItem* __restrict__ items, BufTab bt, SizeTab sz) {
+  const int s = blockIdx.z;
+  const GatherItem g = items[blockIdx.y];
+  const int N = sz.N;
+  const int tnp = sz.t[s * N + 2 * g.p] + sz.t[s * N + 2 * g.p + 1];
+  const int tnq = sz.t[s * N + 2 * g.q] + sz.t[s * N + 2 * g.q + 1];
+  const double* H = addr(bt, B_HAT, g.out_blk, s, 0, 0);
+  const int ldh = bt.ld[B_HAT];
+  double* O = addr(bt, g.dst_buf, g.dst_blk, s, 0, 0);
+  const int ldo = bt.ld[g.dst_buf];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)tnp * tnq; e += (int64_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e % tnp), col = (int)(e / tnp);
+    O[row + (int64_t)col * ldo] = H[row + (int64_t)col * ldh];
   }
 }
 
@@ -1394,6 +1415,16 @@ void launch_gather(const GatherItem* items, int n, const BufTab& bt, const SizeT
   for (int i0 = 0; i0 < n; i0 += 65535) {
     int ni = std::min(65535, n - i0);
     hipLaunchKernelGGL(k_gather, dim3(std::max(1u, cdiv((int64_t)pcap * pcap, 256 * 8)), ni, nshift), dim3(256), 0, st,
+                       items + i0, bt, sz);
+  }
+}
+
+void launch_merge_nn(const GatherItem* items, int n, const BufTab& bt, const SizeTab& sz, int pcap, int nshift,
+                     hipStream_t st) {
+  if (n <= 0) return;
+  for (int i0 = 0; i0 < n; i0 += 65535) {
+    int ni = std::min(65535, n - i0);
+    hipLaunchKernelGGL(k_merge_nn, dim3(std::max(1u, cdiv((int64_t)pcap * pcap, 256 * 8)), ni, nshift), dim3(256), 0, st,
                        items + i0, bt, sz);
   }
 }

@@ -44,6 +44,8 @@ constexpr int PCHOL_NB = 32;     // pivots per pivoted-Cholesky panel
 constexpr int HQR_NB = 8;        // widest Householder panel (columns held in LDS)
 void launch_merge_sizes(const SizeTab& sz, int Np, int nshift, hipStream_t st);
 void launch_gather(const GatherItem* items, int n, const BufTab& bt, const SizeTab& sz, int pcap, int nshift, hipStream_t st);
+void launch_merge_nn(const GatherItem* items, int n, const BufTab& bt, const SizeTab& sz, int pcap, int nshift,
+                     hipStream_t st);
 void launch_next_sizes(const SizeTab& sz, int nshift, hipStream_t st);
 void launch_leaf_init(const BufTab& bt, int nblk, const int* blk_diag_m, const double* sigma, int cap, int nshift,
                       hipStream_t st);

@@ -41,6 +41,7 @@ static GTerm term(Ref a, Ref b, int K, int wbuf = -1, int wblk = 0) {
 static GItem item(Ref c, Ref c2, int M, int N, double alpha, double beta) {
   GItem g;
   g.c = c; g.c2 = c2; g.M = M; g.N = N; g.alpha = alpha; g.beta = beta; g.t0 = 0; g.nt = 0; g.guard = -1;
+  g.rsplit = 0; g.csplit = 0;
   return g;
 }
 
@@ -262,9 +263,9 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
       const int slot = h % MERGE_CHUNK;
       // Parent coordinates [new c1 | new c2 | E^T (old c1, old c2)]: the new
       // directions pass through, only the old skeleton coordinates meet E.
-      // The children block is gathered in the permuted order
-      // [new c1 | new c2 | old c1 | old c2]; its new-new part is final and
-      // goes straight to the output block, the rest to the slot in B_HAT.
+      // The children block is gathered into its slot of B_HAT in the permuted
+      // order [new c1 | new c2 | old c1 | old c2]; once the fill-in is added
+      // its new-new part is final and is copied to the output block.
       const int obuf = is_near ? B_SN : B_FN;
       const int oblk = is_near ? pp.blk(p, q) : pp.fblk(p, q);
       const int tnp = dx(DK_TN, p), tnq = dx(DK_TN, q);
@@ -290,21 +291,19 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
             std::set_intersection(T.near[l][c].begin(), T.near[l][c].end(), T.near[l][d].begin(),
                                   T.near[l][d].end(), std::back_inserter(cn));
             if (!cn.empty()) {
+              // one product per child pair, its rows and columns scattered to
+              // the new and old segments of the permuted layout
               const int rn = a ? dx(DK_T, 2 * p) : 0, ro = a ? dconst(B.r[l][2 * p]) : 0;
               const int cnn = b ? dx(DK_T, 2 * q) : 0, co = b ? dconst(B.r[l][2 * q]) : 0;
-              for (int ra = 0; ra < 2; ++ra)
-                for (int cb = 0; cb < 2; ++cb) {
-                  // ra/cb = 0: new directions of c/d, 1: old skeleton coordinates
-                  std::vector<GTerm> ts;
-                  for (int i : cn)
-                    ts.push_back(term(ref(B_S, lp.blk(c, i), ra ? dx(DK_RT, c) : dx(DK_R, c), 0),
-                                      ref(B_S, lp.blk(d, i), cb ? dx(DK_RT, d) : dx(DK_R, d), 0), dx(DK_R, i), B_SIGN, i));
-                  Ref out = (ra == 0 && cb == 0) ? ref(obuf, oblk, rn, cnn)
-                                                 : ref(B_HAT, slot, ra ? tnp : rn, cb ? tnq : cnn, ra ? ro : 0, cb ? co : 0);
-                  GItem it = item(out, noref(), ra ? dconst(B.r[l][c]) : dx(DK_T, c),
-                                  cb ? dconst(B.r[l][d]) : dx(DK_T, d), -1.0, 1.0);
-                  mp.fill.add(it, ts);
-                }
+              std::vector<GTerm> ts;
+              for (int i : cn)
+                ts.push_back(term(ref(B_S, lp.blk(c, i), dx(DK_R, c), 0), ref(B_S, lp.blk(d, i), dx(DK_R, d), 0),
+                                  dx(DK_R, i), B_SIGN, i));
+              GItem it = item(ref(B_HAT, slot, rn, cnn), noref(), dx(DK_S, c), dx(DK_S, d), -1.0, 1.0);
+              it.c2 = ref(SEG_OUT, slot, tnp, tnq, ro, co);
+              it.rsplit = dx(DK_T, c);
+              it.csplit = dx(DK_T, d);
+              mp.fill.add(it, ts);
             }
           }
         }
