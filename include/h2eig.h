@@ -157,13 +157,19 @@ h2_status h2_tree_perm(h2_matrix A, int64_t* perm);
  * each kernel class accumulates its algorithmic flops (the method's own
  * operation counts from the actual per-shift ranks, e.g. 2*M*N*K per block
  * product, R^3/3 + R^3/3 per pivot LDL and its inverse) in device counters.
- * Enabling resets the totals.  Classes are numbered 0 .. h2_profile_classes()-1.
+ * Enabling resets the totals.  Classes are numbered 0 .. h2_profile_classes()-1:
+ * first the roles of the factorization (names such as "rotate", "schur"), then
+ * one entry per operand layout of the MFMA GEMM kernel (names starting with
+ * "kernel:"), which counts the same GEMM launches by kernel symbol.
  */
 h2_status h2_profile_enable(h2_matrix A, int32_t enable);
 int32_t h2_profile_classes(void);
 const char* h2_profile_class_name(int32_t cls);
 /* launches: events pairs recorded; ms: summed event time; flops: algorithmic flops */
 h2_status h2_profile_read(h2_matrix A, int32_t cls, int64_t* launches, double* ms, double* flops);
+/* Diagnostic: milliseconds of class `cls` spent at tree level `level` (0 = root)
+ * since profiling was enabled.  H2_EINVAL for a bad class, level (>= 32) or NULL. */
+h2_status h2_profile_level_ms(h2_matrix A, int32_t cls, int32_t level, double* ms);
 
 void h2_free(h2_matrix A);
 

@@ -66,7 +66,8 @@ struct BufTab {
   int64_t ss[NBUF];  // shift stride (elements)
   int64_t bs[NBUF];  // block stride (elements)
   int ld[NBUF];      // leading dimension
-  unsigned long long* fc;  // algorithmic flop counter of the launch's kernel class (or null)
+  unsigned long long* fc;   // algorithmic flop counter of the launch's kernel class (or null)
+  unsigned long long* fck;  // second counter, per kernel symbol (GEMM layouts), or null
 };
 
 struct SizeTab {

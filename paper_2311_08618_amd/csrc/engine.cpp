@@ -127,6 +127,9 @@ const char* const kProfNames[PC_N] = {"init", "recompress_pchol", "recompress_pc
                                       "pivot_ldl_update", "pivot_ldl_inverse", "pivot_ldl_operator", "elimination",
                                       "copyback", "schur", "fillin_gram", "merge_gather", "merge_fillin",
                                       "merge_transfer"};
+// per-kernel totals of the GEMM kernel by operand layout (GemmKind order)
+const char* const kGemmNames[4] = {"kernel:k_gemm<false, false>", "kernel:k_gemm<false, true>",
+                                   "kernel:k_gemm<true, false>", "kernel:k_gemm<true, true>"};
 
 // Brackets kernel launches with HIP events on the handle's stream and keeps a
 // device array of per-class algorithmic flop counters.
@@ -135,9 +138,11 @@ struct Profiler {
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> recs;
-  double ms[PC_N] = {0};
-  long long launches[PC_N] = {0};
-  unsigned long long flops[PC_N] = {0};
+  int level = 0;                     // level of the records being made (for the per-level table)
+  double ms_level[PC_N + 4][32] = {{0}};
+  double ms[PC_N + 4] = {0};              // classes, then the four GEMM layouts (kernel symbols)
+  long long launches[PC_N + 4] = {0};
+  unsigned long long flops[PC_N + 4] = {0};
   unsigned long long* d_fc = nullptr;
   hipEvent_t get() {
     if (used == pool.size()) {
@@ -148,22 +153,27 @@ struct Profiler {
     return pool[used++];
   }
   void reset() {
-    for (int c = 0; c < PC_N; ++c) { ms[c] = 0; launches[c] = 0; flops[c] = 0; }
+    for (int c = 0; c < PC_N + 4; ++c) {
+      ms[c] = 0; launches[c] = 0; flops[c] = 0;
+      for (int l = 0; l < 32; ++l) ms_level[c][l] = 0;
+    }
   }
   // after the stream is synchronized: fold the recorded pairs into the totals
   void collect() {
     for (auto& r : recs) {
       float t = 0.f;
       HIPCHK(hipEventElapsedTime(&t, r.second.first, r.second.second));
-      ms[r.first] += t;
-      launches[r.first] += 1;
+      const int cls = r.first & 0xFFFF, lev = r.first >> 16;
+      ms[cls] += t;
+      ms_level[cls][lev & 31] += t;
+      launches[cls] += 1;
     }
     recs.clear();
     used = 0;
     if (d_fc) {
-      unsigned long long h[PC_N];
+      unsigned long long h[PC_N + 4];
       HIPCHK(hipMemcpy(h, d_fc, sizeof(h), hipMemcpyDeviceToHost));
-      for (int c = 0; c < PC_N; ++c) flops[c] += h[c];
+      for (int c = 0; c < PC_N + 4; ++c) flops[c] += h[c];
       HIPCHK(hipMemset(d_fc, 0, sizeof(h)));
     }
   }
@@ -548,6 +558,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     const LevelPlan& lp = A->plan[l];
     const DevLevel& dl = A->dlev[l];
     const int N = lp.N;
+    A->prof.level = l;
     if (cap > hqr_max_rows())
       throw NoMem{"cluster dimension " + std::to_string(cap) + " exceeds the supported maximum " +
                   std::to_string(hqr_max_rows())};
@@ -591,8 +602,11 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
       setb(B_CPL, A->d_cpl[l], 0, (size_t)std::max(1, lpl.rmax) * std::max(1, lpl.rmax), std::max(1, lpl.rmax));
     }
     Profiler& prof = A->prof;
-    auto run = [&](int cls, auto&& fn) {
+    // profiled region: class cls, and for GEMM launches also the kernel symbol
+    // (tag = GEMM layout), whose totals are kept beside the classes
+    auto run = [&](int cls, auto&& fn, int tag = -1) {
       bt.fc = prof.on ? prof.d_fc + cls : nullptr;
+      bt.fck = prof.on && tag >= 0 ? prof.d_fc + PC_N + tag : nullptr;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (prof.on) {
         e0 = prof.get();
@@ -602,9 +616,11 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
       if (prof.on) {
         e1 = prof.get();
         HIPCHK(hipEventRecord(e1, st));
-        prof.recs.push_back({cls, {e0, e1}});
+        prof.recs.push_back({cls | (prof.level << 16), {e0, e1}});
+        if (tag >= 0) prof.recs.push_back({(PC_N + tag) | (prof.level << 16), {e0, e1}});
       }
       bt.fc = nullptr;
+      bt.fck = nullptr;
     };
     SizeTab sz{};
     sz.m = w.m;
@@ -632,7 +648,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
       run(PC_GRAM, [&] {
         launch_gemm(GEMM_NT, A->dp<GItem>(dl.gram_init.items), dl.gram_init.n, A->dp<GTerm>(dl.gram_init.terms), bt,
                     sz, cap, cap, S, st);
-      });
+      }, GEMM_NT);
     const double tau2 = A->tau * A->tau;
     // scratch slots of the out-of-place products: about 2 GB per shift at most
     int max_items = 1;
@@ -645,7 +661,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     auto chunked = [&](int cls, int kind, const DevList& gl, size_t copies) {
       for (int c0 = 0; c0 < gl.n; c0 += CH) {
         int nc = std::min(CH, gl.n - c0);
-        run(cls, [&] { launch_gemm(kind, A->dp<GItem>(gl.items) + c0, nc, A->dp<GTerm>(gl.terms), bt, sz, cap, cap, S, st); });
+        run(cls, [&] { launch_gemm(kind, A->dp<GItem>(gl.items) + c0, nc, A->dp<GTerm>(gl.terms), bt, sz, cap, cap, S, st); }, kind);
         run(PC_COPY, [&] { launch_copyback(A->dp<CopyItem>(copies) + c0, nc, bt, sz, cap, S, st); });
       }
     };
@@ -654,7 +670,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
       const int* cl = A->dp<int>(dc.clusters);
       auto gl = [&](int cls, int kind, const DevList& L, int mcap = 0, int ncap = 0) {
         const int mc = mcap > 0 ? mcap : cap, nc = ncap > 0 ? ncap : cap;
-        if (L.n) run(cls, [&] { launch_gemm(kind, A->dp<GItem>(L.items), L.n, A->dp<GTerm>(L.terms), bt, sz, mc, nc, S, st); });
+        if (L.n) run(cls, [&] { launch_gemm(kind, A->dp<GItem>(L.items), L.n, A->dp<GTerm>(L.terms), bt, sz, mc, nc, S, st); }, kind);
       };
       // pivoted Cholesky of the fill-in Gram, panel by panel (finished clusters
       // make a panel a no-op, so the counters are read back every 4 panels)
@@ -768,16 +784,16 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
         run(PC_MERGE_FILL, [&] {
           launch_gemm(GEMM_NT, A->dp<GItem>(dl.fill.items) + ch.f0, ch.f1 - ch.f0, A->dp<GTerm>(dl.fill.terms), bt, sz,
                       pcap, pcap, S, st);
-        });
+        }, GEMM_NT);
       run(PC_MERGE, [&] { launch_merge_nn(A->dp<GatherItem>(dl.gather) + ch.g0, ch.g1 - ch.g0, bt, sz, pcap, S, st); });
       run(PC_MERGE_E, [&] {
         launch_gemm(GEMM_NN, A->dp<GItem>(dl.tr1.items) + ch.a0, ch.a1 - ch.a0, A->dp<GTerm>(dl.tr1.terms), bt, sz, pcap,
                     emax, S, st);
-      });
+      }, GEMM_NN);
       run(PC_MERGE_E, [&] {
         launch_gemm(GEMM_TN, A->dp<GItem>(dl.tr2.items) + ch.b0, ch.b1 - ch.b0, A->dp<GTerm>(dl.tr2.terms), bt, sz, emax,
                     pcap, S, st);
-      });
+      }, GEMM_TN);
     }
     run(PC_MERGE, [&] { launch_next_sizes(sz, S, st); });
     HIPCHK(hipGetLastError());
@@ -1035,8 +1051,8 @@ h2_status h2_profile_enable(h2_matrix A, int32_t enable) {
   try {
     HIPCHK(hipSetDevice(A->device));
     if (enable && !A->prof.d_fc) {
-      HIPCHK(hipMalloc(&A->prof.d_fc, PC_N * sizeof(unsigned long long)));
-      HIPCHK(hipMemset(A->prof.d_fc, 0, PC_N * sizeof(unsigned long long)));
+      HIPCHK(hipMalloc(&A->prof.d_fc, (PC_N + 4) * sizeof(unsigned long long)));
+      HIPCHK(hipMemset(A->prof.d_fc, 0, (PC_N + 4) * sizeof(unsigned long long)));
     }
   } catch (HipError& e) {
     return fail(H2_EDEVICE, e.where + ": " + hipGetErrorString(e.e));
@@ -1046,15 +1062,25 @@ h2_status h2_profile_enable(h2_matrix A, int32_t enable) {
   return H2_OK;
 }
 
-int32_t h2_profile_classes(void) { return PC_N; }
+int32_t h2_profile_classes(void) { return PC_N + 4; }
 
-const char* h2_profile_class_name(int32_t cls) { return (cls >= 0 && cls < PC_N) ? kProfNames[cls] : ""; }
+const char* h2_profile_class_name(int32_t cls) {
+  if (cls >= 0 && cls < PC_N) return kProfNames[cls];
+  if (cls >= PC_N && cls < PC_N + 4) return kGemmNames[cls - PC_N];
+  return "";
+}
 
 h2_status h2_profile_read(h2_matrix A, int32_t cls, int64_t* launches, double* ms, double* flops) {
-  if (!A || cls < 0 || cls >= PC_N) return fail(H2_EINVAL, "bad handle or class");
+  if (!A || cls < 0 || cls >= PC_N + 4) return fail(H2_EINVAL, "bad handle or class");
   if (launches) *launches = A->prof.launches[cls];
   if (ms) *ms = A->prof.ms[cls];
   if (flops) *flops = (double)A->prof.flops[cls];
+  return H2_OK;
+}
+
+h2_status h2_profile_level_ms(h2_matrix A, int32_t cls, int32_t level, double* ms) {
+  if (!A || cls < 0 || cls >= PC_N + 4 || level < 0 || level >= 32 || !ms) return fail(H2_EINVAL, "bad arguments");
+  *ms = A->prof.ms_level[cls][level];
   return H2_OK;
 }
 

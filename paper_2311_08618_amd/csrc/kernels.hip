@@ -58,6 +58,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, c
     unsigned long long kk = 0;
     for (int tt = 0; tt < it.nt; ++tt) kk += (unsigned long long)max(0, dev_eval(terms[it.t0 + tt].K, sz, s));
     atomicAdd(bt.fc, 2ull * (unsigned long long)M * (unsigned long long)N * kk);
+    if (bt.fck) atomicAdd(bt.fck, 2ull * (unsigned long long)M * (unsigned long long)N * kk);
   }
   __shared__ double As[2][GK][GT + 1];
   __shared__ double Bs[2][GK][GT + 1];

@@ -70,6 +70,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.h2_profile_class_name.argtypes = [C.c_int32]
     lib.h2_profile_read.restype = C.c_int
     lib.h2_profile_read.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double)]
+    lib.h2_profile_level_ms.restype = C.c_int
+    lib.h2_profile_level_ms.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(C.c_double)]
     lib.h2_free.restype = None
     lib.h2_free.argtypes = [C.c_void_p]
     lib.h2_last_error.restype = C.c_char_p
@@ -81,7 +83,7 @@ _lib = load_library()
 
 EXPORTED = ["h2_build", "h2_inertia", "h2_kth_eig", "h2_norm", "h2_stats", "h2_set_stream", "h2_tree_perm",
             "h2_profile_enable", "h2_profile_classes", "h2_profile_class_name", "h2_profile_read",
-            "h2_free", "h2_last_error"]
+            "h2_profile_level_ms", "h2_free", "h2_last_error"]
 
 
 def _check(st: int):
@@ -166,6 +168,18 @@ class H2Matrix:
             fl = C.c_double()
             _check(_lib.h2_profile_read(self._h, c, C.byref(n), C.byref(ms), C.byref(fl)))
             out[_lib.h2_profile_class_name(c).decode()] = {"launches": n.value, "ms": ms.value, "flops": fl.value}
+        return out
+
+    def profile_levels(self, levels: int = 32) -> dict:
+        """{class name: [ms at level 0, 1, ...]} since profiling was enabled."""
+        out = {}
+        for c in range(_lib.h2_profile_classes()):
+            row = []
+            for lev in range(levels):
+                ms = C.c_double()
+                _check(_lib.h2_profile_level_ms(self._h, c, lev, C.byref(ms)))
+                row.append(ms.value)
+            out[_lib.h2_profile_class_name(c).decode()] = row
         return out
 
     def set_stream(self, stream_ptr: int):
