@@ -1,0 +1,95 @@
+"""GPU edge cases through the C ABI: tiny and ragged sizes against dense LAPACK
+inertia, argument errors of calls on a built matrix, and properties that hold
+at any size:
+  * the 1-D second-difference matrix against its closed-form spectrum
+    2 - 2cos(j*pi/(n+1)), exactly, for every shift, at n = 16384;
+  * on the bench workload at its full size (cube, n = 2^18): nu = 0 and n at
+    shifts beyond every eigenvalue, nu monotone in sigma, the batched call
+    equal to a one-shift call, and repeat-determinism.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.dense import tridiag_eigs, tridiag_inertia
+from oracle.kernels import Kernel
+from paper_2311_08618_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2311_08618_amd import h2eig
+    return h2eig
+
+
+@pytest.mark.parametrize("n,leaf", [(1, 2), (2, 2), (3, 2), (5, 4), (17, 4), (130, 16)])
+def test_tiny_and_ragged_vs_dense(lib, n, leaf):
+    print("case tiny n=%d leaf=%d" % (n, leaf), flush=True)
+    X = W.cube_points(n, 5)
+    A = lib.H2Matrix(X, W.K_LAPLACE, 10.0, leaf, 1.0, 1e-12)
+    ev = np.linalg.eigvalsh(Kernel(W.K_LAPLACE, 10.0).dense(X))
+    gap = 1e-6 * A.norm()
+    sig = [ev[0] - 1.0] + [0.5 * (ev[i] + ev[i + 1]) for i in range(n - 1) if ev[i + 1] - ev[i] > gap] + [ev[-1] + 1.0]
+    nu = A.inertia(np.array(sig))
+    want = np.array([int(np.sum(ev < s)) for s in sig])
+    assert np.array_equal(nu, want), (nu, want)
+
+
+def test_small_kth_eig_vs_dense(lib):
+    n = 64
+    X = W.cube_points(n, 7)
+    A = lib.H2Matrix(X, W.K_LAPLACE, 10.0, 8, 1.0, 1e-12)
+    ev = np.linalg.eigvalsh(Kernel(W.K_LAPLACE, 10.0).dense(X))
+    ks = [1, 32, 64]
+    lam, _ = A.kth_eig(ks, 1e-9)
+    for k, l in zip(ks, lam):
+        assert abs(l - ev[k - 1]) <= 0.5e-9 + 10 * 1e-12 * A.norm(), (k, l, ev[k - 1])
+
+
+def test_argument_errors(lib):
+    n = 64
+    A = lib.H2Matrix(W.cube_points(n, 7), W.K_LAPLACE, 10.0, 8, 1.0, 1e-10)
+    for ks, tol, ab in [([0], 1e-8, None), ([n + 1], 1e-8, None), ([1], 0.0, None), ([1], -1.0, None),
+                        ([1], 1e-8, (1.0, 1.0)), ([1], 1e-8, (math.nan, 2.0))]:
+        with pytest.raises(lib.H2EigError) as e:
+            A.kth_eig(ks, tol, ab)
+        assert e.value.status == lib.H2_EINVAL
+    with pytest.raises(lib.H2EigError) as e:
+        A.inertia(np.array([1.0, math.nan]))
+    assert e.value.status == lib.H2_EINVAL
+    assert len(A.inertia(np.array([], dtype=np.float64))) == 0
+
+
+def test_tridiag_closed_form_large(lib):
+    # the largest size whose far fields the host builds exactly in seconds (the
+    # second-difference far field is one boundary point, which a strided sample
+    # of an ancestor's interaction cluster can miss)
+    n, leaf = 1 << 14, 64
+    print("case tridiag n=%d leaf=%d" % (n, leaf), flush=True)
+    A = lib.H2Matrix(W.line_points(n), W.K_TRIDIAG_1D, 2.0, leaf, 1.0, 1e-12, p0=1.0)
+    lam = tridiag_eigs(n)
+    rng = np.random.default_rng(11)
+    sig = list(np.linspace(-0.1, 4.1, 7) + 1e-3 * math.sqrt(2.0))
+    for j in rng.integers(0, n, 3):
+        sig += [lam[j] - 1e-9, lam[j] + 1e-9]
+    nu = A.inertia(np.array(sig))
+    want = np.array([tridiag_inertia(n, s) for s in sig])
+    assert np.array_equal(nu, want), (nu - want)
+
+
+def test_cube_full_size_properties(lib):
+    n = 1 << 18
+    print("case cube n=%d properties" % n, flush=True)
+    A = lib.H2Matrix(W.cube_points(n, 0), W.K_LAPLACE, 1e3, 256, 1.0, 1e-8, max_shifts=1)
+    # |lambda| <= max row sum < n / (smallest distance), far below 1e12
+    sig = np.array([-1e12, 950.0, 1000.0, 1e12])
+    nu = A.inertia(sig)
+    assert nu[0] == 0 and nu[3] == n
+    assert 0 < nu[1] <= nu[2] < n
+    one = A.inertia(np.array([1000.0]))
+    assert one[0] == nu[2]
+    again = A.inertia(np.array([1000.0]))
+    assert again[0] == one[0]
