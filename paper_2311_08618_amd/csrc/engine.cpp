@@ -215,6 +215,8 @@ struct h2_matrix_s {
   double g_lo = 0, g_hi = 0;
   h2_stats_t st{};
   int max_shifts = 0;
+  int max_list = 1;        // longest GEMM list of the plan (tile-count scratch)
+  int* d_prefix = nullptr;  // per-shift tile counts of the current GEMM launch (in the small arena)
   Profiler prof;
   int* d_more = nullptr;   // per-iteration "more panels needed" counters + colour maxima
   int* h_more = nullptr;   // pinned host copy (4 ints)
@@ -239,16 +241,21 @@ struct Busy {
   }
 };
 
+// longest GEMM list of the plan: sizes the per-shift tile-count scratch
+int g_max_list = 1;
+
 DevList put_list(Blob& b, const GList& g) {
   DevList d;
   d.items = b.put(g.items);
   d.terms = b.put(g.terms);
   d.n = (int)g.items.size();
+  g_max_list = std::max(g_max_list, d.n);
   return d;
 }
 
 void upload_plan(h2_matrix A) {
   Blob b;
+  g_max_list = 1;
   int L = A->T.L;
   A->dlev.assign(L + 1, {});
   for (int l = 0; l <= L; ++l) {
@@ -305,6 +312,7 @@ void upload_plan(h2_matrix A) {
   }
   A->leaf_m0 = b.put(m0);
   A->leaf_blkdiag = b.put(bdm);
+  A->max_list = g_max_list;
   HIPCHK(hipMalloc(&A->d_plan, b.h.size()));
   HIPCHK(hipMemcpy(A->d_plan, b.h.data(), b.h.size(), hipMemcpyHostToDevice));
   A->resident += (int64_t)b.h.size();
@@ -402,9 +410,12 @@ void build_near_blocks(h2_matrix A) {
     bt.p[B_HAT] = dA;
     bt.p[B_TMP] = dT;
     bt.p[B_BRES] = A->d_bres;
-    launch_gemm(GEMM_TN, di1, nb, dt1, bt, sz, cap, cap, 1, st);
-    launch_gemm(GEMM_NN, di2, nb, dt2, bt, sz, cap, cap, 1, st);
+    int* dpre = nullptr;
+    HIPCHK(hipMalloc(&dpre, (size_t)(nb + 1) * sizeof(int)));
+    launch_gemm(GEMM_TN, di1, nb, dt1, bt, sz, cap, cap, 1, dpre, st);
+    launch_gemm(GEMM_NN, di2, nb, dt2, bt, sz, cap, cap, 1, dpre, st);
     HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipFree(dpre));
     HIPCHK(hipFree(di1));
     HIPCHK(hipFree(di2));
     HIPCHK(hipFree(dt1));
@@ -530,9 +541,11 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
   size_t nsz = (size_t)S * Nmax;
   size_t off_m = 0, off_R = off_m + nsz * 4, off_t = off_R + nsz * 4, off_pm = off_t + nsz * 4,
          off_pR = off_pm + nsz * 4, off_a0 = off_pR + nsz * 4, off_a1 = off_a0 + nsz * 4, off_st = off_a1 + nsz * 4,
-         off_sig = ((off_st + S * 4 + 255) / 256) * 256, off_nu = off_sig + S * 8, total = off_nu + S * 8;
+         off_sig = ((off_st + S * 4 + 255) / 256) * 256, off_nu = off_sig + S * 8,
+         off_pre = off_nu + S * 8, total = off_pre + (size_t)S * (A->max_list + 1) * 4;
   A->small.ensure(total, st);
   char* base = (char*)A->small.p;
+  int* const dpre = (int*)(base + off_pre);
   Work w;
   w.S = S;
   w.m = (int*)(base + off_m);
@@ -647,7 +660,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     if (dl.gram_init.n)
       run(PC_GRAM, [&] {
         launch_gemm(GEMM_NT, A->dp<GItem>(dl.gram_init.items), dl.gram_init.n, A->dp<GTerm>(dl.gram_init.terms), bt,
-                    sz, cap, cap, S, st);
+                    sz, cap, cap, S, dpre, st);
       }, GEMM_NT);
     const double tau2 = A->tau * A->tau;
     // scratch slots of the out-of-place products: about 2 GB per shift at most
@@ -661,7 +674,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     auto chunked = [&](int cls, int kind, const DevList& gl, size_t copies) {
       for (int c0 = 0; c0 < gl.n; c0 += CH) {
         int nc = std::min(CH, gl.n - c0);
-        run(cls, [&] { launch_gemm(kind, A->dp<GItem>(gl.items) + c0, nc, A->dp<GTerm>(gl.terms), bt, sz, cap, cap, S, st); }, kind);
+        run(cls, [&] { launch_gemm(kind, A->dp<GItem>(gl.items) + c0, nc, A->dp<GTerm>(gl.terms), bt, sz, cap, cap, S, dpre, st); }, kind);
         run(PC_COPY, [&] { launch_copyback(A->dp<CopyItem>(copies) + c0, nc, bt, sz, cap, S, st); });
       }
     };
@@ -670,7 +683,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
       const int* cl = A->dp<int>(dc.clusters);
       auto gl = [&](int cls, int kind, const DevList& L, int mcap = 0, int ncap = 0) {
         const int mc = mcap > 0 ? mcap : cap, nc = ncap > 0 ? ncap : cap;
-        if (L.n) run(cls, [&] { launch_gemm(kind, A->dp<GItem>(L.items), L.n, A->dp<GTerm>(L.terms), bt, sz, mc, nc, S, st); }, kind);
+        if (L.n) run(cls, [&] { launch_gemm(kind, A->dp<GItem>(L.items), L.n, A->dp<GTerm>(L.terms), bt, sz, mc, nc, S, dpre, st); }, kind);
       };
       // pivoted Cholesky of the fill-in Gram, panel by panel (finished clusters
       // make a panel a no-op, so the counters are read back every 4 panels)
@@ -783,16 +796,16 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
       if (ch.f1 > ch.f0)
         run(PC_MERGE_FILL, [&] {
           launch_gemm(GEMM_NT, A->dp<GItem>(dl.fill.items) + ch.f0, ch.f1 - ch.f0, A->dp<GTerm>(dl.fill.terms), bt, sz,
-                      pcap, pcap, S, st);
+                      pcap, pcap, S, dpre, st);
         }, GEMM_NT);
       run(PC_MERGE, [&] { launch_merge_nn(A->dp<GatherItem>(dl.gather) + ch.g0, ch.g1 - ch.g0, bt, sz, pcap, S, st); });
       run(PC_MERGE_E, [&] {
         launch_gemm(GEMM_NN, A->dp<GItem>(dl.tr1.items) + ch.a0, ch.a1 - ch.a0, A->dp<GTerm>(dl.tr1.terms), bt, sz, pcap,
-                    emax, S, st);
+                    emax, S, dpre, st);
       }, GEMM_NN);
       run(PC_MERGE_E, [&] {
         launch_gemm(GEMM_TN, A->dp<GItem>(dl.tr2.items) + ch.b0, ch.b1 - ch.b0, A->dp<GTerm>(dl.tr2.terms), bt, sz, emax,
-                    pcap, S, st);
+                    pcap, S, dpre, st);
       }, GEMM_TN);
     }
     run(PC_MERGE, [&] { launch_next_sizes(sz, S, st); });

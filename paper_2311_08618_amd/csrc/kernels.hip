@@ -44,24 +44,87 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int GT = 64;   // output tile
 constexpr int GK = 16;   // k step
+constexpr int GEMM_GRID = 2048;   // workgroups of a GEMM launch (8 per CU)
 
+// Per shift, the exclusive prefix sum of the output tiles of every item of a
+// list (0 for an item whose guard or sizes are 0): the GEMM below then runs on a
+// fixed grid over the real tiles only.
+__global__ __launch_bounds__(1024) void k_tile_scan(const GItem* __restrict__ items, int nitems, SizeTab sz,
+                                                    int* __restrict__ prefix) {
+  __shared__ int wsum[16];
+  __shared__ int carry;
+  const int s = blockIdx.x;
+  int* pre = prefix + (int64_t)s * (nitems + 1);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nitems; base += 1024) {
+    const int i = base + tid;
+    int v = 0;
+    if (i < nitems) {
+      const GItem it = items[i];
+      const bool skip = it.guard != -1 && dev_eval(it.guard, sz, s) == 0;
+      const int M = dev_eval(it.M, sz, s), N = dev_eval(it.N, sz, s);
+      v = (skip || M <= 0 || N <= 0) ? 0 : ((M + GT - 1) / GT) * ((N + GT - 1) / GT);
+    }
+    int x = v;   // inclusive scan within the wave
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    if (tid < 16) {
+      int w = wsum[tid];
+      for (int d = 1; d < 16; d <<= 1) {
+        const int y = __shfl_up(w, d, 64);
+        if (tid >= d) w += y;
+      }
+      wsum[tid] = w;   // inclusive over waves
+    }
+    __syncthreads();
+    const int before = carry + (wave > 0 ? wsum[wave - 1] : 0);
+    if (i < nitems) pre[i] = before + x - v;
+    __syncthreads();
+    if (tid == 0) carry += wsum[15];
+    __syncthreads();
+  }
+  if (tid == 0) pre[nitems] = carry;
+}
+
+// The GEMM proper: a fixed grid strides over the tiles counted by k_tile_scan;
+// workgroups on one XCD (blockIdx.x % 8) take consecutive tiles, so that tiles
+// sharing panels of A or B meet in the same L2.
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, const GTerm* __restrict__ terms,
-                                              BufTab bt, SizeTab sz, int tiles_n, int slot_base) {
+__global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, int nitems,
+                                              const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
+                                              const int* __restrict__ prefix, int slot_base) {
   const int s = blockIdx.z;
-  const GItem it = items[blockIdx.y];
-  if (it.guard != -1 && dev_eval(it.guard, sz, s) == 0) return;
+  const int* pre = prefix + (int64_t)s * (nitems + 1);
+  const int total = pre[nitems];
+  const int G = gridDim.x;
+  const int lw = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);   // G is a multiple of 8
+  __shared__ double As[2][GK][GT + 1];
+  __shared__ double Bs[2][GK][GT + 1];
+  for (int tile = lw; tile < total; tile += G) {
+  int lo = 0, hi = nitems - 1;   // the item: the last i with pre[i] <= tile
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  const int idx = lo;
+  const GItem it = items[idx];
   const int M = dev_eval(it.M, sz, s), N = dev_eval(it.N, sz, s);
-  const int m0 = (blockIdx.x / tiles_n) * GT, n0 = (blockIdx.x % tiles_n) * GT;
-  if (m0 >= M || n0 >= N) return;
-  if (bt.fc && blockIdx.x == 0 && threadIdx.x == 0) {
+  const int tn = (N + GT - 1) / GT;
+  const int local = tile - pre[idx];
+  const int m0 = (local / tn) * GT, n0 = (local % tn) * GT;
+  if (bt.fc && local == 0 && threadIdx.x == 0) {
     unsigned long long kk = 0;
     for (int tt = 0; tt < it.nt; ++tt) kk += (unsigned long long)max(0, dev_eval(terms[it.t0 + tt].K, sz, s));
     atomicAdd(bt.fc, 2ull * (unsigned long long)M * (unsigned long long)N * kk);
     if (bt.fck) atomicAdd(bt.fck, 2ull * (unsigned long long)M * (unsigned long long)N * kk);
   }
-  __shared__ double As[2][GK][GT + 1];
-  __shared__ double Bs[2][GK][GT + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   v4d acc[2][2];
@@ -138,7 +201,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, c
   }
   int cr, cc;
   ref_origin(it.c, sz, s, &cr, &cc);
-  double* C = addr(bt, it.c.buf, it.c.blk >= 0 ? it.c.blk : (int)blockIdx.y + slot_base, s, 0, 0);
+  double* C = addr(bt, it.c.buf, it.c.blk >= 0 ? it.c.blk : idx + slot_base, s, 0, 0);
   const int ldc = bt.ld[it.c.buf];
   double* C2 = nullptr;
   int ldc2 = 0;
@@ -170,6 +233,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, c
           }
         }
       }
+  }
 }
 
 // --------------------------------------------------------------- matrix sums
@@ -1262,18 +1326,18 @@ void launch_fill_int(int* p, int64_t n, int v, hipStream_t st) {
 }
 
 void launch_gemm(int kind, const GItem* items, int nitems, const GTerm* terms, const BufTab& bt, const SizeTab& sz,
-                 int mcap, int ncap, int nshift, hipStream_t st) {
+                 int mcap, int ncap, int nshift, int* prefix, hipStream_t st) {
   if (nitems <= 0) return;
-  int tm = (int)cdiv(mcap, GT), tn = (int)cdiv(ncap, GT);
-  for (int i0 = 0; i0 < nitems; i0 += 65535) {
-    int ni = std::min(65535, nitems - i0);
-    dim3 grid(tm * tn, ni, nshift);
-    switch (kind) {
-      case GEMM_NN: hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, items + i0, terms, bt, sz, tn, i0); break;
-      case GEMM_NT: hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, items + i0, terms, bt, sz, tn, i0); break;
-      case GEMM_TN: hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, items + i0, terms, bt, sz, tn, i0); break;
-      default: hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, items + i0, terms, bt, sz, tn, i0); break;
-    }
+  hipLaunchKernelGGL(k_tile_scan, dim3(nshift), dim3(1024), 0, st, items, nitems, sz, prefix);
+  // a fixed grid, no larger than the tiles the capacities allow (multiple of 8)
+  const int64_t upper = (int64_t)nitems * cdiv(mcap, GT) * cdiv(ncap, GT);
+  const int G = (int)std::max<int64_t>(8, std::min<int64_t>(GEMM_GRID, (upper + 7) / 8 * 8));
+  dim3 grid(G, 1, nshift);
+  switch (kind) {
+    case GEMM_NN: hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
+    case GEMM_NT: hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
+    case GEMM_TN: hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
+    default: hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
   }
 }
 

@@ -10,8 +10,9 @@ enum GemmKind { GEMM_NN = 0, GEMM_NT = 1, GEMM_TN = 2, GEMM_TT = 3 };
 
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void launch_fill_int(int* p, int64_t n, int v, hipStream_t st);
+// prefix: device scratch of at least nshift * (nitems + 1) ints (the per-shift tile counts)
 void launch_gemm(int kind, const GItem* items, int nitems, const GTerm* terms, const BufTab& bt, const SizeTab& sz,
-                 int mcap, int ncap, int nshift, hipStream_t st);
+                 int mcap, int ncap, int nshift, int* prefix, hipStream_t st);
 void launch_copyback(const CopyItem* items, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
 void launch_matsum(const SumItem* items, int nitems, const int* src, const BufTab& bt, const SizeTab& sz, int cap,
                    int nshift, hipStream_t st);
