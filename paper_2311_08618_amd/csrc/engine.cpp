@@ -104,7 +104,7 @@ struct DevColour {
   int ncl = 0;
   DevList pc_upd, ut_s, ut_t, ut_x, ut_u, ut_w, ldl_upd, inv_t, inv_x;
   DevList rot_rows, rot_cols, trsm;
-  size_t rr_copy = 0, rc_copy = 0, tr_copy = 0;
+  size_t rr_copy = 0, rc_copy = 0, tr_copy = 0, rr_copyt = 0;
   DevList schur, gm, gt, gg;
   size_t gp_items = 0, gp_src = 0;
   int ngp = 0;
@@ -282,6 +282,7 @@ void upload_plan(h2_matrix A) {
       dc.rot_cols = put_list(b, cp.rot_cols);
       dc.trsm = put_list(b, cp.trsm);
       dc.rr_copy = b.put(cp.rot_rows_copy);
+      dc.rr_copyt = b.put(cp.rot_rows_copyt);
       dc.rc_copy = b.put(cp.rot_cols_copy);
       dc.tr_copy = b.put(cp.trsm_copy);
       dc.schur = put_list(b, cp.schur);
@@ -671,11 +672,12 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
                                                                 (int64_t)(2LL << 30) / (int64_t)(bsz * 8)}));
     A->rs.ensure((size_t)S * CH * bsz * 8 + 64, st);
     setb(B_RS, (double*)A->rs.p, (size_t)CH * bsz, bsz, cap);
-    auto chunked = [&](int cls, int kind, const DevList& gl, size_t copies) {
+    auto chunked = [&](int cls, int kind, const DevList& gl, size_t copies, size_t tcopies = 0) {
       for (int c0 = 0; c0 < gl.n; c0 += CH) {
         int nc = std::min(CH, gl.n - c0);
         run(cls, [&] { launch_gemm(kind, A->dp<GItem>(gl.items) + c0, nc, A->dp<GTerm>(gl.terms), bt, sz, cap, cap, S, dpre, st); }, kind);
         run(PC_COPY, [&] { launch_copyback(A->dp<CopyItem>(copies) + c0, nc, bt, sz, cap, S, st); });
+        if (tcopies) run(PC_COPY, [&] { launch_copyback_t(A->dp<CopyItem>(tcopies) + c0, nc, bt, sz, S, st); });
       }
     };
     for (size_t c = 0; c < dl.colours.size(); ++c) {
@@ -726,7 +728,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
         run(PC_WFORM, [&] { launch_eye(cl, dc.ncl, bt, sz, cap, S, st); });
         gl(PC_WFORM, GEMM_NT, dc.ut_w);
       }
-      chunked(PC_ROTATE, GEMM_TN, dc.rot_rows, dc.rr_copy);
+      chunked(PC_ROTATE, GEMM_TN, dc.rot_rows, dc.rr_copy, dc.rr_copyt);
       chunked(PC_ROTATE, GEMM_NN, dc.rot_cols, dc.rc_copy);
       // pivot LDL, panel by panel (each panel takes at least ldl_panel_min()
       // pivots unless it reaches R), then the elimination operator

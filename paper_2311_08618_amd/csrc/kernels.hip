@@ -236,6 +236,38 @@ __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, i
   }
 }
 
+// Transposed copy of a scratch slot into a block: X[r0 + a][c0 + b] = RS[slot][b][a]
+// (a < M, b < N), through 64x64 LDS tiles so that both sides are coalesced.
+__global__ __launch_bounds__(256) void k_copyback_t(const CopyItem* __restrict__ items, BufTab bt, SizeTab sz,
+                                                    int slot_base) {
+  __shared__ double tile[64][65];
+  const int s = blockIdx.z;
+  const CopyItem it = items[blockIdx.y];
+  if (it.guard != -1 && dev_eval(it.guard, sz, s) == 0) return;
+  const int M = dev_eval(it.M, sz, s), N = dev_eval(it.N, sz, s);
+  if (M <= 0 || N <= 0) return;
+  int r0, c0;
+  ref_origin(it.x, sz, s, &r0, &c0);
+  double* X = addr(bt, it.x.buf, it.x.blk, s, r0, c0);
+  const int ldx = bt.ld[it.x.buf];
+  const double* Sc = addr(bt, B_RS, (int)blockIdx.y + slot_base, s, 0, 0);
+  const int lds = bt.ld[B_RS];
+  const int tm = (M + 63) / 64, tn = (N + 63) / 64;
+  for (int t = blockIdx.x; t < tm * tn; t += gridDim.x) {
+    const int a0 = (t % tm) * 64, b0 = (t / tm) * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {   // source rows are the destination's columns
+      const int j = e % 64, i = e / 64;
+      if (a0 + i < M && b0 + j < N) tile[i][j] = Sc[(b0 + j) + (int64_t)(a0 + i) * lds];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+      const int i = e % 64, j = e / 64;
+      if (a0 + i < M && b0 + j < N) X[(a0 + i) + (int64_t)(b0 + j) * ldx] = tile[i][j];
+    }
+    __syncthreads();
+  }
+}
+
 // --------------------------------------------------------------- matrix sums
 __global__ void k_matsum(const SumItem* __restrict__ items, const int* __restrict__ src, BufTab bt, SizeTab sz) {
   const int s = blockIdx.z;
@@ -1347,6 +1379,14 @@ void launch_copyback(const CopyItem* items, int n, const BufTab& bt, const SizeT
     int ni = std::min(65535, n - i0);
     hipLaunchKernelGGL(k_copyback, dim3(std::max(1u, cdiv((int64_t)cap * cap, 256 * 8)), ni, nshift), dim3(256), 0, st,
                        items + i0, bt, sz, i0);
+  }
+}
+
+void launch_copyback_t(const CopyItem* items, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st) {
+  if (n <= 0) return;
+  for (int i0 = 0; i0 < n; i0 += 65535) {
+    int ni = std::min(65535, n - i0);
+    hipLaunchKernelGGL(k_copyback_t, dim3(16, ni, nshift), dim3(256), 0, st, items + i0, bt, sz, i0);
   }
 }
 

@@ -14,6 +14,7 @@ void launch_fill_int(int* p, int64_t n, int v, hipStream_t st);
 void launch_gemm(int kind, const GItem* items, int nitems, const GTerm* terms, const BufTab& bt, const SizeTab& sz,
                  int mcap, int ncap, int nshift, int* prefix, hipStream_t st);
 void launch_copyback(const CopyItem* items, int n, const BufTab& bt, const SizeTab& sz, int cap, int nshift, hipStream_t st);
+void launch_copyback_t(const CopyItem* items, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st);
 void launch_matsum(const SumItem* items, int nitems, const int* src, const BufTab& bt, const SizeTab& sz, int cap,
                    int nshift, hipStream_t st);
 void launch_pchol_init(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st);

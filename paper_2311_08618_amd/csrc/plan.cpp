@@ -139,21 +139,31 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
       }
       // rotation by W (rows, then columns) and elimination by K, each as an
       // out-of-place product into a scratch slot followed by a copy back
-      auto rot = [&](int buf, int blk_row, int blk_col, int i, int other) {
+      // Both orientations of a block are stored and (k,i) = (i,k)^T, so the
+      // columns of (k,i) receive the transpose of the rotated rows of (i,k).
+      // Blocks whose row and column clusters are rotated in the same class
+      // (the diagonal block, and fill-in blocks between two clusters of one
+      // colour) are rotated on both sides by products instead.
+      auto rot = [&](int buf, int blk_row, int blk_col, int i, int other, bool both_sides) {
+        const bool diag = both_sides;
         GItem g = item(ref(B_RS, -1), noref(), dx(DK_RT, i), other, 1.0, 0.0);
         g.guard = dx(DK_T, i);
         cp.rot_rows.add(g, {term(ref(B_W, i), ref(buf, blk_row), dx(DK_RT, i))});
         CopyItem cr{ref(buf, blk_row), dx(DK_RT, i), other, dx(DK_T, i)};
         cp.rot_rows_copy.push_back(cr);
-        GItem h = item(ref(B_RS, -1), noref(), other, dx(DK_RT, i), 1.0, 0.0);
-        h.guard = dx(DK_T, i);
-        cp.rot_cols.add(h, {term(ref(buf, blk_col), ref(B_W, i), dx(DK_RT, i))});
-        CopyItem cc{ref(buf, blk_col), other, dx(DK_RT, i), dx(DK_T, i)};
-        cp.rot_cols_copy.push_back(cc);
+        CopyItem ct{ref(buf, blk_col), other, dx(DK_RT, i), diag ? dconst(0) : dx(DK_T, i)};
+        cp.rot_rows_copyt.push_back(ct);
+        if (diag) {
+          GItem h = item(ref(B_RS, -1), noref(), other, dx(DK_RT, i), 1.0, 0.0);
+          h.guard = dx(DK_T, i);
+          cp.rot_cols.add(h, {term(ref(buf, blk_col), ref(B_W, i), dx(DK_RT, i))});
+          CopyItem cc{ref(buf, blk_col), other, dx(DK_RT, i), dx(DK_T, i)};
+          cp.rot_cols_copy.push_back(cc);
+        }
       };
       for (int i : cp.clusters) {
-        for (int k : T.near[l][i]) rot(B_S, lp.blk(i, k), lp.blk(k, i), i, dx(DK_M, k));
-        for (int q : carried[l][i]) rot(B_F, lp.fblk(i, q), lp.fblk(q, i), i, dx(DK_M, q));
+        for (int k : T.near[l][i]) rot(B_S, lp.blk(i, k), lp.blk(k, i), i, dx(DK_M, k), k == i);
+        for (int q : carried[l][i]) rot(B_F, lp.fblk(i, q), lp.fblk(q, i), i, dx(DK_M, q), col[q] == col[i]);
         for (int k : T.near[l][i]) {
           GItem g = item(ref(B_RS, -1), noref(), nrows(k), dx(DK_R, i), 1.0, 0.0);
           g.guard = dx(DK_R, i);

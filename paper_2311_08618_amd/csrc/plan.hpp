@@ -39,6 +39,7 @@ struct ColourPlan {
   GList inv_x;                 // NN: X[block ib, 0:a0] = -X_ii T
   GList rot_rows, rot_cols;    // TN: RS = W^T X ; NN: RS = X W
   std::vector<CopyItem> rot_rows_copy, rot_cols_copy;
+  std::vector<CopyItem> rot_rows_copyt;   // transposed copies into the mirror blocks (parallel to rot_rows)
   GList trsm;                  // NT: RS = X (K^T)^T, operator stored transposed
   std::vector<CopyItem> trsm_copy;
   GList schur;                 // NT, alpha -1
