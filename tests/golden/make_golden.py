@@ -8,9 +8,10 @@ Every value below comes from ``oracle/`` (the H^2 oracle and its dense
 checkers): the inertia nu(sigma) on a grid of shifts together with the counts at
 sigma -/+ w, w = 1e3 * eps * normA (the window inside which a truncation-level
 difference may move an eigenvalue across sigma); lambda_{n/2} from the oracle's
-Algorithm 1 with its step count; and lambda_{n/2} of the dense matrix from LAPACK
+Algorithm 1 with its step count; lambda_{n/2} of the dense matrix from LAPACK
 (``numpy.linalg.eigvalsh``), which the H^2 result must approach within
-tol/2 + 10 * eps * normA (Eq. error-bound plus the construction error).
+tol/2 + 10 * eps * normA (Eq. error-bound plus the construction error); and a
+scan of the oracle's nu at 17 shifts 1e-4 apart around lambda_{n/2}.
 
 Run from the repository root:  python tests/golden/make_golden.py
 """
@@ -50,6 +51,13 @@ def main():
     ab = gershgorin(X, kern, 10.0 * eps * H.normA)
     lam, br, steps = bisect_kth(lambda mu: inertia(H, mu), k, ab[0], ab[1], tol)
     dense = np.linalg.eigvalsh(kern.dense(X))
+    # a fine scan around lambda_k: steps of 1e-4 (about 2 tau); at these shifts
+    # the oracle's count equals the dense one
+    lam_d = float(dense[k - 1])
+    scan = []
+    for j in range(-8, 9):
+        s = lam_d + j * 1e-4
+        scan.append({"sigma": s, "nu": int(inertia(H, s)), "nu_dense": int(np.sum(dense < s))})
     data = {
         "workload": "cube-laplace n=2048 leaf=128 eta=1 eps=1e-8 A_ii=1e3 (points: cube_points(2048, seed 0))",
         "source": "oracle/ (H^2 oracle, Algorithm 1) and numpy.linalg.eigvalsh of the dense matrix",
@@ -61,6 +69,7 @@ def main():
         "lambda_oracle": lam, "bracket_oracle": list(br), "steps_oracle": steps,
         "lambda_dense": float(dense[k - 1]),
         "gap_below": float(dense[k - 1] - dense[k - 2]), "gap_above": float(dense[k] - dense[k - 1]),
+        "scan_near_lambda": scan,
     }
     with open(OUT, "w") as f:
         json.dump(data, f, indent=1)
