@@ -123,6 +123,17 @@ h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol,
  * |A_ii|), s = max(1, n/16384). */
 h2_status h2_norm(h2_matrix A, double* normA);
 
+/* Default starting interval of Algorithm 1 (Sec. 2) used when h2_kth_eig gets
+ * ab = NULL: the Gershgorin interval of the kernel matrix widened by
+ * 10*eps*normA on both sides (it contains the spectrum of the H^2 matrix).
+ * ab: host output, 2 doubles.  Computed once per handle (O(n^2) kernel
+ * evaluations on the host), then cached. */
+h2_status h2_interval(h2_matrix A, double* ab);
+
+/* Shifts this handle factors together in one launch, from the free device
+ * memory at the time of the call (the admission unit of the serving loop). */
+h2_status h2_capacity(h2_matrix A, int32_t* max_shifts);
+
 typedef struct {
   int64_t n;
   int32_t levels;           /* depth L of the cluster tree (leaves at level L) */
@@ -172,6 +183,38 @@ h2_status h2_profile_read(h2_matrix A, int32_t cls, int64_t* launches, double* m
 h2_status h2_profile_level_ms(h2_matrix A, int32_t cls, int32_t level, double* ms);
 
 void h2_free(h2_matrix A);
+
+/*
+ * Serving loop (continuous batching of k-th eigenvalue queries over resident
+ * matrices).  Every resident matrix gets a worker thread; each tick the worker
+ * admits queued queries up to the matrix's slot count, merges the next
+ * bisection midpoint of every in-flight query (Algorithm 1, Sec. 2) into one
+ * h2_inertia call on the matrix's stream, narrows every bracket with every new
+ * inertia record (inertia reuse, Sec. 4.2) and completes queries whose bracket
+ * is below their tolerance.  Matrices are served concurrently.  The server does
+ * not own the matrices: free them after h2s_destroy.  A matrix added to a
+ * server must not be used by the caller until h2s_destroy.
+ */
+typedef struct h2_server_s* h2_server;
+/* max_slots: in-flight queries per matrix (0 = h2_capacity of each matrix). */
+h2_status h2s_create(int32_t max_slots, h2_server* out);
+/* Make A resident; id: index used by h2s_submit.  Computes the starting
+ * interval (h2_interval) and the slot count at this point. */
+h2_status h2s_add(h2_server S, h2_matrix A, int32_t* id);
+/* Queue a query for lambda_k (1-based, ascending) of matrix id to absolute
+ * tolerance tol; returns immediately with a ticket.  H2_EINVAL for a bad id,
+ * k outside [1, n] or tol <= 0. */
+h2_status h2s_submit(h2_server S, int32_t id, int64_t k, double tol, int64_t* ticket);
+/* done = 1 and lambda set once the query has finished; the status of a failed
+ * factorization is returned for its queries. */
+h2_status h2s_poll(h2_server S, int64_t ticket, double* lambda, int32_t* done);
+/* Block until the query has finished. */
+h2_status h2s_wait(h2_server S, int64_t ticket, double* lambda);
+/* Latency percentiles (submission to completion, ms) of the finished queries,
+ * and the numbers of finished and submitted queries. */
+h2_status h2s_stats(h2_server S, double* p50_ms, double* p99_ms, int64_t* served, int64_t* submitted);
+/* Stop the workers (in-flight queries are abandoned) and free the server. */
+void h2s_destroy(h2_server S);
 
 const char* h2_last_error(void);
 

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libh2eig.so")
-SOURCES = ["kernels.hip", "engine.cpp", "plan.cpp", "host.cpp"]
+SOURCES = ["kernels.hip", "engine.cpp", "plan.cpp", "host.cpp", "server.cpp"]
 ARCH = os.environ.get("H2EIG_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -27,10 +27,7 @@ HIPFLAGS = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature",
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src + ".o")
     path = os.path.join(CSRC, src)
-    if src.endswith(".hip") or src == "engine.cpp":
-        cmd = [HIPCC] + COMMON + HIPFLAGS + ["-c", path, "-o", obj]
-    else:
-        cmd = [HIPCC] + COMMON + ["-c", path, "-o", obj]
+    cmd = [HIPCC] + COMMON + HIPFLAGS + ["-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

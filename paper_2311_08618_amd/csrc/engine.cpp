@@ -55,10 +55,22 @@ struct NoMem {
   std::string what;
 };
 
+// H2EIG_POISON=1: every workspace byte is set to 0xFF (a NaN in every double)
+// when it is allocated and before every factorization, so that a read of
+// memory the call did not write changes the result (a test of the kernels'
+// initialisation).  Read at every call.
+bool poison_on() {
+  const char* e = std::getenv("H2EIG_POISON");
+  return e && e[0] == '1';
+}
+
 // Device buffer that only grows.
 struct Arena {
   void* p = nullptr;
   size_t cap = 0;
+  void poison(hipStream_t st) {
+    if (p) HIPCHK(hipMemsetAsync(p, 0xFF, cap, st));
+  }
   void ensure(size_t bytes, hipStream_t st) {
     if (bytes <= cap) return;
     if (p) {
@@ -74,6 +86,7 @@ struct Arena {
       throw NoMem{"device allocation of " + std::to_string(want) + " bytes failed"};
     }
     cap = want;
+    if (poison_on()) poison(st);
   }
   void release() {
     if (p) (void)hipFree(p);
@@ -241,8 +254,9 @@ struct Busy {
   }
 };
 
-// longest GEMM list of the plan: sizes the per-shift tile-count scratch
-int g_max_list = 1;
+// longest GEMM list of the plan being uploaded (per thread: builds may run
+// concurrently): sizes the per-shift tile-count scratch
+thread_local int g_max_list = 1;
 
 DevList put_list(Blob& b, const GList& g) {
   DevList d;
@@ -545,6 +559,14 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
          off_sig = ((off_st + S * 4 + 255) / 256) * 256, off_nu = off_sig + S * 8,
          off_pre = off_nu + S * 8, total = off_pre + (size_t)S * (A->max_list + 1) * 4;
   A->small.ensure(total, st);
+  if (poison_on()) {
+    for (auto& a : A->sf) a.poison(st);
+    A->lvl.poison(st);
+    A->mrg.poison(st);
+    A->rs.poison(st);
+    A->small.poison(st);
+    HIPCHK(hipMemsetAsync(A->d_more, 0xFF, (MORE_SLOTS + 4) * sizeof(int), st));
+  }
   char* base = (char*)A->small.p;
   int* const dpre = (int*)(base + off_pre);
   Work w;
@@ -877,6 +899,11 @@ h2_status run_inertia(h2_matrix A, const double* sigma, int64_t ns, int64_t* nu,
 
 }  // namespace
 
+// error message of the calling thread, shared with the serving loop
+namespace h2 {
+void set_last_error(const std::string& msg) { g_err = msg; }
+}  // namespace h2
+
 // =================================================================== C ABI
 extern "C" {
 
@@ -1005,7 +1032,11 @@ h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol, cons
     b0 = A->g_hi + mg;
   }
   if (nk == 0) return H2_OK;
-  std::vector<double> lo(nk, a0), hi(nk, b0);
+  std::vector<double> lo(nk, a0), hi(nk, b0), sp(nk);
+  // split point of bracket j: the midpoint, moved by nudge[j]/64 of the width
+  // after a shift there met an exactly singular pivot (any point strictly
+  // inside the bracket keeps bisection correct)
+  std::vector<int> nudge(nk, 0);
   auto narrow = [&](double mu, int64_t v) {
     for (int64_t j = 0; j < nk; ++j) {
       if (!(mu > lo[j] && mu < hi[j])) continue;
@@ -1016,16 +1047,33 @@ h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol, cons
   for (auto& rec : A->cache) narrow(rec.first, rec.second);
   for (;;) {
     std::vector<double> mus;
-    for (int64_t j = 0; j < nk; ++j)
-      if (hi[j] - lo[j] >= tol) mus.push_back(0.5 * (lo[j] + hi[j]));
+    std::vector<char> act(nk, 0);
+    for (int64_t j = 0; j < nk; ++j) {
+      sp[j] = lo[j] + (hi[j] - lo[j]) * (0.5 + nudge[j] / 64.0);
+      // active while wider than tol and still splittable in double precision
+      if (hi[j] - lo[j] >= tol && sp[j] > lo[j] && sp[j] < hi[j]) {
+        act[j] = 1;
+        mus.push_back(sp[j]);
+      }
+    }
     if (mus.empty()) break;
     std::sort(mus.begin(), mus.end());
     mus.erase(std::unique(mus.begin(), mus.end()), mus.end());
     std::vector<int64_t> nus(mus.size());
     std::vector<int32_t> sts(mus.size());
     h2_status r = h2_inertia(A, mus.data(), (int64_t)mus.size(), nus.data(), sts.data());
-    if (r != H2_OK) return r;
-    for (size_t q = 0; q < mus.size(); ++q) narrow(mus[q], nus[q]);
+    if (r != H2_OK && r != H2_ENUMERIC) return r;
+    for (int64_t j = 0; j < nk; ++j) {
+      if (!act[j]) continue;
+      const size_t q = std::lower_bound(mus.begin(), mus.end(), sp[j]) - mus.begin();
+      if (sts[q] == H2_OK) {
+        nudge[j] = 0;
+      } else if (++nudge[j] > 8) {
+        return fail(H2_ENUMERIC, "singular pivot block at every split point tried");
+      }
+    }
+    for (size_t q = 0; q < mus.size(); ++q)
+      if (sts[q] == H2_OK) narrow(mus[q], nus[q]);
   }
   for (int64_t j = 0; j < nk; ++j) {
     lambda[j] = 0.5 * (lo[j] + hi[j]);
@@ -1033,6 +1081,31 @@ h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol, cons
       bracket[2 * j] = lo[j];
       bracket[2 * j + 1] = hi[j];
     }
+  }
+  return H2_OK;
+}
+
+h2_status h2_interval(h2_matrix A, double* ab) {
+  if (!A || !ab) return fail(H2_EINVAL, "NULL argument");
+  Busy b(A);
+  if (!b.ok) return fail(H2_EBUSY, "handle in use by another thread");
+  if (!A->have_gersh) {
+    gershgorin(A->T, A->kern, &A->g_lo, &A->g_hi);
+    A->have_gersh = true;
+  }
+  const double mg = 10.0 * A->eps * A->normA;
+  ab[0] = A->g_lo - mg;
+  ab[1] = A->g_hi + mg;
+  return H2_OK;
+}
+
+h2_status h2_capacity(h2_matrix A, int32_t* max_shifts) {
+  if (!A || !max_shifts) return fail(H2_EINVAL, "NULL argument");
+  try {
+    HIPCHK(hipSetDevice(A->device));
+    *max_shifts = auto_max_shifts(A);
+  } catch (HipError& e) {
+    return fail(H2_EDEVICE, e.where + ": " + hipGetErrorString(e.e));
   }
   return H2_OK;
 }

@@ -72,8 +72,26 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.h2_profile_read.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double)]
     lib.h2_profile_level_ms.restype = C.c_int
     lib.h2_profile_level_ms.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(C.c_double)]
+    lib.h2_interval.restype = C.c_int
+    lib.h2_interval.argtypes = [C.c_void_p, P(C.c_double)]
+    lib.h2_capacity.restype = C.c_int
+    lib.h2_capacity.argtypes = [C.c_void_p, P(C.c_int32)]
     lib.h2_free.restype = None
     lib.h2_free.argtypes = [C.c_void_p]
+    lib.h2s_create.restype = C.c_int
+    lib.h2s_create.argtypes = [C.c_int32, P(C.c_void_p)]
+    lib.h2s_add.restype = C.c_int
+    lib.h2s_add.argtypes = [C.c_void_p, C.c_void_p, P(C.c_int32)]
+    lib.h2s_submit.restype = C.c_int
+    lib.h2s_submit.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_double, P(C.c_int64)]
+    lib.h2s_poll.restype = C.c_int
+    lib.h2s_poll.argtypes = [C.c_void_p, C.c_int64, P(C.c_double), P(C.c_int32)]
+    lib.h2s_wait.restype = C.c_int
+    lib.h2s_wait.argtypes = [C.c_void_p, C.c_int64, P(C.c_double)]
+    lib.h2s_stats.restype = C.c_int
+    lib.h2s_stats.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_int64), P(C.c_int64)]
+    lib.h2s_destroy.restype = None
+    lib.h2s_destroy.argtypes = [C.c_void_p]
     lib.h2_last_error.restype = C.c_char_p
     lib.h2_last_error.argtypes = []
     return lib
@@ -83,7 +101,8 @@ _lib = load_library()
 
 EXPORTED = ["h2_build", "h2_inertia", "h2_kth_eig", "h2_norm", "h2_stats", "h2_set_stream", "h2_tree_perm",
             "h2_profile_enable", "h2_profile_classes", "h2_profile_class_name", "h2_profile_read",
-            "h2_profile_level_ms", "h2_free", "h2_last_error"]
+            "h2_profile_level_ms", "h2_interval", "h2_capacity", "h2_free", "h2_last_error",
+            "h2s_create", "h2s_add", "h2s_submit", "h2s_poll", "h2s_wait", "h2s_stats", "h2s_destroy"]
 
 
 def _check(st: int):
@@ -184,3 +203,63 @@ class H2Matrix:
 
     def set_stream(self, stream_ptr: int):
         _check(_lib.h2_set_stream(self._h, C.c_void_p(stream_ptr)))
+
+    def interval(self):
+        ab = np.zeros(2)
+        _check(_lib.h2_interval(self._h, _dptr(ab)))
+        return float(ab[0]), float(ab[1])
+
+    def capacity(self) -> int:
+        v = C.c_int32()
+        _check(_lib.h2_capacity(self._h, C.byref(v)))
+        return v.value
+
+
+class H2Server:
+    """Serving loop over resident matrices (h2s_*): continuous batching of
+    k-th eigenvalue queries, one worker per matrix.  Holds references to the
+    added matrices until close()."""
+
+    def __init__(self, max_slots: int = 0):
+        h = C.c_void_p()
+        _check(_lib.h2s_create(int(max_slots), C.byref(h)))
+        self._h = h
+        self._mats = []
+
+    def add(self, A: H2Matrix) -> int:
+        i = C.c_int32()
+        _check(_lib.h2s_add(self._h, A._h, C.byref(i)))
+        self._mats.append(A)
+        return i.value
+
+    def submit(self, mat: int, k: int, tol: float) -> int:
+        t = C.c_int64()
+        _check(_lib.h2s_submit(self._h, int(mat), int(k), float(tol), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """lambda once finished, else None."""
+        lam = C.c_double()
+        done = C.c_int32()
+        _check(_lib.h2s_poll(self._h, int(ticket), C.byref(lam), C.byref(done)))
+        return lam.value if done.value else None
+
+    def wait(self, ticket: int) -> float:
+        lam = C.c_double()
+        _check(_lib.h2s_wait(self._h, int(ticket), C.byref(lam)))
+        return lam.value
+
+    def stats(self) -> dict:
+        p50, p99 = C.c_double(), C.c_double()
+        served, submitted = C.c_int64(), C.c_int64()
+        _check(_lib.h2s_stats(self._h, C.byref(p50), C.byref(p99), C.byref(served), C.byref(submitted)))
+        return {"p50_ms": p50.value, "p99_ms": p99.value, "served": served.value, "submitted": submitted.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.h2s_destroy(self._h)
+            self._h = None
+            self._mats = []
+
+    def __del__(self):
+        self.close()

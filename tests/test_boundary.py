@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "h2eig.h")
 def _declared():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:h2_status|int32_t|const char\*|void)\s+(h2_\w+)\s*\(", txt, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:h2_status|int32_t|const char\*|void)\s+(h2s?_\w+)\s*\(", txt, flags=re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -108,3 +108,31 @@ def test_build_without_gpu_is_edevice(mod):
         mod._lib.h2_free(h)
         pytest.skip("a GPU is present")
     assert st == mod.H2_EDEVICE, st
+
+
+def test_server_argument_errors(mod):
+    """The serving loop's calls reject bad arguments before any device work;
+    a server with no matrices starts and stops cleanly."""
+    L = mod._lib
+    h = C.c_void_p()
+    assert L.h2s_create(-1, C.byref(h)) == mod.H2_EINVAL
+    assert L.h2s_create(0, None) == mod.H2_EINVAL
+    assert L.h2s_create(4, C.byref(h)) == mod.H2_OK and h.value
+    i = C.c_int32()
+    t = C.c_int64()
+    lam = C.c_double()
+    done = C.c_int32()
+    assert L.h2s_add(h, None, C.byref(i)) == mod.H2_EINVAL
+    assert L.h2s_add(None, None, C.byref(i)) == mod.H2_EINVAL
+    assert L.h2_interval(None, None) == mod.H2_EINVAL
+    assert L.h2_capacity(None, None) == mod.H2_EINVAL
+    assert L.h2s_submit(h, 0, 1, 1e-8, C.byref(t)) == mod.H2_EINVAL       # no matrix 0
+    assert L.h2s_submit(h, 0, 1, 0.0, C.byref(t)) == mod.H2_EINVAL
+    assert L.h2s_poll(h, 1, C.byref(lam), C.byref(done)) == mod.H2_EINVAL  # unknown ticket
+    assert L.h2s_wait(h, 7, C.byref(lam)) == mod.H2_EINVAL
+    p50, p99 = C.c_double(-1), C.c_double(-1)
+    served, sub = C.c_int64(-1), C.c_int64(-1)
+    assert L.h2s_stats(h, C.byref(p50), C.byref(p99), C.byref(served), C.byref(sub)) == mod.H2_OK
+    assert (p50.value, p99.value, served.value, sub.value) == (0.0, 0.0, 0, 0)
+    L.h2s_destroy(h)
+    L.h2s_destroy(None)   # no-op

@@ -1,0 +1,93 @@
+"""The serving loop (h2s_*) on the GPU: k-th eigenvalue queries for two resident
+matrices, submitted interleaved and batched by the workers (Algorithm 1 with
+inertia reuse, Secs. 2 and 4.2).  Every answer is checked against what fixes it
+independently of the path: the closed-form spectrum 2 - 2cos(j pi/(n+1)) of the
+second-difference matrix, LAPACK on the dense cube matrix, and a standalone
+h2_kth_eig on the same handle before it was made resident.
+"""
+import numpy as np
+import pytest
+
+from oracle.dense import tridiag_eigs
+from oracle.kernels import Kernel
+from paper_2311_08618_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2311_08618_amd import h2eig
+    return h2eig
+
+
+def test_serve_two_matrices_interleaved(lib):
+    print("case serve cube n=2048 + tridiag n=4096, slots 3", flush=True)
+    n1, n2, tol = 2048, 4096, 1e-8
+    X = W.cube_points(n1, 0)
+    A = lib.H2Matrix(X, W.K_LAPLACE, 1e3, 128, 1.0, 1e-8)
+    T = lib.H2Matrix(W.line_points(n2), W.K_TRIDIAG_1D, 2.0, 64, 1.0, 1e-12, p0=1.0)
+    dense = np.linalg.eigvalsh(Kernel(W.K_LAPLACE, 1e3).dense(X))
+    exact_t = tridiag_eigs(n2)
+    rng = np.random.default_rng(5)
+    ks_a = [int(k) for k in rng.integers(1, n1 + 1, 5)] + [n1 // 2, n1 // 2]   # a repeated query
+    ks_t = [1, n2] + [int(k) for k in rng.integers(1, n2 + 1, 4)]
+    alone_a, _ = A.kth_eig(ks_a, tol)
+    bound_a = tol / 2 + 10 * 1e-8 * A.norm()
+    bound_t = tol / 2 + 10 * 1e-12 * T.norm()
+    # the first midpoint of the Gershgorin interval [0, 4] is 2, where the
+    # leaf pivot blocks of odd order are exactly singular: bisection must
+    # split elsewhere and still converge
+    assert T.inertia(np.array([2.0]), return_status=True)[1][0] == lib.H2_ENUMERIC
+    alone_t, _ = T.kth_eig([n2 // 2, n2 // 2 + 1], tol)
+    assert np.all(np.abs(alone_t - exact_t[[n2 // 2 - 1, n2 // 2]]) <= bound_t), alone_t
+
+    S = lib.H2Server(max_slots=3)
+    try:
+        ia, it = S.add(A), S.add(T)
+        assert (ia, it) == (0, 1)
+        tickets = []
+        for j in range(max(len(ks_a), len(ks_t))):
+            if j < len(ks_a):
+                tickets.append(("a", ks_a[j], j, S.submit(ia, ks_a[j], tol)))
+            if j < len(ks_t):
+                tickets.append(("t", ks_t[j], j, S.submit(it, ks_t[j], tol)))
+        for which, k, j, tk in tickets:
+            lam = S.wait(tk)
+            assert S.poll(tk) == lam
+            if which == "a":
+                assert abs(lam - dense[k - 1]) <= bound_a, (k, lam, dense[k - 1])
+                assert abs(lam - alone_a[j]) <= tol + 10 * 1e-8 * A.norm(), (k, lam, alone_a[j])
+            else:
+                assert abs(lam - exact_t[k - 1]) <= bound_t, (k, lam, exact_t[k - 1])
+        st = S.stats()
+        assert st["served"] == st["submitted"] == len(ks_a) + len(ks_t)
+        assert 0.0 < st["p50_ms"] <= st["p99_ms"]
+    finally:
+        S.close()
+    # the handles are the caller's again once the server is gone
+    nu = T.inertia(np.array([2.5]))
+    assert nu[0] == int(np.sum(exact_t < 2.5))
+
+
+def test_serve_one_slot_queue(lib):
+    """One slot: queries wait in the queue and are admitted one at a time."""
+    print("case serve tridiag n=1024, slots 1", flush=True)
+    n, tol = 1024, 1e-9
+    T = lib.H2Matrix(W.line_points(n), W.K_TRIDIAG_1D, 2.0, 32, 1.0, 1e-12, p0=1.0)
+    exact = tridiag_eigs(n)
+    S = lib.H2Server(max_slots=1)
+    try:
+        m = S.add(T)
+        ks = [3, 500, 1024, 77, 3]
+        tk = [S.submit(m, k, tol) for k in ks]
+        for k, t in zip(ks, tk):
+            lam = S.wait(t)
+            assert abs(lam - exact[k - 1]) <= tol / 2 + 10 * 1e-12 * T.norm(), (k, lam)
+        with pytest.raises(lib.H2EigError):
+            S.submit(m, n + 1, tol)
+        with pytest.raises(lib.H2EigError):
+            S.submit(5, 1, tol)
+        assert S.stats()["served"] == len(ks)
+    finally:
+        S.close()
