@@ -19,8 +19,11 @@ sample of the same workload family).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
+import re
 import sys
 import time
 
@@ -31,6 +34,128 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
 HBM_PEAK_GBS = 8000.0
 GEMM_CLASSES = {"recompress_w", "rotate", "elimination", "schur", "fillin_gram", "merge_fillin", "merge_transfer",
                 "pivot_ldl_inverse", "recompress_pchol_update", "pivot_ldl_update"}
+
+
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2311_08618_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_gemm_nt_cube_laplace_n262144.md")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, n: int, S: int):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None
+    when it covers another kernel or workload, or the kernel source changed
+    since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    fields = dict(re.findall(r"^- (\w+): (.+)$", txt, flags=re.M))
+    try:
+        if (fields["kernel"].strip() != kernel or int(fields["n"]) != n or int(fields["shifts_per_step"]) != S
+                or fields["kernels_hip_sha256_16"].strip() != kernel_source_hash()):
+            return None
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(nbytes: int, reps: int = 4):
+    """A plain device-to-device copy of nbytes, reps times: the reference that
+    scales the HBM byte counters (FETCH_SIZE reads nbytes, WRITE_SIZE writes
+    nbytes per copy)."""
+    import torch
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 8, "reps": reps}))
+
+
+def serve_bench(args):
+    """Serving loop: matrices resident in HBM, Poisson arrivals of k-th
+    eigenvalue queries, continuous batching per matrix (h2s_*).  Prints one
+    JSON line with the latency percentiles (arrival to result) and the served
+    and offered rates."""
+    import numpy as np
+    from paper_2311_08618_amd import workloads as W
+    from paper_2311_08618_amd.h2eig import H2Matrix, H2Server
+
+    sizes = [int(x) for x in args.serve_sizes.split(",")]
+    slots = [int(x) for x in args.serve_slots.split(",")]
+    seeds = {n: i for i, n in enumerate(sorted(sizes))}
+    t0 = time.perf_counter()
+    mats = [H2Matrix(W.cube_points(n, seeds[n]), W.K_LAPLACE, 1e3, 256, 1.0, 1e-8) for n in sizes]
+    build_s = time.perf_counter() - t0
+    print("serve: built %s in %.1f s" % (sizes, build_s), file=sys.stderr, flush=True)
+    srv = H2Server()
+    t0 = time.perf_counter()
+    ids = [srv.add(A, s) for A, s in zip(mats, slots)]
+    add_s = time.perf_counter() - t0
+    print("serve: resident, workspace reserved in %.1f s" % add_s, file=sys.stderr, flush=True)
+    rng = np.random.default_rng(7)
+    arr = np.cumsum(rng.exponential(1.0 / args.serve_rate, size=int(args.serve_rate * args.serve_window * 2) + 16))
+    arr = arr[arr < args.serve_window]
+    which = rng.integers(0, len(sizes), len(arr))
+    tols = np.where(rng.random(len(arr)) < 0.5, 1e-6, 1e-10)
+    ks = [int(rng.integers(1, sizes[w] + 1)) for w in which]
+    tickets = []
+    t0 = time.perf_counter()
+    for t_a, w, k, tol in zip(arr, which, ks, tols):
+        dt = t0 + t_a - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(ids[w], k, float(tol)))
+    print("serve: %d queries submitted over %.1f s" % (len(tickets), args.serve_window), file=sys.stderr, flush=True)
+    done = {}
+    t_last = time.perf_counter()
+    while len(done) < len(tickets) and time.perf_counter() - t0 < args.serve_cap:
+        for tk in tickets:
+            if tk not in done:
+                lam = srv.poll(tk)
+                if lam is not None:
+                    done[tk] = lam
+        if time.perf_counter() - t_last > 10.0:
+            t_last = time.perf_counter()
+            print("serve: %d/%d served after %.0f s" % (len(done), len(tickets), t_last - t0),
+                  file=sys.stderr, flush=True)
+        time.sleep(0.05)
+    elapsed = time.perf_counter() - t0
+    st = srv.stats()
+    per = {}
+    for n in sizes:
+        idx = [j for j, w in enumerate(which) if sizes[w] == n]
+        per[str(n)] = {"offered": len(idx), "served": sum(1 for j in idx if tickets[j] in done)}
+    srv.close()
+    line = {
+        "metric": "k-th eigenvalue queries served/s (serving loop, continuous batching)",
+        "value": st["served"] / elapsed,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f64",
+        "data": "synthetic",
+        "p50_ms": st["p50_ms"],
+        "p99_ms": st["p99_ms"],
+        "served": st["served"],
+        "offered": len(tickets),
+        "offered_rate": len(tickets) / args.serve_window,
+        "unfinished_at_cap": len(tickets) - st["served"],
+        "elapsed_s": elapsed,
+        "per_matrix": per,
+        "config": {"workload": "cube-laplace resident n=%s leaf=256 eta=1 eps=1e-8 A_ii=1e3; Poisson %g/s for %g s "
+                               "(seed 7), k uniform in [1,n], tol 1e-6 or 1e-10 (p=0.5); drain cap %g s"
+                               % (sizes, args.serve_rate, args.serve_window, args.serve_cap),
+                   "slots": dict(zip(map(str, sizes), slots)), "build_s": round(build_s, 1),
+                   "reserve_s": round(add_s, 1)},
+    }
+    print(json.dumps(line))
 
 
 def cpu_baseline(n_sample: int = 4096, shifts: int = 4, n_target: int = 262144) -> dict:
@@ -69,11 +194,25 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 18)
     ap.add_argument("--batch", type=int, default=2, help="shifts per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="serving-loop measurement instead of the step bench")
+    ap.add_argument("--serve-sizes", default="262144,131072,65536,16384")
+    ap.add_argument("--serve-slots", default="1,1,2,4", help="in-flight queries per matrix")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-window", type=float, default=1.0, help="seconds of arrivals")
+    ap.add_argument("--serve-cap", type=float, default=120.0, help="seconds until the measurement stops")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the batch of shifts is one GPU's share); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_calib:
+        copy_calibration(args.copy_calib)
+        return
+    if args.serve:
+        serve_bench(args)
+        return
 
     from paper_2311_08618_amd import workloads as W
     from paper_2311_08618_amd.h2eig import H2Matrix
@@ -113,7 +252,7 @@ def main():
         "peak": PEAK_FP64_TFLOPS,
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP64_TFLOPS,
-        "traffic": None,
+        "traffic": measured_traffic("h2::" + kname, n, S),
         "launches": krec["launches"],
         "avg_launch_ms": krec["ms"] / max(1, krec["launches"]),
         "share_of_step": krec["ms"] / (dt * 1e3),
@@ -121,6 +260,10 @@ def main():
                          "bound": "mfma" if cname in GEMM_CLASSES else "latency"},
     }
     total_flops = sum(v["flops"] for v in roles.values())
+    # k-th eigenvalues per second implied by this rate: one query takes
+    # ceil(log2((b - a) / tol)) bisection steps from the starting interval
+    a0, b0 = A.interval()
+    steps_q = {tol: math.ceil(math.log2((b0 - a0) / tol)) for tol in (1e-6, 1e-10)}
     line = {
         "metric": "H2 LDL+inertia evals/sec at n=2^18",
         "value": value,
@@ -138,6 +281,8 @@ def main():
                    "n": n, "shifts_per_step": S, "build_s": round(build_s, 2)},
         "roofline": roofline,
         "path_tflops": total_flops / dt / 1e12,
+        "kth_eigvals_per_s_derived": {"tol=%g" % t: value / s for t, s in steps_q.items()},
+        "steps_per_query": {"tol=%g" % t: s for t, s in steps_q.items()},
         "max_cluster_dim": st["last_rank_max"],
         "workspace_gb": st["last_work_bytes"] / 1e9,
         "nu": [int(x) for x in nu],

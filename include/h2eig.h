@@ -125,14 +125,20 @@ h2_status h2_norm(h2_matrix A, double* normA);
 
 /* Default starting interval of Algorithm 1 (Sec. 2) used when h2_kth_eig gets
  * ab = NULL: the Gershgorin interval of the kernel matrix widened by
- * 10*eps*normA on both sides (it contains the spectrum of the H^2 matrix).
- * ab: host output, 2 doubles.  Computed once per handle (O(n^2) kernel
- * evaluations on the host), then cached. */
+ * 10*eps*normA on both sides to cover the approximation error of the H^2
+ * matrix.  ab: host output, 2 doubles.  Computed once per handle (all n^2
+ * kernel entries, summed on the device), then cached.  H2_EDEVICE on a HIP
+ * error. */
 h2_status h2_interval(h2_matrix A, double* ab);
 
 /* Shifts this handle factors together in one launch, from the free device
  * memory at the time of the call (the admission unit of the serving loop). */
 h2_status h2_capacity(h2_matrix A, int32_t* max_shifts);
+
+/* Cap on the shifts factored together in one launch (0 = automatic, from the
+ * free device memory at each call); larger batches are split.  H2_EINVAL for
+ * max_shifts < 0. */
+h2_status h2_set_max_shifts(h2_matrix A, int32_t max_shifts);
 
 typedef struct {
   int64_t n;
@@ -198,9 +204,14 @@ void h2_free(h2_matrix A);
 typedef struct h2_server_s* h2_server;
 /* max_slots: in-flight queries per matrix (0 = h2_capacity of each matrix). */
 h2_status h2s_create(int32_t max_slots, h2_server* out);
-/* Make A resident; id: index used by h2s_submit.  Computes the starting
- * interval (h2_interval) and the slot count at this point. */
-h2_status h2s_add(h2_server S, h2_matrix A, int32_t* id);
+/* Make A resident with `slots` in-flight queries (0 = the smaller of the
+ * server's max_slots, if set, and h2_capacity); id: index used by h2s_submit.
+ * Admission by memory: the call caps A's batch at `slots` shifts and reserves
+ * their device workspace now by running the first step of every future query
+ * (the starting interval h2_interval cut at `slots` equally spaced shifts,
+ * whose counts seed the matrix's records), since the workspace of a shift is
+ * known only once its ranks are.  H2_ENOMEM if even that does not fit. */
+h2_status h2s_add(h2_server S, h2_matrix A, int32_t slots, int32_t* id);
 /* Queue a query for lambda_k (1-based, ascending) of matrix id to absolute
  * tolerance tol; returns immediately with a ticket.  H2_EINVAL for a bad id,
  * k outside [1, n] or tol <= 0. */

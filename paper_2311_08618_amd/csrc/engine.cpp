@@ -851,6 +851,37 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
   if (maxdim_out) *maxdim_out = maxdim;
 }
 
+// Gershgorin interval [min_i A_ii - rad_i, max_i A_ii + rad_i] of the kernel
+// matrix, rad_i = sum_{j != i} |A_ij| over all n points, computed on the device
+// once per handle.
+void ensure_gershgorin(h2_matrix A) {
+  if (A->have_gersh) return;
+  const Tree& T = A->T;
+  const int64_t n = T.n;
+  hipStream_t st = A->stream;
+  double *dX = nullptr, *drad = nullptr;
+  struct Guard {
+    double** a;
+    double** b;
+    ~Guard() {
+      if (*a) (void)hipFree(*a);
+      if (*b) (void)hipFree(*b);
+    }
+  } guard{&dX, &drad};
+  HIPCHK(hipMalloc(&dX, (size_t)n * T.dim * 8));
+  HIPCHK(hipMalloc(&drad, (size_t)n * 8));
+  HIPCHK(hipMemcpyAsync(dX, T.X.data(), (size_t)n * T.dim * 8, hipMemcpyHostToDevice, st));
+  launch_row_abs_sum(dX, n, T.dim, A->kern.kind, A->kern.p0, A->kern.p1, drad, st);
+  HIPCHK(hipGetLastError());
+  std::vector<double> rad(n);
+  HIPCHK(hipMemcpyAsync(rad.data(), drad, (size_t)n * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double rmax = *std::max_element(rad.begin(), rad.end());
+  A->g_lo = A->kern.diag - rmax;
+  A->g_hi = A->kern.diag + rmax;
+  A->have_gersh = true;
+}
+
 int auto_max_shifts(h2_matrix A) {
   if (A->max_shifts > 0) return A->max_shifts;
   size_t freeb = 0, totalb = 0;
@@ -1023,13 +1054,11 @@ h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol, cons
     b0 = ab[1];
     if (!(std::isfinite(a0) && std::isfinite(b0) && a0 < b0)) return fail(H2_EINVAL, "bad interval ab");
   } else {
-    if (!A->have_gersh) {
-      gershgorin(A->T, A->kern, &A->g_lo, &A->g_hi);
-      A->have_gersh = true;
-    }
-    double mg = 10.0 * A->eps * A->normA;
-    a0 = A->g_lo - mg;
-    b0 = A->g_hi + mg;
+    double iv[2];
+    const h2_status r = h2_interval(A, iv);
+    if (r != H2_OK) return r;
+    a0 = iv[0];
+    b0 = iv[1];
   }
   if (nk == 0) return H2_OK;
   std::vector<double> lo(nk, a0), hi(nk, b0), sp(nk);
@@ -1089,13 +1118,24 @@ h2_status h2_interval(h2_matrix A, double* ab) {
   if (!A || !ab) return fail(H2_EINVAL, "NULL argument");
   Busy b(A);
   if (!b.ok) return fail(H2_EBUSY, "handle in use by another thread");
-  if (!A->have_gersh) {
-    gershgorin(A->T, A->kern, &A->g_lo, &A->g_hi);
-    A->have_gersh = true;
+  try {
+    HIPCHK(hipSetDevice(A->device));
+    ensure_gershgorin(A);
+  } catch (HipError& e) {
+    return fail(H2_EDEVICE, e.where + ": " + hipGetErrorString(e.e));
   }
   const double mg = 10.0 * A->eps * A->normA;
   ab[0] = A->g_lo - mg;
   ab[1] = A->g_hi + mg;
+  return H2_OK;
+}
+
+h2_status h2_set_max_shifts(h2_matrix A, int32_t max_shifts) {
+  if (!A) return fail(H2_EINVAL, "NULL handle");
+  if (max_shifts < 0) return fail(H2_EINVAL, "max_shifts must be >= 0");
+  Busy b(A);
+  if (!b.ok) return fail(H2_EBUSY, "handle in use by another thread");
+  A->max_shifts = max_shifts;
   return H2_OK;
 }
 

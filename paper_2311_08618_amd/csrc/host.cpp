@@ -342,20 +342,6 @@ double estimate_norm(const Tree& T, const KernelSpec& k) {
   return std::max(tot / (double)nrows, std::fabs(k.diag));
 }
 
-void gershgorin(const Tree& T, const KernelSpec& k, double* lo, double* hi) {
-  int64_t n = T.n;
-  std::vector<double> a(n), b(n);
-  parallel_for(n, default_threads(), [&](int64_t i) {
-    double rad = 0.0;
-    for (int64_t j = 0; j < n; ++j)
-      if (j != i) rad += std::fabs(kernel_f(k, dist(T, i, j)));
-    a[i] = k.diag - rad;
-    b[i] = k.diag + rad;
-  });
-  *lo = *std::min_element(a.begin(), a.end());
-  *hi = *std::max_element(b.begin(), b.end());
-}
-
 void build_basis(const Tree& T, const BuildParams& P, double tau, Basis& B) {
   int L = T.L;
   const bool exact = T.n <= 16384;

@@ -62,7 +62,6 @@ struct BuildParams {
 // Computes normA (mean sampled row sum / |diag|), the bases and the couplings.
 void build_basis(const Tree& T, const BuildParams& P, double tau, Basis& B);
 double estimate_norm(const Tree& T, const KernelSpec& k);
-void gershgorin(const Tree& T, const KernelSpec& k, double* lo, double* hi);
 
 // small dense helpers (column-major)
 void kernel_block(const Tree& T, const KernelSpec& k, const int64_t* rows, int nr,

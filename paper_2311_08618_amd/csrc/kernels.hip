@@ -1313,6 +1313,51 @@ __device__ inline double kf(int kind, double p0, double p1, double r) {
   return 0.0;
 }
 
+// Gershgorin radii: rad_i = sum_{j != i} |f(|x_i - x_j|)| over all n points
+// (X row-major n x dim).  One row per thread; the column points stream through
+// LDS in tiles of 256.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_row_abs_sum(const double* __restrict__ X, int64_t n, int dim, double p0,
+                                                     double p1, double* __restrict__ rad) {
+  __shared__ double tx[256], ty[256], tz[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double xi = 0.0, yi = 0.0, zi = 0.0;
+  if (i < n) {
+    xi = X[i * dim];
+    if (dim > 1) yi = X[i * dim + 1];
+    if (dim > 2) zi = X[i * dim + 2];
+  }
+  double acc = 0.0;
+  for (int64_t j0 = 0; j0 < n; j0 += 256) {
+    __syncthreads();
+    const int64_t j = j0 + threadIdx.x;
+    tx[threadIdx.x] = j < n ? X[j * dim] : 0.0;
+    ty[threadIdx.x] = (j < n && dim > 1) ? X[j * dim + 1] : 0.0;
+    tz[threadIdx.x] = (j < n && dim > 2) ? X[j * dim + 2] : 0.0;
+    __syncthreads();
+    const int jn = (int)min<int64_t>(256, n - j0);
+    for (int q = 0; q < jn; ++q) {
+      const double dx = xi - tx[q], dy = yi - ty[q], dz = zi - tz[q];
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      const double v = fabs(kf(KIND, p0, p1, r));
+      acc += (j0 + q == i) ? 0.0 : v;
+    }
+  }
+  if (i < n) rad[i] = acc;
+}
+
+void launch_row_abs_sum(const double* X, int64_t n, int dim, int kind, double p0, double p1, double* rad,
+                        hipStream_t st) {
+  const dim3 g((unsigned)((n + 255) / 256)), b(256);
+  switch (kind) {
+    case 0: hipLaunchKernelGGL(k_row_abs_sum<0>, g, b, 0, st, X, n, dim, p0, p1, rad); break;
+    case 1: hipLaunchKernelGGL(k_row_abs_sum<1>, g, b, 0, st, X, n, dim, p0, p1, rad); break;
+    case 2: hipLaunchKernelGGL(k_row_abs_sum<2>, g, b, 0, st, X, n, dim, p0, p1, rad); break;
+    case 3: hipLaunchKernelGGL(k_row_abs_sum<3>, g, b, 0, st, X, n, dim, p0, p1, rad); break;
+    default: hipLaunchKernelGGL(k_row_abs_sum<4>, g, b, 0, st, X, n, dim, p0, p1, rad); break;
+  }
+}
+
 // near block (i, j) of the leaf level: A(tau_i, tau_j) in leaf order
 __global__ void k_kernel_blocks(double* out, int64_t bstride, int ld, const int* __restrict__ bi, const int* __restrict__ bj,
                                 const int64_t* __restrict__ start, const int* __restrict__ msz, const double* __restrict__ X,

@@ -52,6 +52,8 @@ void launch_next_sizes(const SizeTab& sz, int nshift, hipStream_t st);
 void launch_leaf_init(const BufTab& bt, int nblk, const int* blk_diag_m, const double* sigma, int cap, int nshift,
                       hipStream_t st);
 void launch_sizes_init(const SizeTab& sz, const int* m0, int nshift, hipStream_t st);
+void launch_row_abs_sum(const double* X, int64_t n, int dim, int kind, double p0, double p1, double* rad,
+                        hipStream_t st);
 void launch_kernel_blocks(double* out, int64_t bstride, int ld, const int* bi, const int* bj, int nblk,
                           const int64_t* start, const int* msz, const double* X, int dim, int kind, double diag,
                           double p0, double p1, int* bad, hipStream_t st);

@@ -199,8 +199,9 @@ h2_status h2s_create(int32_t max_slots, h2_server* out) {
   return H2_OK;
 }
 
-h2_status h2s_add(h2_server S, h2_matrix A, int32_t* id) {
+h2_status h2s_add(h2_server S, h2_matrix A, int32_t slots, int32_t* id) {
   if (!S || !A || !id) return fail(H2_EINVAL, "NULL argument");
+  if (slots < 0) return fail(H2_EINVAL, "slots must be >= 0");
   auto R = std::make_unique<Resident>();
   R->A = A;
   double ab[2];
@@ -215,7 +216,19 @@ h2_status h2s_add(h2_server S, h2_matrix A, int32_t* id) {
   R->n = st.n;
   R->a0 = ab[0];
   R->b0 = ab[1];
-  R->slots = std::max(1, S->max_slots > 0 ? std::min(S->max_slots, cap) : cap);
+  R->slots = slots > 0 ? slots : std::max(1, S->max_slots > 0 ? std::min(S->max_slots, cap) : cap);
+  // reserve the workspace of `slots` shifts: the first step of every query,
+  // a multisection of the starting interval
+  r = h2_set_max_shifts(A, R->slots);
+  if (r != H2_OK) return r;
+  std::vector<double> mus(R->slots);
+  std::vector<int64_t> nus(R->slots);
+  std::vector<int32_t> sts(R->slots);
+  for (int j = 0; j < R->slots; ++j) mus[j] = R->a0 + (R->b0 - R->a0) * (j + 1) / (R->slots + 1);
+  r = h2_inertia(A, mus.data(), R->slots, nus.data(), sts.data());
+  if (r != H2_OK && r != H2_ENUMERIC) return r;
+  for (int j = 0; j < R->slots; ++j)
+    if (sts[j] == H2_OK) R->records.push_back({mus[j], nus[j]});
   std::lock_guard<std::mutex> g(S->mu);
   if (S->stop) return fail(H2_EINVAL, "server is shutting down");
   *id = (int32_t)S->mats.size();

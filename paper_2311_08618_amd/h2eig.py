@@ -76,12 +76,14 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.h2_interval.argtypes = [C.c_void_p, P(C.c_double)]
     lib.h2_capacity.restype = C.c_int
     lib.h2_capacity.argtypes = [C.c_void_p, P(C.c_int32)]
+    lib.h2_set_max_shifts.restype = C.c_int
+    lib.h2_set_max_shifts.argtypes = [C.c_void_p, C.c_int32]
     lib.h2_free.restype = None
     lib.h2_free.argtypes = [C.c_void_p]
     lib.h2s_create.restype = C.c_int
     lib.h2s_create.argtypes = [C.c_int32, P(C.c_void_p)]
     lib.h2s_add.restype = C.c_int
-    lib.h2s_add.argtypes = [C.c_void_p, C.c_void_p, P(C.c_int32)]
+    lib.h2s_add.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, P(C.c_int32)]
     lib.h2s_submit.restype = C.c_int
     lib.h2s_submit.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_double, P(C.c_int64)]
     lib.h2s_poll.restype = C.c_int
@@ -101,7 +103,7 @@ _lib = load_library()
 
 EXPORTED = ["h2_build", "h2_inertia", "h2_kth_eig", "h2_norm", "h2_stats", "h2_set_stream", "h2_tree_perm",
             "h2_profile_enable", "h2_profile_classes", "h2_profile_class_name", "h2_profile_read",
-            "h2_profile_level_ms", "h2_interval", "h2_capacity", "h2_free", "h2_last_error",
+            "h2_profile_level_ms", "h2_interval", "h2_capacity", "h2_set_max_shifts", "h2_free", "h2_last_error",
             "h2s_create", "h2s_add", "h2s_submit", "h2s_poll", "h2s_wait", "h2s_stats", "h2s_destroy"]
 
 
@@ -209,6 +211,9 @@ class H2Matrix:
         _check(_lib.h2_interval(self._h, _dptr(ab)))
         return float(ab[0]), float(ab[1])
 
+    def set_max_shifts(self, max_shifts: int):
+        _check(_lib.h2_set_max_shifts(self._h, int(max_shifts)))
+
     def capacity(self) -> int:
         v = C.c_int32()
         _check(_lib.h2_capacity(self._h, C.byref(v)))
@@ -226,9 +231,9 @@ class H2Server:
         self._h = h
         self._mats = []
 
-    def add(self, A: H2Matrix) -> int:
+    def add(self, A: H2Matrix, slots: int = 0) -> int:
         i = C.c_int32()
-        _check(_lib.h2s_add(self._h, A._h, C.byref(i)))
+        _check(_lib.h2s_add(self._h, A._h, int(slots), C.byref(i)))
         self._mats.append(A)
         return i.value
 

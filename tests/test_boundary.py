@@ -122,8 +122,9 @@ def test_server_argument_errors(mod):
     t = C.c_int64()
     lam = C.c_double()
     done = C.c_int32()
-    assert L.h2s_add(h, None, C.byref(i)) == mod.H2_EINVAL
-    assert L.h2s_add(None, None, C.byref(i)) == mod.H2_EINVAL
+    assert L.h2s_add(h, None, 0, C.byref(i)) == mod.H2_EINVAL
+    assert L.h2s_add(None, None, 0, C.byref(i)) == mod.H2_EINVAL
+    assert L.h2_set_max_shifts(None, 1) == mod.H2_EINVAL
     assert L.h2_interval(None, None) == mod.H2_EINVAL
     assert L.h2_capacity(None, None) == mod.H2_EINVAL
     assert L.h2s_submit(h, 0, 1, 1e-8, C.byref(t)) == mod.H2_EINVAL       # no matrix 0

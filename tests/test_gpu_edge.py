@@ -93,3 +93,21 @@ def test_cube_full_size_properties(lib):
     assert one[0] == nu[2]
     again = A.inertia(np.array([1000.0]))
     assert again[0] == one[0]
+
+
+@pytest.mark.parametrize("n,dim,kind,diag", [(2048, 3, W.K_LAPLACE, 1e3), (1000, 2, W.K_YUKAWA, 50.0)])
+def test_interval_is_gershgorin(lib, n, dim, kind, diag):
+    """h2_interval = [min_i A_ii - rad_i, max_i A_ii + rad_i] -/+ 10 eps normA,
+    rad_i = sum_{j != i} |A_ij| of the dense kernel matrix (a ragged last tile
+    and a 2-D point set included)."""
+    print("case interval n=%d dim=%d kind=%d" % (n, dim, kind), flush=True)
+    X = np.random.default_rng(3).random((n, dim))
+    eps = 1e-8
+    A = lib.H2Matrix(X, kind, diag, 64, 1.0, eps)
+    D = Kernel(kind, diag).dense(X)
+    rad = np.sum(np.abs(D), axis=1) - np.abs(np.diag(D))
+    mg = 10 * eps * A.norm()
+    want = (diag - rad.max() - mg, diag + rad.max() + mg)
+    got = A.interval()
+    assert abs(got[0] - want[0]) <= 1e-12 * abs(rad.max()) + 1e-12 and abs(got[1] - want[1]) <= 1e-12 * rad.max(), \
+        (got, want)
