@@ -235,6 +235,12 @@ def main():
     prof = A.profile_read()
     A.profile_enable(False)
     st = A.stats()
+    # the same shifts with the contractions in FP32 (h2_inertia_f32), outside
+    # the timed region of `value`: its rate and whether its counts agree
+    t1 = time.perf_counter()
+    nu32 = A.inertia(sig, f32=True)
+    dt32 = time.perf_counter() - t1
+    print("bench: FP32 step done", file=sys.stderr, flush=True)
 
     evals = S * args.steps
     value = evals / dt
@@ -286,6 +292,10 @@ def main():
         "max_cluster_dim": st["last_rank_max"],
         "workspace_gb": st["last_work_bytes"] / 1e9,
         "nu": [int(x) for x in nu],
+        "f32_step": {"evals_per_s": S / dt32, "ms_per_step": dt32 * 1e3, "nu": [int(x) for x in nu32],
+                     "counts_equal_f64": bool(list(nu32) == list(nu)),
+                     "note": "rotation, elimination, Schur and merge contractions in FP32; recompression and "
+                             "pivot LDL in FP64"},
         "classes_ms": {k: round(v["ms"], 1) for k, v in roles.items()},
         "gemm_kernels_ms": {k: round(v["ms"], 1) for k, v in kern.items()},
     }

@@ -105,6 +105,20 @@ h2_status h2_inertia(h2_matrix A, const double* sigma, int64_t nshift,
                      int64_t* nu, int32_t* status);
 
 /*
+ * The same counts with the contractions of the basis rotation, elimination,
+ * Schur updates and merge (Eqs. blr2-diag-elimination, blr2-diag-schur;
+ * Sec. 3.3) multiplied in FP32 on the matrix cores with FP32 accumulation;
+ * operands and results stay FP64 in memory, and the recompression (rank
+ * decisions, Sec. 3.4) and the pivot-block LDL with its negative count run in
+ * FP64.  Meant for shifts far from every eigenvalue (early bisection steps):
+ * a count may differ from h2_inertia's when an eigenvalue lies within the
+ * FP32 error of sigma.  Arguments and errors as h2_inertia.  The counts do
+ * not join the handle's record cache.
+ */
+h2_status h2_inertia_f32(h2_matrix A, const double* sigma, int64_t nshift,
+                         int64_t* nu, int32_t* status);
+
+/*
  * k-th smallest eigenvalues of A~ by Algorithm 1 (bisection), for nk 1-based
  * indices k[j] in [1, n], to absolute tolerance tol > 0:
  *   lambda[j] = midpoint of the final bracket, |lambda - lambda_k| < tol/2 when
@@ -122,6 +136,16 @@ h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol,
 /* normA used for tau = eps*normA: max(mean row sum of A over rows i = 0 mod s,
  * |A_ii|), s = max(1, n/16384). */
 h2_status h2_norm(h2_matrix A, double* normA);
+
+/* Precision policy of h2_kth_eig (and of nothing else): a bracket is bisected
+ * with h2_inertia_f32 while it is at least switch_rel * normA wide, then in
+ * FP64.  At the switch its two ends, when FP32 counts set them, are counted in
+ * FP64 and the bracket is rebuilt from FP64 counts alone (the largest shift
+ * with fewer than k eigenvalues below it, then the smallest larger shift with
+ * at least k), so a wrong FP32 decision falls back to the nearest FP64-checked
+ * shifts.  0 (the default) = FP64 throughout.  H2_EINVAL for a negative or
+ * non-finite value. */
+h2_status h2_set_mixed(h2_matrix A, double switch_rel);
 
 /* Default starting interval of Algorithm 1 (Sec. 2) used when h2_kth_eig gets
  * ab = NULL: the Gershgorin interval of the kernel matrix widened by
@@ -155,7 +179,9 @@ typedef struct {
   double build_seconds;
   int32_t last_rank_max;    /* largest cluster dimension met in the last
                                factorization (after rank growth)               */
-  int32_t reserved[5];
+  int32_t evals_f64;        /* shifts factored in FP64 since h2_build          */
+  int32_t evals_f32;        /* shifts factored with FP32 contractions          */
+  int32_t reserved[3];
 } h2_stats_t;
 
 h2_status h2_stats(h2_matrix A, h2_stats_t* out);

@@ -68,6 +68,7 @@ struct BufTab {
   int ld[NBUF];      // leading dimension
   unsigned long long* fc;   // algorithmic flop counter of the launch's kernel class (or null)
   unsigned long long* fck;  // second counter, per kernel symbol (GEMM layouts), or null
+  int f32;                  // GEMMs of this launch multiply in FP32 (operands rounded, FP32 accumulation)
 };
 
 struct SizeTab {

@@ -140,9 +140,18 @@ const char* const kProfNames[PC_N] = {"init", "recompress_pchol", "recompress_pc
                                       "pivot_ldl_update", "pivot_ldl_inverse", "pivot_ldl_operator", "elimination",
                                       "copyback", "schur", "fillin_gram", "merge_gather", "merge_fillin",
                                       "merge_transfer"};
-// per-kernel totals of the GEMM kernel by operand layout (GemmKind order)
-const char* const kGemmNames[4] = {"kernel:k_gemm<false, false>", "kernel:k_gemm<false, true>",
-                                   "kernel:k_gemm<true, false>", "kernel:k_gemm<true, true>"};
+// per-kernel totals of the GEMM kernels by operand layout (GemmKind order),
+// FP64 then FP32
+constexpr int PROF_N = PC_N + 8;
+const char* const kGemmNames[8] = {"kernel:k_gemm<false, false>",     "kernel:k_gemm<false, true>",
+                                   "kernel:k_gemm<true, false>",      "kernel:k_gemm<true, true>",
+                                   "kernel:k_gemm_f32<false, false>", "kernel:k_gemm_f32<false, true>",
+                                   "kernel:k_gemm_f32<true, false>",  "kernel:k_gemm_f32<true, true>"};
+// classes whose contractions run in FP32 in an FP32 factorization (rotation,
+// elimination, Schur, merge); recompression and the pivot LDL stay FP64
+inline bool f32_class(int cls) {
+  return cls == PC_ROTATE || cls == PC_ELIM || cls == PC_SCHUR || cls == PC_MERGE_FILL || cls == PC_MERGE_E;
+}
 
 // Brackets kernel launches with HIP events on the handle's stream and keeps a
 // device array of per-class algorithmic flop counters.
@@ -152,10 +161,10 @@ struct Profiler {
   size_t used = 0;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> recs;
   int level = 0;                     // level of the records being made (for the per-level table)
-  double ms_level[PC_N + 4][32] = {{0}};
-  double ms[PC_N + 4] = {0};              // classes, then the four GEMM layouts (kernel symbols)
-  long long launches[PC_N + 4] = {0};
-  unsigned long long flops[PC_N + 4] = {0};
+  double ms_level[PROF_N][32] = {{0}};
+  double ms[PROF_N] = {0};              // classes, then the GEMM kernel symbols
+  long long launches[PROF_N] = {0};
+  unsigned long long flops[PROF_N] = {0};
   unsigned long long* d_fc = nullptr;
   hipEvent_t get() {
     if (used == pool.size()) {
@@ -166,7 +175,7 @@ struct Profiler {
     return pool[used++];
   }
   void reset() {
-    for (int c = 0; c < PC_N + 4; ++c) {
+    for (int c = 0; c < PROF_N; ++c) {
       ms[c] = 0; launches[c] = 0; flops[c] = 0;
       for (int l = 0; l < 32; ++l) ms_level[c][l] = 0;
     }
@@ -184,9 +193,9 @@ struct Profiler {
     recs.clear();
     used = 0;
     if (d_fc) {
-      unsigned long long h[PC_N + 4];
+      unsigned long long h[PROF_N];
       HIPCHK(hipMemcpy(h, d_fc, sizeof(h), hipMemcpyDeviceToHost));
-      for (int c = 0; c < PC_N + 4; ++c) flops[c] += h[c];
+      for (int c = 0; c < PROF_N; ++c) flops[c] += h[c];
       HIPCHK(hipMemset(d_fc, 0, sizeof(h)));
     }
   }
@@ -225,6 +234,7 @@ struct h2_matrix_s {
   // slicing cache and statistics
   std::vector<std::pair<double, int64_t>> cache;
   bool have_gersh = false;
+  double mixed_rel = 0.0;   // h2_kth_eig: FP32 steps while a bracket is >= mixed_rel * normA wide
   double g_lo = 0, g_hi = 0;
   h2_stats_t st{};
   int max_shifts = 0;
@@ -546,8 +556,8 @@ void debug_dump_level(int l, int N, int S, const Work& w, hipStream_t st) {
 }
 
 // Factor S shifts; nu/status are host outputs.
-void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_t* st_out, double* flops_out,
-                  int* maxdim_out) {
+void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_out, int32_t* st_out,
+                  double* flops_out, int* maxdim_out) {
   const Tree& T = A->T;
   const int L = T.L;
   hipStream_t st = A->stream;
@@ -641,6 +651,8 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
     // profiled region: class cls, and for GEMM launches also the kernel symbol
     // (tag = GEMM layout), whose totals are kept beside the classes
     auto run = [&](int cls, auto&& fn, int tag = -1) {
+      bt.f32 = (f32 && f32_class(cls)) ? 1 : 0;
+      if (tag >= 0 && bt.f32) tag += 4;   // the FP32 kernel symbols follow the FP64 ones
       bt.fc = prof.on ? prof.d_fc + cls : nullptr;
       bt.fck = prof.on && tag >= 0 ? prof.d_fc + PC_N + tag : nullptr;
       hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -657,6 +669,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, int64_t* nu_out, int32_
       }
       bt.fc = nullptr;
       bt.fck = nullptr;
+      bt.f32 = 0;
     };
     SizeTab sz{};
     sz.m = w.m;
@@ -896,7 +909,9 @@ int auto_max_shifts(h2_matrix A) {
   return std::max(1, std::min(s, 64));
 }
 
-h2_status run_inertia(h2_matrix A, const double* sigma, int64_t ns, int64_t* nu, int32_t* status) {
+// nu(sigma_s) for every shift, in batches of at most the handle's capacity;
+// FP64 counts join the handle's record cache, FP32 counts (f32) do not.
+h2_status run_inertia(h2_matrix A, const double* sigma, int64_t ns, bool f32, int64_t* nu, int32_t* status) {
   int maxs = auto_max_shifts(A);
   bool anybad = false;
   auto t0 = std::chrono::steady_clock::now();
@@ -904,7 +919,7 @@ h2_status run_inertia(h2_matrix A, const double* sigma, int64_t ns, int64_t* nu,
     int S = (int)std::min<int64_t>(maxs, ns - s0);
     try {
       int md = 0;
-      factor_batch(A, sigma + s0, S, nu + s0, status ? status + s0 : nullptr, nullptr, &md);
+      factor_batch(A, sigma + s0, S, f32, nu + s0, status ? status + s0 : nullptr, nullptr, &md);
       A->st.last_rank_max = std::max(A->st.last_rank_max, md);
     } catch (NoMem&) {
       if (S == 1) throw;
@@ -918,8 +933,10 @@ h2_status run_inertia(h2_matrix A, const double* sigma, int64_t ns, int64_t* nu,
     }
     for (int k = 0; k < S; ++k) {
       if (nu[s0 + k] < 0) anybad = true;
-      else A->cache.push_back({sigma[s0 + k], nu[s0 + k]});
+      else if (!f32) A->cache.push_back({sigma[s0 + k], nu[s0 + k]});
     }
+    int32_t& cnt = f32 ? A->st.evals_f32 : A->st.evals_f64;
+    cnt = (int32_t)std::min<int64_t>(INT32_MAX, (int64_t)cnt + S);
     s0 += S;
   }
   (void)t0;
@@ -936,6 +953,26 @@ void set_last_error(const std::string& msg) { g_err = msg; }
 }  // namespace h2
 
 // =================================================================== C ABI
+static h2_status inertia_impl(h2_matrix A, const double* sigma, int64_t nshift, bool f32, int64_t* nu, int32_t* status) {
+  if (!A) return fail(H2_EINVAL, "NULL handle");
+  if (nshift < 0 || (nshift > 0 && (!sigma || !nu))) return fail(H2_EINVAL, "bad shift arrays");
+  for (int64_t s = 0; s < nshift; ++s)
+    if (!std::isfinite(sigma[s])) return fail(H2_EINVAL, "non-finite shift");
+  Busy b(A);
+  if (!b.ok) return fail(H2_EBUSY, "handle in use by another thread");
+  if (nshift == 0) return H2_OK;
+  try {
+    HIPCHK(hipSetDevice(A->device));
+    h2_status r = run_inertia(A, sigma, nshift, f32, nu, status);
+    if (r != H2_OK) return fail(r, "singular or non-finite pivot block for at least one shift");
+    return H2_OK;
+  } catch (HipError& e) {
+    return fail(H2_EDEVICE, e.where + ": " + hipGetErrorString(e.e));
+  } catch (NoMem& e) {
+    return fail(H2_ENOMEM, e.what);
+  }
+}
+
 extern "C" {
 
 const char* h2_last_error(void) { return g_err.c_str(); }
@@ -1020,24 +1057,22 @@ h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern,
   return H2_OK;
 }
 
+
 h2_status h2_inertia(h2_matrix A, const double* sigma, int64_t nshift, int64_t* nu, int32_t* status) {
+  return inertia_impl(A, sigma, nshift, false, nu, status);
+}
+
+h2_status h2_inertia_f32(h2_matrix A, const double* sigma, int64_t nshift, int64_t* nu, int32_t* status) {
+  return inertia_impl(A, sigma, nshift, true, nu, status);
+}
+
+h2_status h2_set_mixed(h2_matrix A, double switch_rel) {
   if (!A) return fail(H2_EINVAL, "NULL handle");
-  if (nshift < 0 || (nshift > 0 && (!sigma || !nu))) return fail(H2_EINVAL, "bad shift arrays");
-  for (int64_t s = 0; s < nshift; ++s)
-    if (!std::isfinite(sigma[s])) return fail(H2_EINVAL, "non-finite shift");
+  if (!(switch_rel >= 0.0) || !std::isfinite(switch_rel)) return fail(H2_EINVAL, "switch_rel must be finite and >= 0");
   Busy b(A);
   if (!b.ok) return fail(H2_EBUSY, "handle in use by another thread");
-  if (nshift == 0) return H2_OK;
-  try {
-    HIPCHK(hipSetDevice(A->device));
-    h2_status r = run_inertia(A, sigma, nshift, nu, status);
-    if (r != H2_OK) return fail(r, "singular or non-finite pivot block for at least one shift");
-    return H2_OK;
-  } catch (HipError& e) {
-    return fail(H2_EDEVICE, e.where + ": " + hipGetErrorString(e.e));
-  } catch (NoMem& e) {
-    return fail(H2_ENOMEM, e.what);
-  }
+  A->mixed_rel = switch_rel;
+  return H2_OK;
 }
 
 h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol, const double* ab, double* lambda,
@@ -1061,48 +1096,98 @@ h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol, cons
     b0 = iv[1];
   }
   if (nk == 0) return H2_OK;
+  // mixed precision: FP32 steps while a bracket is at least thr wide
+  const double thr = A->mixed_rel > 0.0 ? A->mixed_rel * A->normA : 0.0;
   std::vector<double> lo(nk, a0), hi(nk, b0), sp(nk);
   // split point of bracket j: the midpoint, moved by nudge[j]/64 of the width
   // after a shift there met an exactly singular pivot (any point strictly
   // inside the bracket keeps bisection correct)
   std::vector<int> nudge(nk, 0);
-  auto narrow = [&](double mu, int64_t v) {
+  // phase of bracket j: 0 FP32 steps; 1 switched to FP64, its ends (set by
+  // FP32 counts) get FP64 counts this step; 2 FP64 steps on a bracket whose
+  // ends all have FP64 counts
+  std::vector<int> phase(nk, thr > 0.0 ? 0 : 2);
+  // FP64 counts narrow every bracket, FP32 counts only brackets in phase 0
+  auto narrow = [&](double mu, int64_t v, bool fp32) {
     for (int64_t j = 0; j < nk; ++j) {
+      if (fp32 && phase[j] != 0) continue;
       if (!(mu > lo[j] && mu < hi[j])) continue;
       if (v >= k[j]) hi[j] = mu;
       else lo[j] = mu;
     }
   };
-  for (auto& rec : A->cache) narrow(rec.first, rec.second);
+  auto has64 = [&](double mu) {
+    for (const auto& rec : A->cache)
+      if (rec.first == mu) return true;
+    return false;
+  };
+  // the bracket of j from FP64 counts alone: the largest shift below k
+  // eigenvalues, then the smallest shift above it with at least k
+  auto rebuild = [&](int64_t j) {
+    double L = a0, H = b0;
+    for (const auto& rec : A->cache)
+      if (rec.second < k[j] && rec.first > L && rec.first < b0) L = rec.first;
+    for (const auto& rec : A->cache)
+      if (rec.second >= k[j] && rec.first > L && rec.first < H) H = rec.first;
+    lo[j] = L;
+    hi[j] = H;
+  };
+  for (auto& rec : A->cache) narrow(rec.first, rec.second, false);
   for (;;) {
-    std::vector<double> mus;
-    std::vector<char> act(nk, 0);
+    std::vector<double> m32, m64;
+    std::vector<char> act(nk, 0), verify(nk, 0);
     for (int64_t j = 0; j < nk; ++j) {
+      if (phase[j] == 0 && hi[j] - lo[j] < thr) phase[j] = 1;
+      if (phase[j] == 1) {
+        if (lo[j] != a0 && !has64(lo[j])) m64.push_back(lo[j]), verify[j] = 1;
+        if (hi[j] != b0 && !has64(hi[j])) m64.push_back(hi[j]), verify[j] = 1;
+        if (verify[j]) continue;
+        rebuild(j);
+        phase[j] = 2;
+      }
       sp[j] = lo[j] + (hi[j] - lo[j]) * (0.5 + nudge[j] / 64.0);
       // active while wider than tol and still splittable in double precision
       if (hi[j] - lo[j] >= tol && sp[j] > lo[j] && sp[j] < hi[j]) {
         act[j] = 1;
-        mus.push_back(sp[j]);
+        (phase[j] == 0 ? m32 : m64).push_back(sp[j]);
       }
     }
-    if (mus.empty()) break;
-    std::sort(mus.begin(), mus.end());
-    mus.erase(std::unique(mus.begin(), mus.end()), mus.end());
-    std::vector<int64_t> nus(mus.size());
-    std::vector<int32_t> sts(mus.size());
-    h2_status r = h2_inertia(A, mus.data(), (int64_t)mus.size(), nus.data(), sts.data());
-    if (r != H2_OK && r != H2_ENUMERIC) return r;
+    if (m32.empty() && m64.empty()) break;
+    for (auto* v : {&m32, &m64}) {
+      std::sort(v->begin(), v->end());
+      v->erase(std::unique(v->begin(), v->end()), v->end());
+    }
+    std::vector<int64_t> n32(m32.size()), n64(m64.size());
+    std::vector<int32_t> s32(m32.size()), s64(m64.size());
+    if (!m64.empty()) {
+      h2_status r = h2_inertia(A, m64.data(), (int64_t)m64.size(), n64.data(), s64.data());
+      if (r != H2_OK && r != H2_ENUMERIC) return r;
+    }
+    if (!m32.empty()) {
+      h2_status r = h2_inertia_f32(A, m32.data(), (int64_t)m32.size(), n32.data(), s32.data());
+      if (r != H2_OK && r != H2_ENUMERIC) return r;
+    }
     for (int64_t j = 0; j < nk; ++j) {
       if (!act[j]) continue;
-      const size_t q = std::lower_bound(mus.begin(), mus.end(), sp[j]) - mus.begin();
-      if (sts[q] == H2_OK) {
+      const auto& m = phase[j] == 0 ? m32 : m64;
+      const auto& sv = phase[j] == 0 ? s32 : s64;
+      const size_t q = std::lower_bound(m.begin(), m.end(), sp[j]) - m.begin();
+      if (sv[q] == H2_OK) {
         nudge[j] = 0;
       } else if (++nudge[j] > 8) {
         return fail(H2_ENUMERIC, "singular pivot block at every split point tried");
       }
     }
-    for (size_t q = 0; q < mus.size(); ++q)
-      if (sts[q] == H2_OK) narrow(mus[q], nus[q]);
+    for (size_t q = 0; q < m64.size(); ++q)
+      if (s64[q] == H2_OK) narrow(m64[q], n64[q], false);
+    for (size_t q = 0; q < m32.size(); ++q)
+      if (s32[q] == H2_OK) narrow(m32[q], n32[q], true);
+    // brackets whose ends were just counted in FP64: rebuilt from FP64 counts
+    for (int64_t j = 0; j < nk; ++j)
+      if (verify[j]) {
+        rebuild(j);
+        phase[j] = 2;
+      }
   }
   for (int64_t j = 0; j < nk; ++j) {
     lambda[j] = 0.5 * (lo[j] + hi[j]);
@@ -1179,8 +1264,8 @@ h2_status h2_profile_enable(h2_matrix A, int32_t enable) {
   try {
     HIPCHK(hipSetDevice(A->device));
     if (enable && !A->prof.d_fc) {
-      HIPCHK(hipMalloc(&A->prof.d_fc, (PC_N + 4) * sizeof(unsigned long long)));
-      HIPCHK(hipMemset(A->prof.d_fc, 0, (PC_N + 4) * sizeof(unsigned long long)));
+      HIPCHK(hipMalloc(&A->prof.d_fc, (PROF_N) * sizeof(unsigned long long)));
+      HIPCHK(hipMemset(A->prof.d_fc, 0, (PROF_N) * sizeof(unsigned long long)));
     }
   } catch (HipError& e) {
     return fail(H2_EDEVICE, e.where + ": " + hipGetErrorString(e.e));
@@ -1190,16 +1275,16 @@ h2_status h2_profile_enable(h2_matrix A, int32_t enable) {
   return H2_OK;
 }
 
-int32_t h2_profile_classes(void) { return PC_N + 4; }
+int32_t h2_profile_classes(void) { return PROF_N; }
 
 const char* h2_profile_class_name(int32_t cls) {
   if (cls >= 0 && cls < PC_N) return kProfNames[cls];
-  if (cls >= PC_N && cls < PC_N + 4) return kGemmNames[cls - PC_N];
+  if (cls >= PC_N && cls < PROF_N) return kGemmNames[cls - PC_N];
   return "";
 }
 
 h2_status h2_profile_read(h2_matrix A, int32_t cls, int64_t* launches, double* ms, double* flops) {
-  if (!A || cls < 0 || cls >= PC_N + 4) return fail(H2_EINVAL, "bad handle or class");
+  if (!A || cls < 0 || cls >= PROF_N) return fail(H2_EINVAL, "bad handle or class");
   if (launches) *launches = A->prof.launches[cls];
   if (ms) *ms = A->prof.ms[cls];
   if (flops) *flops = (double)A->prof.flops[cls];
@@ -1207,7 +1292,7 @@ h2_status h2_profile_read(h2_matrix A, int32_t cls, int64_t* launches, double* m
 }
 
 h2_status h2_profile_level_ms(h2_matrix A, int32_t cls, int32_t level, double* ms) {
-  if (!A || cls < 0 || cls >= PC_N + 4 || level < 0 || level >= 32 || !ms) return fail(H2_EINVAL, "bad arguments");
+  if (!A || cls < 0 || cls >= PROF_N || level < 0 || level >= 32 || !ms) return fail(H2_EINVAL, "bad arguments");
   *ms = A->prof.ms_level[cls][level];
   return H2_OK;
 }

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "desc.hpp"
 #include "kernels.hpp"
@@ -41,6 +42,7 @@ __global__ void k_fill_int(int* p, int64_t n, int v) {
 // per step).
 // op(A): TA ? A^T (A stored K x M) : A (M x K);  op(B): TB ? B^T (B stored N x K) : B (K x N).
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int GT = 64;   // output tile
 constexpr int GK = 16;   // k step
@@ -94,18 +96,23 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const GItem* __restrict__ it
 
 // The GEMM proper: a fixed grid strides over the tiles counted by k_tile_scan;
 // workgroups on one XCD (blockIdx.x % 8) take consecutive tiles, so that tiles
-// sharing panels of A or B meet in the same L2.
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, int nitems,
-                                              const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
-                                              const int* __restrict__ prefix, int slot_base) {
+// sharing panels of A or B meet in the same L2.  Operands and results are FP64
+// in memory; F32 converts the operands to FP32 on their way into LDS and
+// multiplies them on FP32 MFMA with FP32 accumulation (the early bisection
+// steps), else everything is FP64.
+template <bool TA, bool TB, bool F32>
+__device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int nitems, const GTerm* __restrict__ terms,
+                                          const BufTab& bt, const SizeTab& sz, const int* __restrict__ prefix,
+                                          int slot_base) {
+  using CT = typename std::conditional<F32, float, double>::type;
+  using VT = typename std::conditional<F32, v4f, v4d>::type;
   const int s = blockIdx.z;
   const int* pre = prefix + (int64_t)s * (nitems + 1);
   const int total = pre[nitems];
   const int G = gridDim.x;
   const int lw = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);   // G is a multiple of 8
-  __shared__ double As[2][GK][GT + 1];
-  __shared__ double Bs[2][GK][GT + 1];
+  __shared__ CT As[2][GK][GT + 1];
+  __shared__ CT Bs[2][GK][GT + 1];
   for (int tile = lw; tile < total; tile += G) {
   int lo = 0, hi = nitems - 1;   // the item: the last i with pre[i] <= tile
   while (lo < hi) {
@@ -127,9 +134,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, i
   }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  v4d acc[2][2];
+  VT acc[2][2];
   for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 2; ++j) acc[i][j] = VT{0, 0, 0, 0};
 
   for (int tt = 0; tt < it.nt; ++tt) {
     const GTerm tm = terms[it.t0 + tt];
@@ -171,10 +178,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, i
         const int e = tid + 256 * r;
         int mm, kk;
         if (TA) { kk = e % GK; mm = e / GK; } else { mm = e % GT; kk = e / GT; }
-        As[buf][kk][mm] = ra[r];
+        As[buf][kk][mm] = (CT)ra[r];
         int nn, kb;
         if (TB) { nn = e % GT; kb = e / GT; } else { kb = e % GK; nn = e / GK; }
-        Bs[buf][kb][nn] = rb[r];
+        Bs[buf][kb][nn] = (CT)rb[r];
       }
     };
     gload(0);
@@ -186,14 +193,21 @@ __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, i
 #pragma unroll
       for (int kk = 0; kk < GK; kk += 4) {
         const int kr = kk + (lane >> 4);
-        const double a0 = As[cur][kr][wm * 32 + (lane & 15)];
-        const double a1 = As[cur][kr][wm * 32 + 16 + (lane & 15)];
-        const double b0 = Bs[cur][kr][wn * 32 + (lane & 15)];
-        const double b1 = Bs[cur][kr][wn * 32 + 16 + (lane & 15)];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        const CT a0 = As[cur][kr][wm * 32 + (lane & 15)];
+        const CT a1 = As[cur][kr][wm * 32 + 16 + (lane & 15)];
+        const CT b0 = Bs[cur][kr][wn * 32 + (lane & 15)];
+        const CT b1 = Bs[cur][kr][wn * 32 + 16 + (lane & 15)];
+        if constexpr (F32) {
+          acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+        } else {
+          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
       }
       if (kt + 1 < nk) sstore(cur ^ 1);
       __syncthreads();
@@ -220,10 +234,12 @@ __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, i
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)
       for (int v = 0; v < 4; ++v) {
-        int r = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * v;   // D[i][j]: lane j + 16*(i%4), reg i/4
+        // output row of register v: FP64 MFMA puts D[i][j] in lane j + 16*(i%4),
+        // register i/4; FP32 MFMA in lane j + 16*(i/4), register i%4
+        int r = m0 + wm * 32 + i * 16 + (F32 ? 4 * (lane >> 4) + v : (lane >> 4) + 4 * v);
         int c = n0 + wn * 32 + j * 16 + (lane & 15);
         if (r < M && c < N) {
-          double x = it.alpha * acc[i][j][v];
+          double x = it.alpha * (double)acc[i][j][v];
           const int dr = r < rs ? cr + r : r2o + (r - rs), dcol = c < cs ? cc + c : c2o + (c - cs);
           double* p = C + dr + (int64_t)dcol * ldc;
           *p = it.beta != 0.0 ? it.beta * *p + x : x;
@@ -234,6 +250,20 @@ __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, i
         }
       }
   }
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, int nitems,
+                                              const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
+                                              const int* __restrict__ prefix, int slot_base) {
+  gemm_body<TA, TB, false>(items, nitems, terms, bt, sz, prefix, slot_base);
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm_f32(const GItem* __restrict__ items, int nitems,
+                                                  const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
+                                                  const int* __restrict__ prefix, int slot_base) {
+  gemm_body<TA, TB, true>(items, nitems, terms, bt, sz, prefix, slot_base);
 }
 
 // Transposed copy of a scratch slot into a block: X[r0 + a][c0 + b] = RS[slot][b][a]
@@ -1410,6 +1440,15 @@ void launch_gemm(int kind, const GItem* items, int nitems, const GTerm* terms, c
   const int64_t upper = (int64_t)nitems * cdiv(mcap, GT) * cdiv(ncap, GT);
   const int G = (int)std::max<int64_t>(8, std::min<int64_t>(GEMM_GRID, (upper + 7) / 8 * 8));
   dim3 grid(G, 1, nshift);
+  if (bt.f32) {
+    switch (kind) {
+      case GEMM_NN: hipLaunchKernelGGL((k_gemm_f32<false, false>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
+      case GEMM_NT: hipLaunchKernelGGL((k_gemm_f32<false, true>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
+      case GEMM_TN: hipLaunchKernelGGL((k_gemm_f32<true, false>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
+      default: hipLaunchKernelGGL((k_gemm_f32<true, true>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
+    }
+    return;
+  }
   switch (kind) {
     case GEMM_NN: hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
     case GEMM_NT: hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;

@@ -38,7 +38,8 @@ class _Stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("levels", C.c_int32), ("leaf_max", C.c_int32), ("rank_max", C.c_int32),
                 ("near_max", C.c_int32), ("near_blocks", C.c_int64), ("resident_bytes", C.c_int64),
                 ("last_work_bytes", C.c_int64), ("last_flops", C.c_double), ("last_bytes", C.c_double),
-                ("build_seconds", C.c_double), ("last_rank_max", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("build_seconds", C.c_double), ("last_rank_max", C.c_int32), ("evals_f64", C.c_int32),
+                ("evals_f32", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -72,6 +73,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.h2_profile_read.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double)]
     lib.h2_profile_level_ms.restype = C.c_int
     lib.h2_profile_level_ms.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(C.c_double)]
+    lib.h2_inertia_f32.restype = C.c_int
+    lib.h2_inertia_f32.argtypes = [C.c_void_p, P(C.c_double), C.c_int64, P(C.c_int64), P(C.c_int32)]
+    lib.h2_set_mixed.restype = C.c_int
+    lib.h2_set_mixed.argtypes = [C.c_void_p, C.c_double]
     lib.h2_interval.restype = C.c_int
     lib.h2_interval.argtypes = [C.c_void_p, P(C.c_double)]
     lib.h2_capacity.restype = C.c_int
@@ -101,7 +106,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
 
 _lib = load_library()
 
-EXPORTED = ["h2_build", "h2_inertia", "h2_kth_eig", "h2_norm", "h2_stats", "h2_set_stream", "h2_tree_perm",
+EXPORTED = ["h2_build", "h2_inertia", "h2_inertia_f32", "h2_set_mixed", "h2_kth_eig", "h2_norm", "h2_stats", "h2_set_stream", "h2_tree_perm",
             "h2_profile_enable", "h2_profile_classes", "h2_profile_class_name", "h2_profile_read",
             "h2_profile_level_ms", "h2_interval", "h2_capacity", "h2_set_max_shifts", "h2_free", "h2_last_error",
             "h2s_create", "h2s_add", "h2s_submit", "h2s_poll", "h2s_wait", "h2s_stats", "h2s_destroy"]
@@ -141,12 +146,14 @@ class H2Matrix:
     def __del__(self):
         self.close()
 
-    def inertia(self, sigma, return_status: bool = False):
+    def inertia(self, sigma, return_status: bool = False, f32: bool = False):
+        """nu(sigma_s) = #{eigenvalues < sigma_s}; f32 = h2_inertia_f32."""
         s = np.ascontiguousarray(np.atleast_1d(sigma), dtype=np.float64)
         nu = np.zeros(len(s), dtype=np.int64)
         st = np.zeros(len(s), dtype=np.int32)
-        r = _lib.h2_inertia(self._h, _dptr(s), len(s), nu.ctypes.data_as(C.POINTER(C.c_int64)),
-                            st.ctypes.data_as(C.POINTER(C.c_int32)))
+        fn = _lib.h2_inertia_f32 if f32 else _lib.h2_inertia
+        r = fn(self._h, _dptr(s), len(s), nu.ctypes.data_as(C.POINTER(C.c_int64)),
+               st.ctypes.data_as(C.POINTER(C.c_int32)))
         if r != H2_OK and not (return_status and r == H2_ENUMERIC):
             _check(r)
         return (nu, st) if return_status else nu
@@ -205,6 +212,10 @@ class H2Matrix:
 
     def set_stream(self, stream_ptr: int):
         _check(_lib.h2_set_stream(self._h, C.c_void_p(stream_ptr)))
+
+    def set_mixed(self, switch_rel: float):
+        """h2_kth_eig bisects in FP32 while a bracket is >= switch_rel * normA wide (0 = FP64 only)."""
+        _check(_lib.h2_set_mixed(self._h, float(switch_rel)))
 
     def interval(self):
         ab = np.zeros(2)

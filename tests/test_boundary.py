@@ -82,6 +82,8 @@ def test_null_handles(mod):
     nu = (C.c_int64 * 1)()
     sig = (C.c_double * 1)(1.0)
     assert L.h2_inertia(None, sig, 1, nu, None) == mod.H2_EINVAL
+    assert L.h2_inertia_f32(None, sig, 1, nu, None) == mod.H2_EINVAL
+    assert L.h2_set_mixed(None, 1e-4) == mod.H2_EINVAL
     k = (C.c_int64 * 1)(1)
     lam = (C.c_double * 1)()
     assert L.h2_kth_eig(None, k, 1, 1e-8, None, lam, None) == mod.H2_EINVAL

@@ -1,0 +1,91 @@
+"""FP32 contractions (h2_inertia_f32) and the mixed-precision policy of
+h2_kth_eig (h2_set_mixed) on the GPU.
+
+  * FP32 counts equal the dense counts (LAPACK) at shifts midway between
+    eigenvalues whose gap is far above the FP32 error of the factorization;
+  * mixed bisection gives every requested eigenvalue within the bound of the
+    FP64 path (tol/2 + 10 eps normA of the dense value) and within tol of the
+    plain FP64 result, with FP32 steps actually taken;
+  * on the 1-D second difference, whose extreme eigenvalues are 4e-8 apart
+    (below the FP32 error), FP32 decisions near them can be wrong: the check
+    at the switch to FP64 must catch them, so the results still match the
+    closed form 2 - 2cos(j pi/(n+1)).
+"""
+import numpy as np
+import pytest
+
+from oracle.dense import tridiag_eigs
+from oracle.kernels import Kernel
+from paper_2311_08618_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2311_08618_amd import h2eig
+    return h2eig
+
+
+@pytest.fixture(scope="module")
+def cube(lib):
+    n = 2048
+    X = W.cube_points(n, 0)
+    A = lib.H2Matrix(X, W.K_LAPLACE, 1e3, 128, 1.0, 1e-8)
+    ev = np.linalg.eigvalsh(Kernel(W.K_LAPLACE, 1e3).dense(X))
+    return A, ev
+
+
+def test_f32_counts_at_separated_shifts(lib, cube):
+    print("case f32 counts cube n=2048", flush=True)
+    A, ev = cube
+    gaps = np.diff(ev)
+    idx = np.flatnonzero(gaps > 0.2)           # FP32 error here is ~1e-6 normA = 5e-3
+    pick = idx[np.linspace(0, len(idx) - 1, 12).astype(int)]
+    sig = np.concatenate([[ev[0] - 50.0], 0.5 * (ev[pick] + ev[pick + 1]), [ev[-1] + 50.0]])
+    want = np.array([int(np.sum(ev < s)) for s in sig])
+    nu32 = A.inertia(sig, f32=True)
+    nu64 = A.inertia(sig)
+    assert np.array_equal(nu64, want), (nu64 - want)
+    assert np.array_equal(nu32, want), (nu32 - want)
+
+
+def test_mixed_kth_eig_cube(lib, cube):
+    print("case mixed kth_eig cube n=2048", flush=True)
+    A, ev = cube
+    n, tol = len(ev), 1e-8
+    ks = [1, 512, 1024, 1537, n]
+    plain, _ = A.kth_eig(ks, tol)
+    # a fresh handle: the record cache of A would answer every query at once
+    M = lib.H2Matrix(W.cube_points(n, 0), W.K_LAPLACE, 1e3, 128, 1.0, 1e-8)
+    M.set_mixed(1e-4)
+    mixed, br = M.kth_eig(ks, tol)
+    st1 = M.stats()
+    assert st1["evals_f32"] > 0 and st1["evals_f64"] > 0, st1
+    bound = tol / 2 + 10 * 1e-8 * A.norm()
+    for k, lm, lp in zip(ks, mixed, plain):
+        assert abs(lm - ev[k - 1]) <= bound, (k, lm, ev[k - 1])
+        assert abs(lm - lp) <= tol + 10 * 1e-8 * A.norm(), (k, lm, lp)
+    assert np.all(br[:, 1] - br[:, 0] < tol)
+
+
+def test_mixed_kth_eig_catches_wrong_f32_decisions(lib):
+    n, tol = 16384, 1e-10
+    print("case mixed kth_eig tridiag n=%d" % n, flush=True)
+    T = lib.H2Matrix(W.line_points(n), W.K_TRIDIAG_1D, 2.0, 64, 1.0, 1e-12, p0=1.0)
+    lam = tridiag_eigs(n)
+    ks = [1, 2, 3, n // 2, n - 1, n]
+    T.set_mixed(1e-3)
+    got, _ = T.kth_eig(ks, tol)
+    bound = tol / 2 + 10 * 1e-12 * T.norm()
+    for k, g in zip(ks, got):
+        assert abs(g - lam[k - 1]) <= bound, (k, g, lam[k - 1])
+    assert T.stats()["evals_f32"] > 0
+
+
+def test_mixed_argument_errors(lib, cube):
+    A, _ = cube
+    for v in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(lib.H2EigError) as e:
+            A.set_mixed(v)
+        assert e.value.status == lib.H2_EINVAL
