@@ -159,6 +159,23 @@ h2_status h2_interval(h2_matrix A, double* ab);
  * memory at the time of the call (the admission unit of the serving loop). */
 h2_status h2_capacity(h2_matrix A, int32_t* max_shifts);
 
+/* Block capacity (largest cluster dimension, rounded up to 8) of levels
+ * 0..nlev-1 in the last factorization, 0 for levels it did not reach; shows
+ * the rank growth level by level.  cap: host output, nlev ints. */
+h2_status h2_level_dims(h2_matrix A, int32_t nlev, int32_t* cap);
+
+/* Launch parameters of the dense contractions (the batched MFMA GEMM), by
+ * operand layout (0 NN, 1 NT, 2 TN, 3 TT), precision (f32 0/1) and capacity
+ * bucket (largest block dimension <= 256, 512, 1024, 2048, larger: 0..4):
+ * grid = workgroups per shift (0 = built-in default, else a multiple of 8 in
+ * [8, 65536]), group_m = tile-order group (tiles taken column by column within
+ * groups of group_m tile rows; 0 or 1 = row by row).  The table is
+ * process-wide and written by the autotuner's file at load time; set it while
+ * no factorization runs.  Results do not depend on it.  H2_EINVAL for values
+ * out of range. */
+h2_status h2_set_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_t grid, int32_t group_m);
+h2_status h2_get_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_t* grid, int32_t* group_m);
+
 /* Cap on the shifts factored together in one launch (0 = automatic, from the
  * free device memory at each call); larger batches are split.  H2_EINVAL for
  * max_shifts < 0. */

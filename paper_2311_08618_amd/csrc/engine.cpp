@@ -234,7 +234,8 @@ struct h2_matrix_s {
   // slicing cache and statistics
   std::vector<std::pair<double, int64_t>> cache;
   bool have_gersh = false;
-  double mixed_rel = 0.0;   // h2_kth_eig: FP32 steps while a bracket is >= mixed_rel * normA wide
+  double mixed_rel = 0.0;
+  std::vector<int32_t> last_cap;   // block capacity of each level in the last factorization (0 = not reached)   // h2_kth_eig: FP32 steps while a bracket is >= mixed_rel * normA wide
   double g_lo = 0, g_hi = 0;
   h2_stats_t st{};
   int max_shifts = 0;
@@ -600,11 +601,13 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
   double flops = 0.0;
   int maxdim = cap;
   std::vector<int> hpm;
+  A->last_cap.assign(L + 1, 0);
   for (int l = L; l >= 0; --l) {
     const LevelPlan& lp = A->plan[l];
     const DevLevel& dl = A->dlev[l];
     const int N = lp.N;
     A->prof.level = l;
+    A->last_cap[l] = cap;
     if (cap > hqr_max_rows())
       throw NoMem{"cluster dimension " + std::to_string(cap) + " exceeds the supported maximum " +
                   std::to_string(hqr_max_rows())};
@@ -1212,6 +1215,34 @@ h2_status h2_interval(h2_matrix A, double* ab) {
   const double mg = 10.0 * A->eps * A->normA;
   ab[0] = A->g_lo - mg;
   ab[1] = A->g_hi + mg;
+  return H2_OK;
+}
+
+h2_status h2_set_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_t grid, int32_t group_m) {
+  if (layout < 0 || layout > 3 || f32 < 0 || f32 > 1 || bucket < 0 || bucket >= GEMM_BUCKETS)
+    return fail(H2_EINVAL, "layout, f32 or bucket out of range");
+  if (grid != 0 && (grid < 8 || grid > 65536 || grid % 8 != 0))
+    return fail(H2_EINVAL, "grid must be 0 or a multiple of 8 in [8, 65536]");
+  if (group_m < 0 || group_m > 64) return fail(H2_EINVAL, "group_m must be in [0, 64]");
+  set_gemm_tuning(layout, f32, bucket, grid, group_m);
+  return H2_OK;
+}
+
+h2_status h2_get_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_t* grid, int32_t* group_m) {
+  if (layout < 0 || layout > 3 || f32 < 0 || f32 > 1 || bucket < 0 || bucket >= GEMM_BUCKETS || !grid || !group_m)
+    return fail(H2_EINVAL, "layout, f32 or bucket out of range, or NULL output");
+  int g = 0, gm = 0;
+  get_gemm_tuning(layout, f32, bucket, &g, &gm);
+  *grid = g;
+  *group_m = gm;
+  return H2_OK;
+}
+
+h2_status h2_level_dims(h2_matrix A, int32_t nlev, int32_t* cap) {
+  if (!A || !cap || nlev < 0) return fail(H2_EINVAL, "NULL argument or nlev < 0");
+  Busy b(A);
+  if (!b.ok) return fail(H2_EBUSY, "handle in use by another thread");
+  for (int32_t l = 0; l < nlev; ++l) cap[l] = l < (int32_t)A->last_cap.size() ? A->last_cap[l] : 0;
   return H2_OK;
 }
 

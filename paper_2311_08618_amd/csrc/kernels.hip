@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <type_traits>
 
@@ -125,7 +126,17 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
   const int M = dev_eval(it.M, sz, s), N = dev_eval(it.N, sz, s);
   const int tn = (N + GT - 1) / GT;
   const int local = tile - pre[idx];
-  const int m0 = (local / tn) * GT, n0 = (local % tn) * GT;
+  int mi, ni;
+  if (bt.group_m <= 1) {
+    mi = local / tn;
+    ni = local % tn;
+  } else {   // concurrent tiles share group_m row panels and a few column panels
+    const int tm = (M + GT - 1) / GT, gsz = bt.group_m * tn;
+    const int g = local / gsz, first = g * bt.group_m, rows = min(tm - first, bt.group_m), r = local - g * gsz;
+    mi = first + r % rows;
+    ni = r / rows;
+  }
+  const int m0 = mi * GT, n0 = ni * GT;
   if (bt.fc && local == 0 && threadIdx.x == 0) {
     unsigned long long kk = 0;
     for (int tt = 0; tt < it.nt; ++tt) kk += (unsigned long long)max(0, dev_eval(terms[it.t0 + tt].K, sz, s));
@@ -1432,13 +1443,42 @@ void launch_fill_int(int* p, int64_t n, int v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_int, dim3(g), dim3(256), 0, st, p, n, v);
 }
 
-void launch_gemm(int kind, const GItem* items, int nitems, const GTerm* terms, const BufTab& bt, const SizeTab& sz,
+// GEMM launch parameters by operand layout, precision and capacity bucket
+// (largest block dimension <= 256, 512, 1024, 2048, larger).  The defaults
+// come from a sweep of square batches on gfx950 (grid 2048/4096/2048/1024/1024,
+// row-by-row tile order); the autotuner's table overrides them.  Process-wide;
+// atomics because concurrent factorizations read it.
+namespace {
+constexpr int kDefaultGrid[GEMM_BUCKETS] = {2048, 4096, 2048, 1024, 1024};
+std::atomic<int> g_tune_grid[4][2][GEMM_BUCKETS];    // 0 = default
+std::atomic<int> g_tune_group[4][2][GEMM_BUCKETS];   // 0 = row by row
+}  // namespace
+
+int gemm_bucket(int cap) { return cap <= 256 ? 0 : cap <= 512 ? 1 : cap <= 1024 ? 2 : cap <= 2048 ? 3 : 4; }
+
+void set_gemm_tuning(int layout, int f32, int bucket, int grid, int group_m) {
+  g_tune_grid[layout][f32][bucket].store(grid);
+  g_tune_group[layout][f32][bucket].store(group_m);
+}
+
+void get_gemm_tuning(int layout, int f32, int bucket, int* grid, int* group_m) {
+  const int g = g_tune_grid[layout][f32][bucket].load();
+  *grid = g > 0 ? g : kDefaultGrid[bucket];
+  *group_m = std::max(1, g_tune_group[layout][f32][bucket].load());
+}
+
+void launch_gemm(int kind, const GItem* items, int nitems, const GTerm* terms, const BufTab& bt_in, const SizeTab& sz,
                  int mcap, int ncap, int nshift, int* prefix, hipStream_t st) {
+  BufTab bt = bt_in;
+  if (bt.grid <= 0) {   // launch parameters from the tuning table
+    get_gemm_tuning(kind, bt.f32 ? 1 : 0, gemm_bucket(std::max(mcap, ncap)), &bt.grid, &bt.group_m);
+  }
   if (nitems <= 0) return;
   hipLaunchKernelGGL(k_tile_scan, dim3(nshift), dim3(1024), 0, st, items, nitems, sz, prefix);
   // a fixed grid, no larger than the tiles the capacities allow (multiple of 8)
   const int64_t upper = (int64_t)nitems * cdiv(mcap, GT) * cdiv(ncap, GT);
-  const int G = (int)std::max<int64_t>(8, std::min<int64_t>(GEMM_GRID, (upper + 7) / 8 * 8));
+  const int gmax = bt.grid > 0 ? bt.grid : GEMM_GRID;
+  const int G = (int)std::max<int64_t>(8, std::min<int64_t>(gmax, (upper + 7) / 8 * 8));
   dim3 grid(G, 1, nshift);
   if (bt.f32) {
     switch (kind) {

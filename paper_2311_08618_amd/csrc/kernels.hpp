@@ -8,6 +8,14 @@ namespace h2 {
 
 enum GemmKind { GEMM_NN = 0, GEMM_NT = 1, GEMM_TN = 2, GEMM_TT = 3 };
 
+// GEMM tuning table: capacity buckets (largest block dimension <= 256, 512,
+// 1024, 2048, larger), and per (layout, FP32, bucket) the workgroups per shift
+// and the tile-order group.
+constexpr int GEMM_BUCKETS = 5;
+int gemm_bucket(int cap);
+void set_gemm_tuning(int layout, int f32, int bucket, int grid, int group_m);
+void get_gemm_tuning(int layout, int f32, int bucket, int* grid, int* group_m);
+
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void launch_fill_int(int* p, int64_t n, int v, hipStream_t st);
 // prefix: device scratch of at least nshift * (nitems + 1) ints (the per-shift tile counts)

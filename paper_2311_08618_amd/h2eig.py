@@ -7,12 +7,14 @@ is present.  There is no CPU fallback.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libh2eig.so")
+TUNING_FILE = os.path.join(_HERE, "tuning", "gemm_tuning.json")
 
 H2_OK, H2_EINVAL, H2_ENOMEM, H2_EDEVICE, H2_ENUMERIC, H2_EBUSY = 0, -1, -2, -3, -4, -5
 
@@ -81,6 +83,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.h2_interval.argtypes = [C.c_void_p, P(C.c_double)]
     lib.h2_capacity.restype = C.c_int
     lib.h2_capacity.argtypes = [C.c_void_p, P(C.c_int32)]
+    lib.h2_level_dims.restype = C.c_int
+    lib.h2_level_dims.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32)]
+    lib.h2_set_gemm_tuning.restype = C.c_int
+    lib.h2_set_gemm_tuning.argtypes = [C.c_int32] * 5
+    lib.h2_get_gemm_tuning.restype = C.c_int
+    lib.h2_get_gemm_tuning.argtypes = [C.c_int32, C.c_int32, C.c_int32, P(C.c_int32), P(C.c_int32)]
     lib.h2_set_max_shifts.restype = C.c_int
     lib.h2_set_max_shifts.argtypes = [C.c_void_p, C.c_int32]
     lib.h2_free.restype = None
@@ -108,7 +116,8 @@ _lib = load_library()
 
 EXPORTED = ["h2_build", "h2_inertia", "h2_inertia_f32", "h2_set_mixed", "h2_kth_eig", "h2_norm", "h2_stats", "h2_set_stream", "h2_tree_perm",
             "h2_profile_enable", "h2_profile_classes", "h2_profile_class_name", "h2_profile_read",
-            "h2_profile_level_ms", "h2_interval", "h2_capacity", "h2_set_max_shifts", "h2_free", "h2_last_error",
+            "h2_profile_level_ms", "h2_interval", "h2_capacity", "h2_set_max_shifts", "h2_level_dims",
+            "h2_set_gemm_tuning", "h2_get_gemm_tuning", "h2_free", "h2_last_error",
             "h2s_create", "h2s_add", "h2s_submit", "h2s_poll", "h2s_wait", "h2s_stats", "h2s_destroy"]
 
 
@@ -117,8 +126,34 @@ def _check(st: int):
         raise H2EigError(st, _lib.h2_last_error().decode())
 
 
+def set_gemm_tuning(layout: int, f32: int, bucket: int, grid: int, group_m: int):
+    _check(_lib.h2_set_gemm_tuning(int(layout), int(f32), int(bucket), int(grid), int(group_m)))
+
+
+def get_gemm_tuning(layout: int, f32: int, bucket: int):
+    g, gm = C.c_int32(), C.c_int32()
+    _check(_lib.h2_get_gemm_tuning(int(layout), int(f32), int(bucket), C.byref(g), C.byref(gm)))
+    return g.value, gm.value
+
+
+def apply_tuning(path: str = TUNING_FILE) -> int:
+    """Load the autotuner's table (JSON written by autotune.py) into the
+    library; returns the number of entries applied."""
+    with open(path) as f:
+        table = json.load(f)
+    n = 0
+    for e in table["entries"]:
+        set_gemm_tuning(e["layout"], e["f32"], e["bucket"], e["grid"], e["group_m"])
+        n += 1
+    return n
+
+
 def _dptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+if os.path.exists(TUNING_FILE):
+    apply_tuning(TUNING_FILE)
 
 
 class H2Matrix:
@@ -221,6 +256,13 @@ class H2Matrix:
         ab = np.zeros(2)
         _check(_lib.h2_interval(self._h, _dptr(ab)))
         return float(ab[0]), float(ab[1])
+
+    def level_dims(self) -> list:
+        """Block capacity of every level in the last factorization (0 = not reached)."""
+        nlev = self.stats()["levels"] + 1
+        cap = (C.c_int32 * nlev)()
+        _check(_lib.h2_level_dims(self._h, nlev, cap))
+        return list(cap)
 
     def set_max_shifts(self, max_shifts: int):
         _check(_lib.h2_set_max_shifts(self._h, int(max_shifts)))

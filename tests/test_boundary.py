@@ -84,6 +84,7 @@ def test_null_handles(mod):
     assert L.h2_inertia(None, sig, 1, nu, None) == mod.H2_EINVAL
     assert L.h2_inertia_f32(None, sig, 1, nu, None) == mod.H2_EINVAL
     assert L.h2_set_mixed(None, 1e-4) == mod.H2_EINVAL
+    assert L.h2_level_dims(None, 1, None) == mod.H2_EINVAL
     k = (C.c_int64 * 1)(1)
     lam = (C.c_double * 1)()
     assert L.h2_kth_eig(None, k, 1, 1e-8, None, lam, None) == mod.H2_EINVAL
@@ -139,3 +140,20 @@ def test_server_argument_errors(mod):
     assert (p50.value, p99.value, served.value, sub.value) == (0.0, 0.0, 0, 0)
     L.h2s_destroy(h)
     L.h2s_destroy(None)   # no-op
+
+
+def test_gemm_tuning_table(mod):
+    """The tuning table validates its arguments and round-trips an entry
+    (host only: no device work)."""
+    L = mod._lib
+    g0, gm0 = mod.get_gemm_tuning(1, 0, 3)
+    assert g0 % 8 == 0 and g0 >= 8 and gm0 >= 1
+    for bad in [(4, 0, 0, 1024, 1), (0, 2, 0, 1024, 1), (0, 0, 5, 1024, 1), (0, 0, 0, 1001, 1),
+                (0, 0, 0, 4, 1), (0, 0, 0, 1024, 65), (-1, 0, 0, 1024, 1)]:
+        assert L.h2_set_gemm_tuning(*bad) == mod.H2_EINVAL, bad
+    try:
+        mod.set_gemm_tuning(1, 0, 3, 512, 8)
+        assert mod.get_gemm_tuning(1, 0, 3) == (512, 8)
+    finally:
+        mod.set_gemm_tuning(1, 0, 3, g0, gm0)
+    assert mod.get_gemm_tuning(1, 0, 3) == (g0, gm0)
