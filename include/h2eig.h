@@ -221,6 +221,8 @@ h2_status h2_tree_perm(h2_matrix A, int64_t* perm);
  * first the roles of the factorization (names such as "rotate", "schur"), then
  * one entry per operand layout of the MFMA GEMM kernel (names starting with
  * "kernel:"), which counts the same GEMM launches by kernel symbol.
+ * enable = 2 brackets only the GEMM launches (less instrumentation; the
+ * other classes then report flops but no time); 0 disables.
  */
 h2_status h2_profile_enable(h2_matrix A, int32_t enable);
 int32_t h2_profile_classes(void);

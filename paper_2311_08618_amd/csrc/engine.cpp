@@ -157,6 +157,7 @@ inline bool f32_class(int cls) {
 // device array of per-class algorithmic flop counters.
 struct Profiler {
   bool on = false;
+  bool gemm_only = false;            // events only around GEMM launches (kernel symbols)
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> recs;
@@ -659,12 +660,13 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
       bt.fc = prof.on ? prof.d_fc + cls : nullptr;
       bt.fck = prof.on && tag >= 0 ? prof.d_fc + PC_N + tag : nullptr;
       hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (prof.on) {
+      const bool ev = prof.on && (!prof.gemm_only || tag >= 0);
+      if (ev) {
         e0 = prof.get();
         HIPCHK(hipEventRecord(e0, st));
       }
       fn();
-      if (prof.on) {
+      if (ev) {
         e1 = prof.get();
         HIPCHK(hipEventRecord(e1, st));
         prof.recs.push_back({cls | (prof.level << 16), {e0, e1}});
@@ -1302,6 +1304,7 @@ h2_status h2_profile_enable(h2_matrix A, int32_t enable) {
     return fail(H2_EDEVICE, e.where + ": " + hipGetErrorString(e.e));
   }
   A->prof.on = enable != 0;
+  A->prof.gemm_only = enable == 2;
   A->prof.reset();
   return H2_OK;
 }

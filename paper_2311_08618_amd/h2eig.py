@@ -220,8 +220,9 @@ class H2Matrix:
         _check(_lib.h2_tree_perm(self._h, p.ctypes.data_as(C.POINTER(C.c_int64))))
         return p
 
-    def profile_enable(self, on: bool = True):
-        _check(_lib.h2_profile_enable(self._h, 1 if on else 0))
+    def profile_enable(self, on=True):
+        """True/1: every launch timed; 2: GEMM launches only; False/0: off."""
+        _check(_lib.h2_profile_enable(self._h, int(on)))
 
     def profile_read(self) -> dict:
         out = {}
