@@ -158,6 +158,57 @@ def serve_bench(args):
     print(json.dumps(line))
 
 
+def queries_bench(args):
+    """k-th eigenvalue queries in three forms on fresh handles (no shared
+    records): one shift per factorization in FP64 (plain), every open bracket
+    in one batched factorization per step in FP64, and batched with FP32
+    contractions while a bracket is at least 1e-4 normA wide.  Prints one JSON
+    line with the eigenvalues per second of each form and the largest
+    difference of their results."""
+    import numpy as np
+    from paper_2311_08618_amd import workloads as W
+    from paper_2311_08618_amd.h2eig import H2Matrix
+
+    n, nq, tol = args.n, args.nq, args.tol
+    ks = [max(1, j * n // nq) for j in range(nq)]
+    X = W.cube_points(n, 0)
+    forms = {"plain_f64_1shift": (1, 0.0), "batched_f64": (0, 0.0), "batched_mixed": (0, 1e-4)}
+    out, lam = {}, {}
+    for name, (maxs, mixed) in forms.items():
+        A = H2Matrix(X, W.K_LAPLACE, 1e3, 256, 1.0, 1e-8)
+        if maxs:
+            A.set_max_shifts(maxs)
+        A.set_mixed(mixed)
+        A.interval()                      # the starting interval, outside the timed region
+        t0 = time.perf_counter()
+        lam[name], _ = A.kth_eig(ks, tol)
+        dt = time.perf_counter() - t0
+        st = A.stats()
+        out[name] = {"seconds": dt, "eigvals_per_s": nq / dt, "evals_f64": st["evals_f64"],
+                     "evals_f32": st["evals_f32"], "evals_per_s": (st["evals_f64"] + st["evals_f32"]) / dt}
+        print("queries: %s done in %.1f s" % (name, dt), file=sys.stderr, flush=True)
+        A.close()
+    ref = lam["plain_f64_1shift"]
+    norm = H2Matrix(X, W.K_LAPLACE, 1e3, 256, 1.0, 1e-8).norm()
+    line = {
+        "metric": "k-th eigenvalues/sec, batched and mixed-precision forms vs plain one-shift FP64",
+        "value": out["batched_mixed"]["eigvals_per_s"],
+        "unit": "eigvals/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f64 (FP32 contractions in early steps for batched_mixed)",
+        "data": "synthetic",
+        "forms": out,
+        "speedup_vs_plain": {k: out[k]["eigvals_per_s"] / out["plain_f64_1shift"]["eigvals_per_s"] for k in out},
+        "max_abs_dlambda_vs_plain": {k: float(np.max(np.abs(lam[k] - ref))) for k in out},
+        "max_rel_dlambda_vs_plain": {k: float(np.max(np.abs(lam[k] - ref)) / norm) for k in out},
+        "config": {"workload": "cube-laplace n=%d leaf=256 eta=1 eps=1e-8 A_ii=1e3; %d eigenvalues "
+                               "k = j*n/%d (j=0..%d, k=1 for j=0), tol %g" % (n, nq, nq, nq - 1, tol),
+                   "n": n, "ks": ks, "tol": tol, "normA": norm},
+    }
+    print(json.dumps(line))
+
+
 def cpu_baseline(n_sample: int = 4096, shifts: int = 4, n_target: int = 262144) -> dict:
     """The oracle as it stands, on the GPU host's cores, on a bounded sample."""
     import numpy as np
@@ -194,6 +245,10 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 18)
     ap.add_argument("--batch", type=int, default=2, help="shifts per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--queries", action="store_true",
+                    help="k-th eigenvalue queries: plain one-shift FP64 vs batched vs batched+mixed (uses --n)")
+    ap.add_argument("--nq", type=int, default=16, help="eigenvalues for --queries")
+    ap.add_argument("--tol", type=float, default=1e-8, help="absolute tolerance for --queries")
     ap.add_argument("--serve", action="store_true", help="serving-loop measurement instead of the step bench")
     ap.add_argument("--serve-sizes", default="262144,131072,65536,16384")
     ap.add_argument("--serve-slots", default="1,1,2,4", help="in-flight queries per matrix")
@@ -212,6 +267,9 @@ def main():
         return
     if args.serve:
         serve_bench(args)
+        return
+    if args.queries:
+        queries_bench(args)
         return
 
     from paper_2311_08618_amd import workloads as W
