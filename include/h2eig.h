@@ -169,12 +169,14 @@ h2_status h2_level_dims(h2_matrix A, int32_t nlev, int32_t* cap);
  * bucket (largest block dimension <= 256, 512, 1024, 2048, larger: 0..4):
  * grid = workgroups per shift (0 = built-in default, else a multiple of 8 in
  * [8, 65536]), group_m = tile-order group (tiles taken column by column within
- * groups of group_m tile rows; 0 or 1 = row by row).  The table is
- * process-wide and written by the autotuner's file at load time; set it while
- * no factorization runs.  Results do not depend on it.  H2_EINVAL for values
- * out of range. */
-h2_status h2_set_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_t grid, int32_t group_m);
-h2_status h2_get_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_t* grid, int32_t* group_m);
+ * groups of group_m tile rows; 0 or 1 = row by row), tile = output tile size
+ * (64 or 128; 0 = 64).  The table is process-wide and written by the
+ * autotuner's file at load time; set it while no factorization runs.  Results
+ * do not depend on it.  H2_EINVAL for values out of range. */
+h2_status h2_set_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_t grid, int32_t group_m,
+                             int32_t tile);
+h2_status h2_get_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_t* grid, int32_t* group_m,
+                             int32_t* tile);
 
 /* Cap on the shifts factored together in one launch (0 = automatic, from the
  * free device memory at each call); larger batches are split.  H2_EINVAL for

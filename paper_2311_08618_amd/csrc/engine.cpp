@@ -140,13 +140,18 @@ const char* const kProfNames[PC_N] = {"init", "recompress_pchol", "recompress_pc
                                       "pivot_ldl_update", "pivot_ldl_inverse", "pivot_ldl_operator", "elimination",
                                       "copyback", "schur", "fillin_gram", "merge_gather", "merge_fillin",
                                       "merge_transfer"};
-// per-kernel totals of the GEMM kernels by operand layout (GemmKind order),
-// FP64 then FP32
-constexpr int PROF_N = PC_N + 8;
-const char* const kGemmNames[8] = {"kernel:k_gemm<false, false>",     "kernel:k_gemm<false, true>",
-                                   "kernel:k_gemm<true, false>",      "kernel:k_gemm<true, true>",
-                                   "kernel:k_gemm_f32<false, false>", "kernel:k_gemm_f32<false, true>",
-                                   "kernel:k_gemm_f32<true, false>",  "kernel:k_gemm_f32<true, true>"};
+// per-kernel totals of the GEMM kernels by operand layout (GemmKind order):
+// 64 x 64 tiles FP64, FP32, then 128 x 128 tiles FP64, FP32
+constexpr int PROF_N = PC_N + 16;
+const char* const kGemmNames[16] = {
+    "kernel:k_gemm<false, false>",        "kernel:k_gemm<false, true>",
+    "kernel:k_gemm<true, false>",         "kernel:k_gemm<true, true>",
+    "kernel:k_gemm_f32<false, false>",    "kernel:k_gemm_f32<false, true>",
+    "kernel:k_gemm_f32<true, false>",     "kernel:k_gemm_f32<true, true>",
+    "kernel:k_gemm128<false, false>",     "kernel:k_gemm128<false, true>",
+    "kernel:k_gemm128<true, false>",      "kernel:k_gemm128<true, true>",
+    "kernel:k_gemm128_f32<false, false>", "kernel:k_gemm128_f32<false, true>",
+    "kernel:k_gemm128_f32<true, false>",  "kernel:k_gemm128_f32<true, true>"};
 // classes whose contractions run in FP32 in an FP32 factorization (rotation,
 // elimination, Schur, merge); recompression and the pivot LDL stay FP64
 inline bool f32_class(int cls) {
@@ -698,11 +703,18 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
     }
     run(PC_INIT, [&] { launch_fill(dG, nG, 0.0, st); });
     run(PC_INIT, [&] { launch_fill(dSg, nSg, 0.0, st); });
-    if (dl.gram_init.n)
-      run(PC_GRAM, [&] {
-        launch_gemm(GEMM_NT, A->dp<GItem>(dl.gram_init.items), dl.gram_init.n, A->dp<GTerm>(dl.gram_init.terms), bt,
-                    sz, cap, cap, S, dpre, st);
-      }, GEMM_NT);
+    // one GEMM launch of class cls: launch parameters from the tuning table,
+    // profiled under its kernel symbol (layout, precision, tile size)
+    auto gemm = [&](int cls, int kind, const GItem* items, int n, const GTerm* terms, int mcap, int ncap) {
+      if (n <= 0) return;
+      const int f = (f32 && f32_class(cls)) ? 1 : 0;
+      get_gemm_tuning(kind, f, gemm_bucket(std::max(mcap, ncap)), &bt.grid, &bt.group_m, &bt.tile);
+      run(cls, [&] { launch_gemm(kind, items, n, terms, bt, sz, mcap, ncap, S, dpre, st); },
+          kind + (bt.tile == 128 ? 8 : 0));
+      bt.grid = bt.group_m = bt.tile = 0;
+    };
+    gemm(PC_GRAM, GEMM_NT, A->dp<GItem>(dl.gram_init.items), dl.gram_init.n, A->dp<GTerm>(dl.gram_init.terms), cap,
+         cap);
     const double tau2 = A->tau * A->tau;
     // scratch slots of the out-of-place products: about 2 GB per shift at most
     int max_items = 1;
@@ -715,7 +727,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
     auto chunked = [&](int cls, int kind, const DevList& gl, size_t copies, size_t tcopies = 0) {
       for (int c0 = 0; c0 < gl.n; c0 += CH) {
         int nc = std::min(CH, gl.n - c0);
-        run(cls, [&] { launch_gemm(kind, A->dp<GItem>(gl.items) + c0, nc, A->dp<GTerm>(gl.terms), bt, sz, cap, cap, S, dpre, st); }, kind);
+        gemm(cls, kind, A->dp<GItem>(gl.items) + c0, nc, A->dp<GTerm>(gl.terms), cap, cap);
         run(PC_COPY, [&] { launch_copyback(A->dp<CopyItem>(copies) + c0, nc, bt, sz, cap, S, st); });
         if (tcopies) run(PC_COPY, [&] { launch_copyback_t(A->dp<CopyItem>(tcopies) + c0, nc, bt, sz, S, st); });
       }
@@ -725,7 +737,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
       const int* cl = A->dp<int>(dc.clusters);
       auto gl = [&](int cls, int kind, const DevList& L, int mcap = 0, int ncap = 0) {
         const int mc = mcap > 0 ? mcap : cap, nc = ncap > 0 ? ncap : cap;
-        if (L.n) run(cls, [&] { launch_gemm(kind, A->dp<GItem>(L.items), L.n, A->dp<GTerm>(L.terms), bt, sz, mc, nc, S, dpre, st); }, kind);
+        gemm(cls, kind, A->dp<GItem>(L.items), L.n, A->dp<GTerm>(L.terms), mc, nc);
       };
       // pivoted Cholesky of the fill-in Gram, panel by panel (finished clusters
       // make a panel a no-op, so the counters are read back every 4 panels)
@@ -835,20 +847,13 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
     setb(B_EMAT, A->d_emat[l - 1], 0, (size_t)A->emat_ld[l - 1] * A->emat_ld[l - 1], A->emat_ld[l - 1]);
     for (const MergeChunk& ch : mp.chunks) {
       run(PC_MERGE, [&] { launch_gather(A->dp<GatherItem>(dl.gather) + ch.g0, ch.g1 - ch.g0, bt, sz, pcap, S, st); });
-      if (ch.f1 > ch.f0)
-        run(PC_MERGE_FILL, [&] {
-          launch_gemm(GEMM_NT, A->dp<GItem>(dl.fill.items) + ch.f0, ch.f1 - ch.f0, A->dp<GTerm>(dl.fill.terms), bt, sz,
-                      pcap, pcap, S, dpre, st);
-        }, GEMM_NT);
+      gemm(PC_MERGE_FILL, GEMM_NT, A->dp<GItem>(dl.fill.items) + ch.f0, ch.f1 - ch.f0, A->dp<GTerm>(dl.fill.terms),
+           pcap, pcap);
       run(PC_MERGE, [&] { launch_merge_nn(A->dp<GatherItem>(dl.gather) + ch.g0, ch.g1 - ch.g0, bt, sz, pcap, S, st); });
-      run(PC_MERGE_E, [&] {
-        launch_gemm(GEMM_NN, A->dp<GItem>(dl.tr1.items) + ch.a0, ch.a1 - ch.a0, A->dp<GTerm>(dl.tr1.terms), bt, sz, pcap,
-                    emax, S, dpre, st);
-      }, GEMM_NN);
-      run(PC_MERGE_E, [&] {
-        launch_gemm(GEMM_TN, A->dp<GItem>(dl.tr2.items) + ch.b0, ch.b1 - ch.b0, A->dp<GTerm>(dl.tr2.terms), bt, sz, emax,
-                    pcap, S, dpre, st);
-      }, GEMM_TN);
+      gemm(PC_MERGE_E, GEMM_NN, A->dp<GItem>(dl.tr1.items) + ch.a0, ch.a1 - ch.a0, A->dp<GTerm>(dl.tr1.terms), pcap,
+           emax);
+      gemm(PC_MERGE_E, GEMM_TN, A->dp<GItem>(dl.tr2.items) + ch.b0, ch.b1 - ch.b0, A->dp<GTerm>(dl.tr2.terms), emax,
+           pcap);
     }
     run(PC_MERGE, [&] { launch_next_sizes(sz, S, st); });
     HIPCHK(hipGetLastError());
@@ -1220,23 +1225,28 @@ h2_status h2_interval(h2_matrix A, double* ab) {
   return H2_OK;
 }
 
-h2_status h2_set_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_t grid, int32_t group_m) {
+h2_status h2_set_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_t grid, int32_t group_m,
+                             int32_t tile) {
   if (layout < 0 || layout > 3 || f32 < 0 || f32 > 1 || bucket < 0 || bucket >= GEMM_BUCKETS)
     return fail(H2_EINVAL, "layout, f32 or bucket out of range");
   if (grid != 0 && (grid < 8 || grid > 65536 || grid % 8 != 0))
     return fail(H2_EINVAL, "grid must be 0 or a multiple of 8 in [8, 65536]");
   if (group_m < 0 || group_m > 64) return fail(H2_EINVAL, "group_m must be in [0, 64]");
-  set_gemm_tuning(layout, f32, bucket, grid, group_m);
+  if (tile != 0 && tile != 64 && tile != 128) return fail(H2_EINVAL, "tile must be 0, 64 or 128");
+  set_gemm_tuning(layout, f32, bucket, grid, group_m, tile);
   return H2_OK;
 }
 
-h2_status h2_get_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_t* grid, int32_t* group_m) {
-  if (layout < 0 || layout > 3 || f32 < 0 || f32 > 1 || bucket < 0 || bucket >= GEMM_BUCKETS || !grid || !group_m)
+h2_status h2_get_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_t* grid, int32_t* group_m,
+                             int32_t* tile) {
+  if (layout < 0 || layout > 3 || f32 < 0 || f32 > 1 || bucket < 0 || bucket >= GEMM_BUCKETS || !grid || !group_m ||
+      !tile)
     return fail(H2_EINVAL, "layout, f32 or bucket out of range, or NULL output");
-  int g = 0, gm = 0;
-  get_gemm_tuning(layout, f32, bucket, &g, &gm);
+  int g = 0, gm = 0, t = 0;
+  get_gemm_tuning(layout, f32, bucket, &g, &gm, &t);
   *grid = g;
   *group_m = gm;
+  *tile = t;
   return H2_OK;
 }
 

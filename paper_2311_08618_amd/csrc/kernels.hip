@@ -45,15 +45,14 @@ __global__ void k_fill_int(int* p, int64_t n, int v) {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int GT = 64;   // output tile
+constexpr int GT = 64;   // output tile of k_gemm (k_gemm128: 128)
 constexpr int GK = 16;   // k step
-constexpr int GEMM_GRID = 2048;   // workgroups of a GEMM launch (8 per CU)
 
 // Per shift, the exclusive prefix sum of the output tiles of every item of a
 // list (0 for an item whose guard or sizes are 0): the GEMM below then runs on a
 // fixed grid over the real tiles only.
 __global__ __launch_bounds__(1024) void k_tile_scan(const GItem* __restrict__ items, int nitems, SizeTab sz,
-                                                    int* __restrict__ prefix) {
+                                                    int* __restrict__ prefix, int T) {
   __shared__ int wsum[16];
   __shared__ int carry;
   const int s = blockIdx.x;
@@ -68,7 +67,7 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const GItem* __restrict__ it
       const GItem it = items[i];
       const bool skip = it.guard != -1 && dev_eval(it.guard, sz, s) == 0;
       const int M = dev_eval(it.M, sz, s), N = dev_eval(it.N, sz, s);
-      v = (skip || M <= 0 || N <= 0) ? 0 : ((M + GT - 1) / GT) * ((N + GT - 1) / GT);
+      v = (skip || M <= 0 || N <= 0) ? 0 : ((M + T - 1) / T) * ((N + T - 1) / T);
     }
     int x = v;   // inclusive scan within the wave
     for (int d = 1; d < 64; d <<= 1) {
@@ -100,8 +99,9 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const GItem* __restrict__ it
 // sharing panels of A or B meet in the same L2.  Operands and results are FP64
 // in memory; F32 converts the operands to FP32 on their way into LDS and
 // multiplies them on FP32 MFMA with FP32 accumulation (the early bisection
-// steps), else everything is FP64.
-template <bool TA, bool TB, bool F32>
+// steps), else everything is FP64.  Output tiles are T x T (64 or 128): four
+// waves in a 2 x 2 layout, each computing (T/2) x (T/2) as (T/32)^2 MFMA blocks.
+template <bool TA, bool TB, bool F32, int T>
 __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int nitems, const GTerm* __restrict__ terms,
                                           const BufTab& bt, const SizeTab& sz, const int* __restrict__ prefix,
                                           int slot_base) {
@@ -112,8 +112,11 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
   const int total = pre[nitems];
   const int G = gridDim.x;
   const int lw = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);   // G is a multiple of 8
-  __shared__ CT As[2][GK][GT + 1];
-  __shared__ CT Bs[2][GK][GT + 1];
+  constexpr int FW = T / 32;     // MFMA blocks per wave and dimension
+  constexpr int HT = T / 2;      // rows (columns) of a wave's part of the tile
+  constexpr int NE = T / 16;     // elements of each operand tile a thread stages
+  __shared__ CT As[2][GK][T + 1];
+  __shared__ CT Bs[2][GK][T + 1];
   for (int tile = lw; tile < total; tile += G) {
   int lo = 0, hi = nitems - 1;   // the item: the last i with pre[i] <= tile
   while (lo < hi) {
@@ -124,19 +127,19 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
   const int idx = lo;
   const GItem it = items[idx];
   const int M = dev_eval(it.M, sz, s), N = dev_eval(it.N, sz, s);
-  const int tn = (N + GT - 1) / GT;
+  const int tn = (N + T - 1) / T;
   const int local = tile - pre[idx];
   int mi, ni;
   if (bt.group_m <= 1) {
     mi = local / tn;
     ni = local % tn;
   } else {   // concurrent tiles share group_m row panels and a few column panels
-    const int tm = (M + GT - 1) / GT, gsz = bt.group_m * tn;
+    const int tm = (M + T - 1) / T, gsz = bt.group_m * tn;
     const int g = local / gsz, first = g * bt.group_m, rows = min(tm - first, bt.group_m), r = local - g * gsz;
     mi = first + r % rows;
     ni = r / rows;
   }
-  const int m0 = mi * GT, n0 = ni * GT;
+  const int m0 = mi * T, n0 = ni * T;
   if (bt.fc && local == 0 && threadIdx.x == 0) {
     unsigned long long kk = 0;
     for (int tt = 0; tt < it.nt; ++tt) kk += (unsigned long long)max(0, dev_eval(terms[it.t0 + tt].K, sz, s));
@@ -145,9 +148,9 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
   }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  VT acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = VT{0, 0, 0, 0};
+  VT acc[FW][FW];
+  for (int i = 0; i < FW; ++i)
+    for (int j = 0; j < FW; ++j) acc[i][j] = VT{0, 0, 0, 0};
 
   for (int tt = 0; tt < it.nt; ++tt) {
     const GTerm tm = terms[it.t0 + tt];
@@ -161,15 +164,15 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
     const int lda = bt.ld[tm.a.buf], ldb = bt.ld[tm.b.buf];
     const double* w = tm.wbuf >= 0 ? addr(bt, tm.wbuf, 0, s, 0, 0) + (int64_t)tm.wblk * bt.bs[tm.wbuf] : nullptr;
     const int nk = (K + GK - 1) / GK;
-    // this thread's four elements of each tile: A as (mm, kk), B as (kk, nn)
-    double ra[4], rb[4];
+    // this thread's NE elements of each tile: A as (mm, kk), B as (kk, nn)
+    double ra[NE], rb[NE];
     auto gload = [&](int kt) {
       const int k0 = kt * GK;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < NE; ++r) {
         const int e = tid + 256 * r;
         int mm, kk;
-        if (TA) { kk = e % GK; mm = e / GK; } else { mm = e % GT; kk = e / GT; }
+        if (TA) { kk = e % GK; mm = e / GK; } else { mm = e % T; kk = e / T; }
         const int gm = m0 + mm, gk = k0 + kk;
         double v = 0.0;
         if (gm < M && gk < K) {
@@ -178,20 +181,20 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
         }
         ra[r] = v;
         int nn, kb;
-        if (TB) { nn = e % GT; kb = e / GT; } else { kb = e % GK; nn = e / GK; }
+        if (TB) { nn = e % T; kb = e / T; } else { kb = e % GK; nn = e / GK; }
         const int gn = n0 + nn, gkb = k0 + kb;
         rb[r] = (gn < N && gkb < K) ? (TB ? B[gn + (int64_t)gkb * ldb] : B[gkb + (int64_t)gn * ldb]) : 0.0;
       }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < NE; ++r) {
         const int e = tid + 256 * r;
         int mm, kk;
-        if (TA) { kk = e % GK; mm = e / GK; } else { mm = e % GT; kk = e / GT; }
+        if (TA) { kk = e % GK; mm = e / GK; } else { mm = e % T; kk = e / T; }
         As[buf][kk][mm] = (CT)ra[r];
         int nn, kb;
-        if (TB) { nn = e % GT; kb = e / GT; } else { kb = e % GK; nn = e / GK; }
+        if (TB) { nn = e % T; kb = e / T; } else { kb = e % GK; nn = e / GK; }
         Bs[buf][kb][nn] = (CT)rb[r];
       }
     };
@@ -204,21 +207,19 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
 #pragma unroll
       for (int kk = 0; kk < GK; kk += 4) {
         const int kr = kk + (lane >> 4);
-        const CT a0 = As[cur][kr][wm * 32 + (lane & 15)];
-        const CT a1 = As[cur][kr][wm * 32 + 16 + (lane & 15)];
-        const CT b0 = Bs[cur][kr][wn * 32 + (lane & 15)];
-        const CT b1 = Bs[cur][kr][wn * 32 + 16 + (lane & 15)];
-        if constexpr (F32) {
-          acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-          acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
-        } else {
-          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        CT a[FW], b[FW];
+#pragma unroll
+        for (int f = 0; f < FW; ++f) {
+          a[f] = As[cur][kr][wm * HT + f * 16 + (lane & 15)];
+          b[f] = Bs[cur][kr][wn * HT + f * 16 + (lane & 15)];
         }
+#pragma unroll
+        for (int i = 0; i < FW; ++i)
+#pragma unroll
+          for (int j = 0; j < FW; ++j) {
+            if constexpr (F32) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+            else acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+          }
       }
       if (kt + 1 < nk) sstore(cur ^ 1);
       __syncthreads();
@@ -242,13 +243,13 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
     C2 = addr(bt, it.c2.buf, it.c2.blk, s, r2, c2);
     ldc2 = bt.ld[it.c2.buf];
   }
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
+  for (int i = 0; i < FW; ++i)
+    for (int j = 0; j < FW; ++j)
       for (int v = 0; v < 4; ++v) {
         // output row of register v: FP64 MFMA puts D[i][j] in lane j + 16*(i%4),
         // register i/4; FP32 MFMA in lane j + 16*(i/4), register i%4
-        int r = m0 + wm * 32 + i * 16 + (F32 ? 4 * (lane >> 4) + v : (lane >> 4) + 4 * v);
-        int c = n0 + wn * 32 + j * 16 + (lane & 15);
+        int r = m0 + wm * HT + i * 16 + (F32 ? 4 * (lane >> 4) + v : (lane >> 4) + 4 * v);
+        int c = n0 + wn * HT + j * 16 + (lane & 15);
         if (r < M && c < N) {
           double x = it.alpha * (double)acc[i][j][v];
           const int dr = r < rs ? cr + r : r2o + (r - rs), dcol = c < cs ? cc + c : c2o + (c - cs);
@@ -267,14 +268,29 @@ template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, int nitems,
                                               const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
                                               const int* __restrict__ prefix, int slot_base) {
-  gemm_body<TA, TB, false>(items, nitems, terms, bt, sz, prefix, slot_base);
+  gemm_body<TA, TB, false, 64>(items, nitems, terms, bt, sz, prefix, slot_base);
 }
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm_f32(const GItem* __restrict__ items, int nitems,
                                                   const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
                                                   const int* __restrict__ prefix, int slot_base) {
-  gemm_body<TA, TB, true>(items, nitems, terms, bt, sz, prefix, slot_base);
+  gemm_body<TA, TB, true, 64>(items, nitems, terms, bt, sz, prefix, slot_base);
+}
+
+// 128 x 128 output tiles: twice the arithmetic per operand byte, for large blocks
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm128(const GItem* __restrict__ items, int nitems,
+                                                 const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
+                                                 const int* __restrict__ prefix, int slot_base) {
+  gemm_body<TA, TB, false, 128>(items, nitems, terms, bt, sz, prefix, slot_base);
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm128_f32(const GItem* __restrict__ items, int nitems,
+                                                     const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
+                                                     const int* __restrict__ prefix, int slot_base) {
+  gemm_body<TA, TB, true, 128>(items, nitems, terms, bt, sz, prefix, slot_base);
 }
 
 // Transposed copy of a scratch slot into a block: X[r0 + a][c0 + b] = RS[slot][b][a]
@@ -1444,56 +1460,63 @@ void launch_fill_int(int* p, int64_t n, int v, hipStream_t st) {
 }
 
 // GEMM launch parameters by operand layout, precision and capacity bucket
-// (largest block dimension <= 256, 512, 1024, 2048, larger).  The defaults
-// come from a sweep of square batches on gfx950 (grid 2048/4096/2048/1024/1024,
-// row-by-row tile order); the autotuner's table overrides them.  Process-wide;
-// atomics because concurrent factorizations read it.
+// (largest block dimension <= 256, 512, 1024, 2048, larger): workgroups per
+// shift, tile order and tile size.  The defaults come from a sweep of square
+// batches on gfx950 (grid 2048/4096/2048/1024/1024, row-by-row tile order,
+// 64 x 64 tiles); the autotuner's table overrides them.  Process-wide; atomics
+// because concurrent factorizations read it.
 namespace {
 constexpr int kDefaultGrid[GEMM_BUCKETS] = {2048, 4096, 2048, 1024, 1024};
 std::atomic<int> g_tune_grid[4][2][GEMM_BUCKETS];    // 0 = default
 std::atomic<int> g_tune_group[4][2][GEMM_BUCKETS];   // 0 = row by row
+std::atomic<int> g_tune_tile[4][2][GEMM_BUCKETS];    // 0 = 64
+
+template <bool TA, bool TB>
+void launch_variant(int f32, int T, dim3 grid, const GItem* items, int nitems, const GTerm* terms, const BufTab& bt,
+                    const SizeTab& sz, int* prefix, hipStream_t st) {
+  if (T == 128) {
+    if (f32) hipLaunchKernelGGL((k_gemm128_f32<TA, TB>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0);
+    else hipLaunchKernelGGL((k_gemm128<TA, TB>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0);
+  } else {
+    if (f32) hipLaunchKernelGGL((k_gemm_f32<TA, TB>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0);
+    else hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0);
+  }
+}
 }  // namespace
 
 int gemm_bucket(int cap) { return cap <= 256 ? 0 : cap <= 512 ? 1 : cap <= 1024 ? 2 : cap <= 2048 ? 3 : 4; }
 
-void set_gemm_tuning(int layout, int f32, int bucket, int grid, int group_m) {
+void set_gemm_tuning(int layout, int f32, int bucket, int grid, int group_m, int tile) {
   g_tune_grid[layout][f32][bucket].store(grid);
   g_tune_group[layout][f32][bucket].store(group_m);
+  g_tune_tile[layout][f32][bucket].store(tile);
 }
 
-void get_gemm_tuning(int layout, int f32, int bucket, int* grid, int* group_m) {
+void get_gemm_tuning(int layout, int f32, int bucket, int* grid, int* group_m, int* tile) {
   const int g = g_tune_grid[layout][f32][bucket].load();
   *grid = g > 0 ? g : kDefaultGrid[bucket];
   *group_m = std::max(1, g_tune_group[layout][f32][bucket].load());
+  *tile = g_tune_tile[layout][f32][bucket].load() == 128 ? 128 : 64;
 }
 
 void launch_gemm(int kind, const GItem* items, int nitems, const GTerm* terms, const BufTab& bt_in, const SizeTab& sz,
                  int mcap, int ncap, int nshift, int* prefix, hipStream_t st) {
   BufTab bt = bt_in;
-  if (bt.grid <= 0) {   // launch parameters from the tuning table
-    get_gemm_tuning(kind, bt.f32 ? 1 : 0, gemm_bucket(std::max(mcap, ncap)), &bt.grid, &bt.group_m);
-  }
+  if (bt.grid <= 0)   // launch parameters from the tuning table
+    get_gemm_tuning(kind, bt.f32 ? 1 : 0, gemm_bucket(std::max(mcap, ncap)), &bt.grid, &bt.group_m, &bt.tile);
+  const int T = bt.tile == 128 ? 128 : 64;
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_tile_scan, dim3(nshift), dim3(1024), 0, st, items, nitems, sz, prefix);
+  hipLaunchKernelGGL(k_tile_scan, dim3(nshift), dim3(1024), 0, st, items, nitems, sz, prefix, T);
   // a fixed grid, no larger than the tiles the capacities allow (multiple of 8)
-  const int64_t upper = (int64_t)nitems * cdiv(mcap, GT) * cdiv(ncap, GT);
-  const int gmax = bt.grid > 0 ? bt.grid : GEMM_GRID;
-  const int G = (int)std::max<int64_t>(8, std::min<int64_t>(gmax, (upper + 7) / 8 * 8));
-  dim3 grid(G, 1, nshift);
-  if (bt.f32) {
-    switch (kind) {
-      case GEMM_NN: hipLaunchKernelGGL((k_gemm_f32<false, false>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
-      case GEMM_NT: hipLaunchKernelGGL((k_gemm_f32<false, true>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
-      case GEMM_TN: hipLaunchKernelGGL((k_gemm_f32<true, false>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
-      default: hipLaunchKernelGGL((k_gemm_f32<true, true>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
-    }
-    return;
-  }
+  const int64_t upper = (int64_t)nitems * cdiv(mcap, T) * cdiv(ncap, T);
+  const int G = (int)std::max<int64_t>(8, std::min<int64_t>(bt.grid, (upper + 7) / 8 * 8));
+  const dim3 grid(G, 1, nshift);
+  const int f32 = bt.f32 ? 1 : 0;
   switch (kind) {
-    case GEMM_NN: hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
-    case GEMM_NT: hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
-    case GEMM_TN: hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
-    default: hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0); break;
+    case GEMM_NN: launch_variant<false, false>(f32, T, grid, items, nitems, terms, bt, sz, prefix, st); break;
+    case GEMM_NT: launch_variant<false, true>(f32, T, grid, items, nitems, terms, bt, sz, prefix, st); break;
+    case GEMM_TN: launch_variant<true, false>(f32, T, grid, items, nitems, terms, bt, sz, prefix, st); break;
+    default: launch_variant<true, true>(f32, T, grid, items, nitems, terms, bt, sz, prefix, st); break;
   }
 }
 

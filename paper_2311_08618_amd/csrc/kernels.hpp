@@ -9,12 +9,12 @@ namespace h2 {
 enum GemmKind { GEMM_NN = 0, GEMM_NT = 1, GEMM_TN = 2, GEMM_TT = 3 };
 
 // GEMM tuning table: capacity buckets (largest block dimension <= 256, 512,
-// 1024, 2048, larger), and per (layout, FP32, bucket) the workgroups per shift
-// and the tile-order group.
+// 1024, 2048, larger), and per (layout, FP32, bucket) the workgroups per shift,
+// the tile-order group and the tile size (64 or 128).
 constexpr int GEMM_BUCKETS = 5;
 int gemm_bucket(int cap);
-void set_gemm_tuning(int layout, int f32, int bucket, int grid, int group_m);
-void get_gemm_tuning(int layout, int f32, int bucket, int* grid, int* group_m);
+void set_gemm_tuning(int layout, int f32, int bucket, int grid, int group_m, int tile);
+void get_gemm_tuning(int layout, int f32, int bucket, int* grid, int* group_m, int* tile);
 
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void launch_fill_int(int* p, int64_t n, int v, hipStream_t st);

@@ -86,9 +86,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.h2_level_dims.restype = C.c_int
     lib.h2_level_dims.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32)]
     lib.h2_set_gemm_tuning.restype = C.c_int
-    lib.h2_set_gemm_tuning.argtypes = [C.c_int32] * 5
+    lib.h2_set_gemm_tuning.argtypes = [C.c_int32] * 6
     lib.h2_get_gemm_tuning.restype = C.c_int
-    lib.h2_get_gemm_tuning.argtypes = [C.c_int32, C.c_int32, C.c_int32, P(C.c_int32), P(C.c_int32)]
+    lib.h2_get_gemm_tuning.argtypes = [C.c_int32, C.c_int32, C.c_int32, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
     lib.h2_set_max_shifts.restype = C.c_int
     lib.h2_set_max_shifts.argtypes = [C.c_void_p, C.c_int32]
     lib.h2_free.restype = None
@@ -126,14 +126,15 @@ def _check(st: int):
         raise H2EigError(st, _lib.h2_last_error().decode())
 
 
-def set_gemm_tuning(layout: int, f32: int, bucket: int, grid: int, group_m: int):
-    _check(_lib.h2_set_gemm_tuning(int(layout), int(f32), int(bucket), int(grid), int(group_m)))
+def set_gemm_tuning(layout: int, f32: int, bucket: int, grid: int, group_m: int, tile: int = 0):
+    _check(_lib.h2_set_gemm_tuning(int(layout), int(f32), int(bucket), int(grid), int(group_m), int(tile)))
 
 
 def get_gemm_tuning(layout: int, f32: int, bucket: int):
-    g, gm = C.c_int32(), C.c_int32()
-    _check(_lib.h2_get_gemm_tuning(int(layout), int(f32), int(bucket), C.byref(g), C.byref(gm)))
-    return g.value, gm.value
+    """(grid, group_m, tile) of one entry."""
+    g, gm, t = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(_lib.h2_get_gemm_tuning(int(layout), int(f32), int(bucket), C.byref(g), C.byref(gm), C.byref(t)))
+    return g.value, gm.value, t.value
 
 
 def apply_tuning(path: str = TUNING_FILE) -> int:
@@ -143,7 +144,7 @@ def apply_tuning(path: str = TUNING_FILE) -> int:
         table = json.load(f)
     n = 0
     for e in table["entries"]:
-        set_gemm_tuning(e["layout"], e["f32"], e["bucket"], e["grid"], e["group_m"])
+        set_gemm_tuning(e["layout"], e["f32"], e["bucket"], e["grid"], e["group_m"], e.get("tile", 64))
         n += 1
     return n
 

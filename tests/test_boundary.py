@@ -146,14 +146,14 @@ def test_gemm_tuning_table(mod):
     """The tuning table validates its arguments and round-trips an entry
     (host only: no device work)."""
     L = mod._lib
-    g0, gm0 = mod.get_gemm_tuning(1, 0, 3)
-    assert g0 % 8 == 0 and g0 >= 8 and gm0 >= 1
-    for bad in [(4, 0, 0, 1024, 1), (0, 2, 0, 1024, 1), (0, 0, 5, 1024, 1), (0, 0, 0, 1001, 1),
-                (0, 0, 0, 4, 1), (0, 0, 0, 1024, 65), (-1, 0, 0, 1024, 1)]:
+    g0, gm0, t0 = mod.get_gemm_tuning(1, 0, 3)
+    assert g0 % 8 == 0 and g0 >= 8 and gm0 >= 1 and t0 in (64, 128)
+    for bad in [(4, 0, 0, 1024, 1, 64), (0, 2, 0, 1024, 1, 64), (0, 0, 5, 1024, 1, 64), (0, 0, 0, 1001, 1, 64),
+                (0, 0, 0, 4, 1, 64), (0, 0, 0, 1024, 65, 64), (-1, 0, 0, 1024, 1, 64), (0, 0, 0, 1024, 1, 96)]:
         assert L.h2_set_gemm_tuning(*bad) == mod.H2_EINVAL, bad
     try:
-        mod.set_gemm_tuning(1, 0, 3, 512, 8)
-        assert mod.get_gemm_tuning(1, 0, 3) == (512, 8)
+        mod.set_gemm_tuning(1, 0, 3, 512, 8, 128)
+        assert mod.get_gemm_tuning(1, 0, 3) == (512, 8, 128)
     finally:
-        mod.set_gemm_tuning(1, 0, 3, g0, gm0)
-    assert mod.get_gemm_tuning(1, 0, 3) == (g0, gm0)
+        mod.set_gemm_tuning(1, 0, 3, g0, gm0, t0)
+    assert mod.get_gemm_tuning(1, 0, 3) == (g0, gm0, t0)

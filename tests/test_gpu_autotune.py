@@ -25,24 +25,24 @@ def test_counts_do_not_depend_on_tuning(lib):
     ref32 = A.inertia(sig, f32=True)
     saved = {(l, f, b): lib.get_gemm_tuning(l, f, b) for l in range(4) for f in (0, 1) for b in range(5)}
     try:
-        for g, gm in [(8, 1), (512, 8), (4096, 3)]:
+        for g, gm, t in [(8, 1, 64), (512, 8, 64), (4096, 3, 64), (256, 1, 128), (1024, 8, 128)]:
             for key in saved:
-                lib.set_gemm_tuning(*key, g, gm)
-            assert np.array_equal(A.inertia(sig), ref), (g, gm)
-            assert np.array_equal(A.inertia(sig, f32=True), ref32), (g, gm)
+                lib.set_gemm_tuning(*key, g, gm, t)
+            assert np.array_equal(A.inertia(sig), ref), (g, gm, t)
+            assert np.array_equal(A.inertia(sig, f32=True), ref32), (g, gm, t)
     finally:
-        for key, (g, gm) in saved.items():
-            lib.set_gemm_tuning(*key, g, gm)
+        for key, val in saved.items():
+            lib.set_gemm_tuning(*key, *val)
 
 
 def test_short_autotune_writes_a_loadable_table(lib, tmp_path):
     print("case autotune n=4096", flush=True)
     from paper_2311_08618_amd import autotune
     saved = {(l, f, b): lib.get_gemm_tuning(l, f, b) for l in range(4) for f in (0, 1) for b in range(5)}
-    table = autotune.tune(n=4096, reps=1, grids=[1024, 2048], groups=[1, 8], log=lambda s: None)
+    table = autotune.tune(n=4096, reps=1, grids=[1024, 2048], groups=[1], tiles=[64, 128], log=lambda s: None)
     assert table["entries"]
     for e in table["entries"]:
-        assert e["grid"] in (1024, 2048) and e["group_m"] in (1, 8)
+        assert e["grid"] in (1024, 2048) and e["group_m"] == 1 and e["tile"] in (64, 128)
         assert 0 <= e["layout"] <= 3 and e["f32"] in (0, 1) and 0 <= e["bucket"] <= 4
     # the tuner leaves the table as it found it
     assert {k: lib.get_gemm_tuning(*k) for k in saved} == saved
@@ -51,7 +51,7 @@ def test_short_autotune_writes_a_loadable_table(lib, tmp_path):
     try:
         assert lib.apply_tuning(str(p)) == len(table["entries"])
         e = table["entries"][0]
-        assert lib.get_gemm_tuning(e["layout"], e["f32"], e["bucket"]) == (e["grid"], e["group_m"])
+        assert lib.get_gemm_tuning(e["layout"], e["f32"], e["bucket"]) == (e["grid"], e["group_m"], e["tile"])
     finally:
-        for key, (g, gm) in saved.items():
-            lib.set_gemm_tuning(*key, g, gm)
+        for key, val in saved.items():
+            lib.set_gemm_tuning(*key, *val)
