@@ -364,6 +364,8 @@ def main():
                      "note": "rotation, elimination, Schur and merge contractions in FP32; recompression and "
                              "pivot LDL in FP64"},
         "classes_ms": {k: round(v["ms"], 1) for k, v in roles.items()},
+        "classes_tflops": {k: round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2) for k, v in roles.items()
+                           if v["ms"] > 0 and v["flops"] > 0},
         "gemm_kernels_ms": {k: round(v["ms"], 1) for k, v in kern.items()},
     }
     if not args.no_cpu_baseline:
