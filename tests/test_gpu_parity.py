@@ -83,6 +83,36 @@ def test_cube_small_vs_oracle(lib, kind, diag, eps):
     _windowed_check(nu, H, sig)
 
 
+@pytest.mark.parametrize("case", ["cylinders-gauss-damped", "circle-reg-laplace"])
+def test_other_geometries_vs_oracle(lib, case):
+    """The nanotube-like layout (16 cylinders, kernel exp(-r^2/0.01)/(r+0.01),
+    A_ii = 10: an indefinite matrix) and the paper's circle experiment
+    (equispaced points, kernel 1/(r + 1e-3)) against the oracle."""
+    n, leaf = 1024, 64
+    if case.startswith("cylinders"):
+        X, kind, diag, p0, p1 = W.cylinder_points(n, 0), W.K_GAUSS_DAMPED, 10.0, 0.01, 0.01
+    else:
+        X, kind, diag, p0, p1 = W.circle_points(n), W.K_REG_LAPLACE, 1e3, 1e-3, 0.0
+    print("case %s n=%d" % (case, n), flush=True)
+    A = lib.H2Matrix(X, kind, diag, leaf, 1.0, 1e-8, p0=p0, p1=p1)
+    H = H2(X, Kernel(kind, diag, p0, p1), leaf, 1.0, 1e-8)
+    assert abs(A.norm() - H.normA) <= 1e-10 * H.normA
+    assert np.array_equal(A.tree_perm(), H.tree.perm())
+    ev = np.linalg.eigvalsh(H.dense())
+    gaps = np.diff(ev)
+    mid = 0.5 * (ev[:-1] + ev[1:])
+    pick = np.flatnonzero(gaps > 1e-3 * H.normA)
+    pick = pick[np.linspace(0, len(pick) - 1, min(12, len(pick))).astype(int)]
+    sig = np.concatenate([mid[pick], [ev[0] - 1.0, ev[-1] + 1.0]])
+    nu = A.inertia(sig)
+    orc = np.array([OF.inertia(H, s) for s in sig])
+    print("gpu", nu.tolist())
+    print("orc", orc.tolist())
+    assert nu[-2] == 0 and nu[-1] == n
+    assert np.array_equal(nu, orc), (nu - orc)
+    _windowed_check(nu, H, sig)
+
+
 def test_batch_equals_single(lib):
     """Per-shift work is independent of the batch: one shift alone gives the
     same count as in a batch of 9."""
