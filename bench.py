@@ -36,6 +36,16 @@ GEMM_CLASSES = {"recompress_w", "rotate", "elimination", "schur", "fillin_gram",
                 "pivot_ldl_inverse", "recompress_pchol_update", "pivot_ldl_update"}
 
 
+# step-bench workloads: (default n, points(n), kernel, A_ii, leaf, eps, p0, p1, shift range, default batch)
+WORKLOADS = {
+    # n points uniform in the unit cube (seed 0), 1/r: the headline configuration at n = 2^18
+    "cube-laplace": (1 << 18, "cube", 0, 1e3, 256, 1e-8, 0.0, 0.0, (900.0, 1100.0), 2),
+    # the same points at n = 131072, exp(-r)/r, eps 1e-10
+    "cube-yukawa": (131072, "cube", 1, 1e3, 256, 1e-10, 0.0, 0.0, (900.0, 1100.0), 2),
+    # 2^20 points on 16 parallel cylinders (seed 0), exp(-r^2/0.01)/(r+0.01), A_ii = 10, leaf 512
+    "cylinders-gauss": (1 << 20, "cylinders", 2, 10.0, 512, 1e-8, 0.01, 0.01, (5.0, 15.0), 1),
+}
+
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2311_08618_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_gemm_nt_cube_laplace_n262144.md")
 
@@ -242,8 +252,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=1 << 18)
-    ap.add_argument("--batch", type=int, default=2, help="shifts per step")
+    ap.add_argument("--workload", default="cube-laplace", choices=sorted(WORKLOADS))
+    ap.add_argument("--n", type=int, default=0, help="points (0 = the workload's size)")
+    ap.add_argument("--batch", type=int, default=0, help="shifts per step (0 = the workload's default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--queries", action="store_true",
                     help="k-th eigenvalue queries: plain one-shift FP64 vs batched vs batched+mixed (uses --n)")
@@ -275,12 +286,14 @@ def main():
     from paper_2311_08618_amd import workloads as W
     from paper_2311_08618_amd.h2eig import H2Matrix
 
-    n, S = args.n, args.batch
+    n0, geom, kind, diag, leaf, eps, p0, p1, srange, S0 = WORKLOADS[args.workload]
+    n, S = args.n or n0, args.batch or S0
+    X = W.cube_points(n, 0) if geom == "cube" else W.cylinder_points(n, 0)
     t0 = time.perf_counter()
-    A = H2Matrix(W.cube_points(n, 0), W.K_LAPLACE, 1e3, 256, 1.0, 1e-8, max_shifts=S)
+    A = H2Matrix(X, kind, diag, leaf, 1.0, eps, p0=p0, p1=p1, max_shifts=S)
     build_s = time.perf_counter() - t0
     print("bench: built n=%d in %.1f s" % (n, build_s), file=sys.stderr, flush=True)
-    sig = W.shift_grid(900.0, 1100.0, S, seed=0)
+    sig = W.shift_grid(srange[0], srange[1], S, seed=0)
     for w in range(args.warmup):
         A.inertia(sig)
         print("bench: warmup %d done" % w, file=sys.stderr, flush=True)
@@ -338,7 +351,8 @@ def main():
     a0, b0 = A.interval()
     steps_q = {tol: math.ceil(math.log2((b0 - a0) / tol)) for tol in (1e-6, 1e-10)}
     line = {
-        "metric": "H2 LDL+inertia evals/sec at n=2^18",
+        "metric": "H2 LDL+inertia evals/sec at n=2^18" if (args.workload, n) == ("cube-laplace", 1 << 18)
+                  else "H2 LDL+inertia evals/sec",
         "value": value,
         "unit": "evals/s",
         "n_gpus": 1,
@@ -350,8 +364,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "cube-laplace n=%d leaf=256 eta=1 eps=1e-8 A_ii=1e3, %d shift(s) per step" % (n, S),
-                   "n": n, "shifts_per_step": S, "build_s": round(build_s, 2)},
+        "config": {"workload": "%s n=%d leaf=%d eta=1 eps=%g A_ii=%g%s, %d shift(s) per step in [%g, %g]"
+                               % (args.workload, n, leaf, eps, diag, " p0=%g p1=%g" % (p0, p1) if p0 or p1 else "",
+                                  S, srange[0], srange[1]),
+                   "n": n, "shifts_per_step": S, "build_s": round(build_s, 2),
+                   "resident_gb": round(st["resident_bytes"] / 1e9, 1)},
         "roofline": roofline,
         "path_tflops": total_flops / dt / 1e12,
         "kth_eigvals_per_s_derived": {"tol=%g" % t: value / s for t, s in steps_q.items()},
@@ -368,7 +385,7 @@ def main():
                            if v["ms"] > 0 and v["flops"] > 0},
         "gemm_kernels_ms": {k: round(v["ms"], 1) for k, v in kern.items()},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "cube-laplace":
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line))
 

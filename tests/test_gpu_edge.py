@@ -111,3 +111,18 @@ def test_interval_is_gershgorin(lib, n, dim, kind, diag):
     got = A.interval()
     assert abs(got[0] - want[0]) <= 1e-12 * abs(rad.max()) + 1e-12 and abs(got[1] - want[1]) <= 1e-12 * rad.max(), \
         (got, want)
+
+
+def test_yukawa_full_size_properties(lib):
+    """The Yukawa workload at its full size (cube, n = 131072, exp(-r)/r,
+    eps 1e-10): nu = 0 and n at the ends of the starting interval, nu monotone
+    in sigma, and a one-shift call equal to the batched one."""
+    n = 131072
+    print("case cube-yukawa n=%d properties" % n, flush=True)
+    A = lib.H2Matrix(W.cube_points(n, 0), W.K_YUKAWA, 1e3, 256, 1.0, 1e-10, max_shifts=2)
+    a, b = A.interval()
+    nu = A.inertia(np.array([a, 990.0, 1000.0, b]))
+    assert nu[0] == 0 and nu[3] == n
+    assert 0 < nu[1] <= nu[2] < n
+    one = A.inertia(np.array([1000.0]))
+    assert one[0] == nu[2]
