@@ -266,12 +266,14 @@ h2_status h2s_submit(h2_server S, int32_t id, int64_t k, double tol, int64_t* ti
 /* done = 1 and lambda set once the query has finished; the status of a failed
  * factorization is returned for its queries. */
 h2_status h2s_poll(h2_server S, int64_t ticket, double* lambda, int32_t* done);
-/* Block until the query has finished. */
+/* Block until the query has finished (H2_EINVAL if the server stops first). */
 h2_status h2s_wait(h2_server S, int64_t ticket, double* lambda);
 /* Latency percentiles (submission to completion, ms) of the finished queries,
  * and the numbers of finished and submitted queries. */
 h2_status h2s_stats(h2_server S, double* p50_ms, double* p99_ms, int64_t* served, int64_t* submitted);
-/* Stop the workers (in-flight queries are abandoned) and free the server. */
+/* Stop the workers (in-flight queries are abandoned; a worker inside a
+ * factorization finishes it first) and free the server.  No other h2s_ call
+ * on S may be running or follow: join the threads that poll or wait first. */
 void h2s_destroy(h2_server S);
 
 const char* h2_last_error(void);
