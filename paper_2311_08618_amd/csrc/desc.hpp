@@ -145,6 +145,7 @@ struct CopyItem {
   Ref x;
   int M, N;
   int guard;
+  Ref src{-1, 0, 0, 0, 0, 0};   // source block of a transposed copy (buf < 0: the item's scratch slot)
 };
 
 // Matrix sum: C[M x N] = sum_t A_t[M x N] (all at origin)

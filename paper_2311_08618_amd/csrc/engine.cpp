@@ -125,8 +125,8 @@ struct DevColour {
 
 struct DevLevel {
   std::vector<DevColour> colours;
-  size_t diag_blk = 0, r0 = 0, pr0 = 0, gather = 0;
-  int ngather = 0;
+  size_t diag_blk = 0, r0 = 0, pr0 = 0, gather = 0, mirror = 0;
+  int ngather = 0, nmirror = 0;
   DevList gram_init, fill, tr1, tr2;
 };
 
@@ -330,6 +330,8 @@ void upload_plan(h2_matrix A) {
       dl.pr0 = b.put(mp.pr0);
       dl.gather = b.put(mp.gather);
       dl.ngather = (int)mp.gather.size();
+      dl.mirror = b.put(mp.mirror);
+      dl.nmirror = (int)mp.mirror.size();
       dl.fill = put_list(b, mp.fill);
       dl.tr1 = put_list(b, mp.tr1);
       dl.tr2 = put_list(b, mp.tr2);
@@ -855,6 +857,8 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
       gemm(PC_MERGE_E, GEMM_TN, A->dp<GItem>(dl.tr2.items) + ch.b0, ch.b1 - ch.b0, A->dp<GTerm>(dl.tr2.terms), emax,
            pcap);
     }
+    // parent blocks (p,q), q < p: transposed copies of the finished (q,p)
+    if (dl.nmirror) run(PC_MERGE, [&] { launch_copyback_t(A->dp<CopyItem>(dl.mirror), dl.nmirror, bt, sz, S, st); });
     run(PC_MERGE, [&] { launch_next_sizes(sz, S, st); });
     HIPCHK(hipGetLastError());
     cur = other;

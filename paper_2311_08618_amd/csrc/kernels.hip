@@ -293,8 +293,9 @@ __global__ __launch_bounds__(256) void k_gemm128_f32(const GItem* __restrict__ i
   gemm_body<TA, TB, true, 128>(items, nitems, terms, bt, sz, prefix, slot_base);
 }
 
-// Transposed copy of a scratch slot into a block: X[r0 + a][c0 + b] = RS[slot][b][a]
-// (a < M, b < N), through 64x64 LDS tiles so that both sides are coalesced.
+// Transposed copy of a scratch slot, or of a source block, into a block:
+// X[r0 + a][c0 + b] = SRC[b][a] (a < M, b < N), through 64x64 LDS tiles so
+// that both sides are coalesced.
 __global__ __launch_bounds__(256) void k_copyback_t(const CopyItem* __restrict__ items, BufTab bt, SizeTab sz,
                                                     int slot_base) {
   __shared__ double tile[64][65];
@@ -307,8 +308,17 @@ __global__ __launch_bounds__(256) void k_copyback_t(const CopyItem* __restrict__
   ref_origin(it.x, sz, s, &r0, &c0);
   double* X = addr(bt, it.x.buf, it.x.blk, s, r0, c0);
   const int ldx = bt.ld[it.x.buf];
-  const double* Sc = addr(bt, B_RS, (int)blockIdx.y + slot_base, s, 0, 0);
-  const int lds = bt.ld[B_RS];
+  const double* Sc;
+  int lds;
+  if (it.src.buf >= 0) {   // from a block
+    int sr, sc;
+    ref_origin(it.src, sz, s, &sr, &sc);
+    Sc = addr(bt, it.src.buf, it.src.blk, s, sr, sc);
+    lds = bt.ld[it.src.buf];
+  } else {                 // from the item's scratch slot
+    Sc = addr(bt, B_RS, (int)blockIdx.y + slot_base, s, 0, 0);
+    lds = bt.ld[B_RS];
+  }
   const int tm = (M + 63) / 64, tn = (N + 63) / 64;
   for (int t = blockIdx.x; t < tm * tn; t += gridDim.x) {
     const int a0 = (t % tm) * 64, b0 = (t / tm) * 64;

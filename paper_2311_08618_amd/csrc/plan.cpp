@@ -335,9 +335,30 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
       ch.b1 = (int)mp.tr2.items.size();
       ++h;
     };
+    // Both orientations of a parent pair are stored and (p,q) = (q,p)^T: the
+    // products run for q >= p only, and (p,q) with q < p is a transposed copy
+    // of the finished (q,p).
+    auto mirror_of = [&](int p, int q, bool is_near) {
+      const int dst = is_near ? pp.blk(p, q) : pp.fblk(p, q), src = is_near ? pp.blk(q, p) : pp.fblk(q, p);
+      if (src < 0) {
+        add_out(p, q, is_near);
+        return;
+      }
+      const int buf = is_near ? B_SN : B_FN;
+      CopyItem c{ref(buf, dst), dx(DK_PM, p), dx(DK_PM, q), -1};
+      c.src = ref(buf, src);
+      mp.mirror.push_back(c);
+    };
     for (int p = 0; p < Np; ++p) {
-      for (int q : T.near[l - 1][p]) add_out(p, q, true);
-      for (int k = pp.f_ptr[p]; k < pp.f_ptr[p + 1]; ++k) add_out(p, pp.f_idx[k], false);
+      for (int q : T.near[l - 1][p]) {
+        if (q >= p) add_out(p, q, true);
+        else mirror_of(p, q, true);
+      }
+      for (int k = pp.f_ptr[p]; k < pp.f_ptr[p + 1]; ++k) {
+        const int q = pp.f_idx[k];
+        if (q >= p) add_out(p, q, false);
+        else mirror_of(p, q, false);
+      }
     }
     mp.nhat = h;
   }

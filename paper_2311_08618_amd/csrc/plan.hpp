@@ -68,6 +68,7 @@ struct MergePlan {
   GList tr2;                   // TN: out[old, new] = E_p^T HAT[old, new] ; out[old, old] = E_p^T TMP
   std::vector<int> pr0;        // parent construction ranks
   std::vector<int> emat_dim;   // r0_c1 + r0_c2 per parent
+  std::vector<CopyItem> mirror;   // (p,q), q < p: the transpose of the finished (q,p), after all chunks
   int emax = 0;
 };
 
