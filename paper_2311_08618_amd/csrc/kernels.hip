@@ -462,7 +462,7 @@ __global__ void k_pchol_init(const int* __restrict__ clusters, BufTab bt, SizeTa
 // panels; columns of this panel are formed from G and the panel's own columns:
 // column t = (G[:, p] - V[:, t0:t] V[p, t0:t]^T) / sqrt(d_p), taken four rows
 // x eight columns of independent loads at a time.
-constexpr int PC_THREADS = 512;
+constexpr int PC_THREADS = 1024;
 
 __global__ __launch_bounds__(PC_THREADS) void k_pchol_panel(const int* __restrict__ clusters, BufTab bt, SizeTab sz,
                                                             double tau2, int* __restrict__ more) {
@@ -577,7 +577,7 @@ __global__ void k_pchol_finish(const int* __restrict__ clusters, BufTab bt, Size
   }
 }
 
-constexpr int HQ_THREADS = 256;
+constexpr int HQ_THREADS = 512;
 constexpr int HQ_LDS = 16384;   // doubles of LDS holding the panel (RT x width)
 
 // Panel width by the number of rows, so that the panel fits in LDS.
