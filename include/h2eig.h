@@ -100,6 +100,9 @@ h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern,
  *            H2_ENUMERIC for a shift whose factorization met an exactly singular
  *            or non-finite pivot (its nu is then -1).
  * Returns H2_ENUMERIC if any shift failed (the others are still valid).
+ * Every count obtained joins the handle's record cache of (sigma, nu) pairs,
+ * kept for the handle's lifetime (16 bytes per shift), from which h2_kth_eig
+ * narrows its brackets before factoring anything (Sec. 4.2).
  */
 h2_status h2_inertia(h2_matrix A, const double* sigma, int64_t nshift,
                      int64_t* nu, int32_t* status);
@@ -128,7 +131,10 @@ h2_status h2_inertia_f32(h2_matrix A, const double* sigma, int64_t nshift,
  *   bracket: optional output, 2*nk doubles (final [a_k, b_k]).
  * All active brackets contribute one shift each to a single batched
  * factorization per bisection step; inertia results are reused across the
- * requested indices (Sec. 4.2).
+ * requested indices and across calls through the record cache (Sec. 4.2).
+ * A split point whose factorization meets an exactly singular pivot block is
+ * moved inside its bracket (by 1/64 of the width, up to 8 times, then
+ * H2_ENUMERIC).  With h2_set_mixed, wide brackets use h2_inertia_f32.
  */
 h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol,
                      const double* ab, double* lambda, double* bracket);
