@@ -12,16 +12,20 @@ also be done in O(n)"):
 
   * rows of cluster i at the leaf level are its points; at a parent level they
     are the children's skeleton points, in child order.
-  * columns (the far field A_{l;i,+}): the points of every cluster in the
-    interaction list of i or of one of its ancestors.  A far cluster of the
-    same level with more than ``cap`` points contributes ``cap`` of them, one of
-    an ancestor's list ``cap_anc``, evenly strided in tree order (index
-    floor(k*|q|/c), k = 0..c-1).  Defaults: all points when n <= 16384, else
-    cap = 2*leaf and cap_anc = max(16, leaf//4).
+  * columns (the far field A_{l;i,+}): every point of every cluster in the
+    interaction list of i or of one of its ancestors, at every size.
   * pivoted QR on the rows of that block with freshly computed remaining
-    norms; the first maximum wins ties; stop when the largest remaining norm
-    is <= tau = eps * normA.  The pivots are the skeleton points s_i and
-    M ~= X_i M(s_i, :) with X_i(s_i, :) = I.
+    norms; the first maximum wins ties; stop when the Frobenius norm of the
+    whole remaining block is <= tau_i = tau * sqrt(|tau_i| / n), with
+    tau = eps * normA and |tau_i| the number of points of cluster i.  The
+    pivots are the skeleton points s_i and M ~= X_i M(s_i, :) with
+    X_i(s_i, :) = I; the residual M - X_i M(s_i, :) is that remaining block,
+    so its norm is at most tau_i: the criterion of Sec. 3.1 for the block row
+    of i at level l.  The budget tau_i shrinks with the cluster so that the
+    block rows of one level, which partition the rows of A, have residuals
+    whose squares sum to at most tau^2: the whole level then errs by at most
+    tau in the 2-norm, at every n (a fixed tau per block row lets the error
+    of a level grow like sqrt(2^l) * tau).
   * orthonormalisation: leaf X_i = U_i T_i (QR); parent
     blkdiag(T_c1, T_c2) X_p = E_p^S T_p.  Completed to square orthonormal
     matrices ordered [redundant | skeleton].
@@ -32,6 +36,8 @@ also be done in O(n)"):
     s = max(1, n // 16384); tau = eps * normA.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -45,17 +51,19 @@ def pivoted_rows_id(M: np.ndarray, tol: float):
     Returns (s, X) with s the selected row indices (pivot order) and X of shape
     (M.shape[0], len(s)) with X[s] = I.  Remaining norms are recomputed from
     scratch at every step (slow, but the pivot rule is exactly
-    "largest remaining row norm, first index on ties")."""
+    "largest remaining row norm, first index on ties").  The loop stops once
+    the Frobenius norm of the remaining block, which equals the Frobenius norm
+    of the residual M - X M[s], is <= tol."""
     m, ncol = M.shape
     A = np.array(M.T, dtype=np.float64, copy=True)    # ncol x m: columns = rows of M
     perm = np.arange(m)
     kmax = min(m, ncol)
     r = 0
     for k in range(kmax):
-        norms = np.sqrt(np.sum(A[k:, k:] * A[k:, k:], axis=0))
-        j = int(np.argmax(norms))
-        if not norms[j] > tol:
+        sq = np.sum(A[k:, k:] * A[k:, k:], axis=0)
+        if not math.sqrt(float(np.sum(sq))) > tol:
             break
+        j = int(np.argmax(sq))
         j += k
         if j != k:
             A[:, [k, j]] = A[:, [j, k]]
@@ -91,14 +99,11 @@ def complete_basis(Y: np.ndarray):
     return Q, Rc[:r, :r]
 
 
-def far_columns(tree: Tree, l: int, i: int, cap: int, cap_anc: int) -> np.ndarray:
+def far_columns(tree: Tree, l: int, i: int) -> np.ndarray:
+    """Every point of the far field of cluster i at level l (original indices)."""
     cols = []
     for (lv, q) in tree.far_field(l, i):
-        pts = tree.pts(lv, q)
-        c = cap if lv == l else cap_anc
-        if len(pts) > c:
-            pts = pts[(np.arange(c) * len(pts)) // c]
-        cols.append(pts)
+        cols.append(tree.pts(lv, q))
     if not cols:
         return np.zeros(0, dtype=np.int64)
     return np.concatenate(cols)
@@ -119,14 +124,10 @@ def estimate_norm(X: np.ndarray, kern: Kernel) -> float:
 class H2:
     """An H^2 matrix built from points + kernel (oracle's own construction)."""
 
-    def __init__(self, X, kern: Kernel, leaf: int, eta: float, eps: float, cap: int | None = None,
-                 cap_anc: int | None = None):
+    def __init__(self, X, kern: Kernel, leaf: int, eta: float, eps: float):
         self.tree = T = Tree(X, leaf, eta)
         self.X = T.X
         self.kern, self.eps = kern, float(eps)
-        exact = T.n <= 16384
-        self.cap = int(cap) if cap else (T.n if exact else 2 * int(leaf))
-        self.cap_anc = int(cap_anc) if cap_anc else (T.n if exact else max(16, int(leaf) // 4))
         self.normA = estimate_norm(self.X, kern)
         self.tau = self.eps * self.normA
         L = T.L
@@ -143,10 +144,10 @@ class H2:
                     rows = T.idx[L][i]
                 else:
                     rows = np.concatenate([self.skel[l + 1][2 * i], self.skel[l + 1][2 * i + 1]])
-                cols = far_columns(T, l, i, self.cap, self.cap_anc)
+                cols = far_columns(T, l, i)
                 if len(cols) and len(rows):
                     M = kern.block(self.X, rows, cols)
-                    piv, Xi = pivoted_rows_id(M, self.tau)
+                    piv, Xi = pivoted_rows_id(M, self.cluster_tol(l, i))
                 else:
                     piv, Xi = np.zeros(0, dtype=np.int64), np.zeros((len(rows), 0))
                 if l < L:
@@ -178,6 +179,10 @@ class H2:
             for j in T.near[L][i]:
                 Aij = kern.block(self.X, T.idx[L][i], T.idx[L][j])
                 self.B[(i, j)] = self.Q[L][i].T @ Aij @ self.Q[L][j]
+
+    def cluster_tol(self, l: int, i: int) -> float:
+        """Truncation budget of cluster i at level l: tau * sqrt(|cluster| / n)."""
+        return self.tau * math.sqrt(len(self.tree.pts(l, i)) / self.tree.n)
 
     # ------------------------------------------------------------------ checks
     def nested_basis(self, l: int, i: int) -> np.ndarray:

@@ -16,8 +16,11 @@ For every cluster i, in colour-major / index-minor order:
         the R_i rows of every fill-in product that landed in row i of a
         non-near block, one product per (eliminated neighbour, block), plus
         the R_i rows of the fill-in carried up from the level below.  A
-        rank-revealing (column-pivoted) QR of the concatenation, truncated at
-        remaining norm <= tau, gives t directions that join the skeleton: the
+        rank-revealing (column-pivoted) QR of the concatenation, truncated
+        once the Frobenius norm of the remaining part is <= tau_i =
+        tau * sqrt(|cluster i| / n) (the construction's budget, so that the
+        truncations of one level sum to at most tau in the 2-norm), gives t
+        directions that join the skeleton: the
         redundant coordinates are rotated by W = [Q_perp | Q_t] (Q_t an
         orthonormal basis of the kept directions) and the last t of them
         become skeleton coordinates.  The redundant rows of the
@@ -40,10 +43,13 @@ pairs is carried up.  The root is reached with no skeleton part left.
 
 Readings where the paper is silent are listed in the design notes: the
 concatenated products (per eliminated neighbour and block), the truncation
-rule (singular values > tau = eps*normA), inherited-far fill-in carried to the
+rule (remaining Frobenius norm <= tau * sqrt(|cluster| / n), tau = eps*normA),
+inherited-far fill-in carried to the
 parent level, and the embedding of the transfer matrix after rank growth.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -53,18 +59,19 @@ def rrqr_directions(X: np.ndarray, tol: float):
 
     Column-pivoted Householder QR of X^T: the pivots are coordinates of the
     redundant part, chosen by largest remaining norm (recomputed at every
-    step, first index on ties), stopping when the largest remaining norm is
-    <= tol.  With X^T P = Q R, X ~= P R^T Q^T, so the kept directions are
-    the first t columns of P R^T.  Returns (t, P R^T[:, :t])."""
+    step, first index on ties), stopping when the Frobenius norm of the whole
+    remaining block is <= tol.  With X^T P = Q R, X ~= P R^T Q^T, so the
+    kept directions are the first t columns of P R^T, and X minus its
+    projection on them has Frobenius norm <= tol.  Returns (t, P R^T[:, :t])."""
     A = np.array(X.T, dtype=np.float64, copy=True)     # ncol x R_i
     n, m = A.shape
     perm = np.arange(m)
     t = 0
     for k in range(min(n, m)):
-        nrm = np.sqrt(np.sum(A[k:, k:] * A[k:, k:], axis=0))
-        j = int(np.argmax(nrm))
-        if not nrm[j] > tol:
+        sq = np.sum(A[k:, k:] * A[k:, k:], axis=0)
+        if not math.sqrt(float(np.sum(sq))) > tol:
             break
+        j = int(np.argmax(sq))
         j += k
         if j != k:
             A[:, [k, j]] = A[:, [j, k]]
@@ -97,7 +104,7 @@ def _rotate(i, W, R_i, S, F, nbS, nbF):
 
 def inertia(H, sigma: float, stats: dict | None = None) -> int:
     """nu(A~ - sigma I) = #{lambda(A~) < sigma} by the generalized H^2-LDL."""
-    T, L, tau = H.tree, H.tree.L, H.tau
+    T, L = H.tree, H.tree.L
     m = list(H.m[L])
     r0 = list(H.r[L])
     R = [m[i] - r0[i] for i in range(1 << L)]
@@ -130,7 +137,7 @@ def inertia(H, sigma: float, stats: dict | None = None) -> int:
             if Ri > 0:
                 if pending[i]:
                     Xc = np.concatenate(pending[i], axis=1)
-                    t, At = rrqr_directions(Xc, tau)
+                    t, At = rrqr_directions(Xc, H.cluster_tol(l, i))
                     if t > 0:
                         Qc, _ = np.linalg.qr(At, mode="complete")
                         W = np.concatenate([Qc[:, t:], Qc[:, :t]], axis=1)

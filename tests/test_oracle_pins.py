@@ -27,7 +27,7 @@ from paper_2311_08618_amd import workloads as W
 
 
 def _tridiag_h2(n, leaf, eta):
-    return H2(W.line_points(n), Kernel(4, 2.0, 1.0), leaf, eta, 1e-12, cap=n)
+    return H2(W.line_points(n), Kernel(4, 2.0, 1.0), leaf, eta, 1e-12)
 
 
 def _shift_grid_near_eigs(lam, count=25, seed=3):
@@ -169,7 +169,7 @@ def test_paper_circle_accuracy():
     tol = 1e-8
     # eps_H2 is an absolute bound in the paper; tau = eps * normA, so scale eps
     eps = 1e-2 * tol / estimate_norm(X, k)
-    H = H2(X, k, 32, 1.0, eps, cap=n)
+    H = H2(X, k, 32, 1.0, eps)
     ev = np.linalg.eigvalsh(k.dense(X))
     ks = [1, n // 4, n // 2, n]
     lam = kth_eigs(H, ks, tol, ab=(0.0, 2048.0 * 2))
@@ -183,6 +183,89 @@ def test_gershgorin_contains_spectrum():
     lo, hi = gershgorin(X, k)
     ev = np.linalg.eigvalsh(k.dense(X))
     assert lo <= ev[0] and ev[-1] <= hi
+
+
+def _id_residual(M, s):
+    """Frobenius norm of M minus its projection on the rows s (the ID residual
+    once X is the least-squares interpolation)."""
+    if len(s) == 0:
+        return float(np.linalg.norm(M))
+    Q, _ = np.linalg.qr(M[s].T)
+    return float(np.linalg.norm(M - (M @ Q) @ Q.T))
+
+
+def test_row_id_stops_on_frobenius_residual():
+    """The ID's stop rule (Sec. 3.1 criterion, Frobenius reading): the residual
+    with the chosen rows is <= tol, with one row fewer it is > tol."""
+    rng = np.random.default_rng(7)
+    U, _ = np.linalg.qr(rng.standard_normal((60, 60)))
+    V, _ = np.linalg.qr(rng.standard_normal((400, 60)))
+    M = (U * np.logspace(0, -12, 60)) @ V.T
+    for tol in (1e-3, 1e-6, 1e-9):
+        s, X = pivoted_rows_id(M, tol)
+        assert np.linalg.norm(M - X @ M[s]) <= tol * (1 + 1e-6)
+        assert _id_residual(M, s[:-1]) > tol
+        # the residual of the returned ID equals that of the orthogonal projection
+        assert abs(np.linalg.norm(M - X @ M[s]) - _id_residual(M, s)) <= 1e-6 * tol
+
+
+def test_block_row_criterion_and_budget():
+    """Sec. 3.1: every leaf cluster's far-field block row is reproduced by its
+    shared basis within its budget tau_i = tau*sqrt(|i|/n), and the budgets of
+    a level sum (in squares) to tau^2."""
+    X = W.cube_points(1024, 3)
+    k = Kernel(0, 1e3)
+    H = H2(X, k, 64, 1.0, 1e-8)
+    T, L = H.tree, H.tree.L
+    from oracle.build import far_columns
+    for l in range(1, L + 1):
+        assert abs(sum(H.cluster_tol(l, i) ** 2 for i in range(1 << l)) - H.tau ** 2) <= 1e-9 * H.tau ** 2
+    for i in range(1 << L):
+        U = H.nested_basis(L, i)
+        M = k.block(H.X, T.pts(L, i), far_columns(T, L, i))
+        res = np.linalg.norm(M - U @ (U.T @ M))
+        assert res <= H.cluster_tol(L, i) * (1 + 1e-6)
+
+
+@pytest.mark.slow
+def test_construction_error_n8192():
+    """||A - A~||_2 <= 10*eps*normA at n = 8192, leaf 256 (the full-size leaf),
+    every far field whole (no sampling)."""
+    X = W.cube_points(8192, 0)
+    k = Kernel(0, 1e3)
+    H = H2(X, k, 256, 1.0, 1e-8)
+    E = k.dense(X)
+    E -= H.dense()
+    from scipy.sparse.linalg import eigsh
+    err = abs(eigsh(E, k=1, which="LM", return_eigenvectors=False, tol=1e-4)[0])
+    assert err <= 10 * H.eps * H.normA, err / (H.eps * H.normA)
+
+
+def test_mutation_sampled_far_field_is_caught(monkeypatch):
+    """Sampling the far fields (a few points per far cluster instead of all of
+    them) must break the construction bound ||A - A~||_2 <= 10*eps*normA."""
+    import oracle.build as OB
+    real = OB.far_columns
+
+    def sampled(tree, l, i):
+        cols = []
+        for (lv, q) in tree.far_field(l, i):
+            pts = tree.pts(lv, q)
+            c = 2 * tree.leaf if lv == l else max(16, tree.leaf // 4)
+            if len(pts) > c:
+                pts = pts[(np.arange(c) * len(pts)) // c]
+            cols.append(pts)
+        return np.concatenate(cols) if cols else real(tree, l, i)
+
+    monkeypatch.setattr(OB, "far_columns", sampled)
+    X = W.cube_points(4096, 0)
+    k = Kernel(0, 1e3)
+    H = OB.H2(X, k, 128, 1.0, 1e-8)
+    E = k.dense(X)
+    E -= H.dense()
+    from scipy.sparse.linalg import eigsh
+    err = abs(eigsh(E, k=1, which="LM", return_eigenvectors=False, tol=1e-3)[0])
+    assert err > 10 * H.eps * H.normA
 
 
 def test_row_id_reproduces_low_rank():
