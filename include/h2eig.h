@@ -58,13 +58,8 @@ typedef struct {
 
 /* Build options (pass NULL for defaults). */
 typedef struct {
-  int32_t sample_cap;        /* far-field columns taken from each cluster of the
-                                same-level interaction list in the basis
-                                construction; 0 = automatic (all points when
-                                n <= 16384, else 2*leaf)                        */
-  int32_t sample_cap_anc;    /* same, for clusters of an ancestor's interaction
-                                list; 0 = automatic (all points when
-                                n <= 16384, else max(16, leaf/4))               */
+  int32_t reserved0;         /* must be 0                                       */
+  int32_t reserved1;         /* must be 0                                       */
   int32_t max_shifts;        /* shifts factored together per launch; 0 = auto   */
   int32_t reserved[5];
 } h2_opts;
@@ -218,6 +213,23 @@ h2_status h2_set_stream(h2_matrix A, void* hip_stream);
 /* Tree permutation: perm[p] = original index of the p-th point in leaf order
  * (n int64, host output). */
 h2_status h2_tree_perm(h2_matrix A, int64_t* perm);
+
+/*
+ * Construction diagnostics (Sec. 3.1).
+ * h2_basis_ranks: r[i] = rank of the shared basis of cluster i at tree level
+ *   `level` (0 = root), i = 0 .. 2^level - 1 (host output).
+ * h2_matvec: y = A~ x with the built H^2 matrix (near blocks, nested bases,
+ *   couplings), evaluated on the host; x, y host arrays of n doubles in the
+ *   original point order.
+ * h2_kernel_matvec: y = A x with the exact kernel matrix (A_ii = diag), O(n^2)
+ *   kernel evaluations on the GPU; x, y as above.
+ * Together they measure the construction error ||A - A~|| at sizes where no
+ * dense matrix fits.  Errors: H2_EINVAL (NULL argument, level out of range),
+ * H2_EBUSY, H2_EDEVICE.
+ */
+h2_status h2_basis_ranks(h2_matrix A, int32_t level, int32_t* r);
+h2_status h2_matvec(h2_matrix A, const double* x, double* y);
+h2_status h2_kernel_matvec(h2_matrix A, const double* x, double* y);
 
 /*
  * Diagnostic profiling (not needed for results).  When enabled, every kernel

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libh2eig.so")
-SOURCES = ["kernels.hip", "engine.cpp", "plan.cpp", "host.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "construct.hip", "engine.cpp", "plan.cpp", "host.cpp", "server.cpp"]
 ARCH = os.environ.get("H2EIG_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "../../include/h2eig.h"
+#include "construct.hpp"
 #include "host.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -249,6 +250,7 @@ struct h2_matrix_s {
   int* d_prefix = nullptr;  // per-shift tile counts of the current GEMM launch (in the small arena)
   Profiler prof;
   int* d_more = nullptr;   // per-iteration "more panels needed" counters + colour maxima
+  std::vector<double*> d_tau2;   // per level: squared truncation budget tau^2 * |cluster| / n of every cluster
   int* h_more = nullptr;   // pinned host copy (4 ints)
 
   template <class T>
@@ -717,7 +719,6 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
     };
     gemm(PC_GRAM, GEMM_NT, A->dp<GItem>(dl.gram_init.items), dl.gram_init.n, A->dp<GTerm>(dl.gram_init.terms), cap,
          cap);
-    const double tau2 = A->tau * A->tau;
     // scratch slots of the out-of-place products: about 2 GB per shift at most
     int max_items = 1;
     for (const DevColour& dc : dl.colours)
@@ -748,7 +749,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
         const int nit = std::min(MORE_SLOTS, cap / PCHOL_NB + 2);
         HIPCHK(hipMemsetAsync(A->d_more, 0, nit * sizeof(int), st));
         for (int it = 0; it < nit; ++it) {
-          run(PC_PCHOL, [&] { launch_pchol_panel(cl, dc.ncl, bt, sz, tau2, A->d_more + it, cap, S, st); });
+          run(PC_PCHOL, [&] { launch_pchol_panel(cl, dc.ncl, bt, sz, A->d_tau2[l], A->d_more + it, cap, S, st); });
           gl(PC_PCHOL_UPD, GEMM_NT, dc.pc_upd);
           if (it % 4 == 3 || it == nit - 1) {
             read_back(A, A->d_more + it, 1, st);
@@ -996,6 +997,7 @@ h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern,
   if (!out) return fail(H2_EINVAL, "out is NULL");
   *out = nullptr;
   if (!points || n < 1) return fail(H2_EINVAL, "n must be >= 1 and points non-NULL");
+  if (opts && (opts->reserved0 != 0 || opts->reserved1 != 0)) return fail(H2_EINVAL, "reserved options must be 0");
   if (dim < 1 || dim > 3) return fail(H2_EINVAL, "dim must be 1, 2 or 3");
   if (leaf < 2 && n > 1) return fail(H2_EINVAL, "leaf must be >= 2");
   if (!(eta > 0.0) || !(eps > 0.0)) return fail(H2_EINVAL, "eta and eps must be > 0");
@@ -1025,16 +1027,21 @@ h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern,
     BuildParams P;
     P.kern = A->kern;
     P.eps = eps;
-    P.sample_cap = opts ? opts->sample_cap : 0;
-    P.sample_cap_anc = opts ? opts->sample_cap_anc : 0;
     if (opts && opts->max_shifts > 0) A->max_shifts = opts->max_shifts;
-    build_basis(A->T, P, A->tau, A->B);
+    build_basis(A->T, P, A->tau, A->B, A->stream);
     A->plan = build_plan(A->T, A->B);
     int L = A->T.L;
     A->leafcap = 0;
     for (int i = 0; i < (1 << L); ++i) A->leafcap = std::max<int>(A->leafcap, (int)A->T.size[L][i]);
     A->leafcap = round_cap(A->leafcap);
     HIPCHK(hipMalloc(&A->d_more, (MORE_SLOTS + 4) * sizeof(int)));
+    A->d_tau2.assign(L + 1, nullptr);
+    for (int l = 0; l <= L; ++l) {
+      std::vector<double> t2(1 << l);
+      for (int i = 0; i < (1 << l); ++i) t2[i] = A->tau * A->tau * (double)A->T.size[l][i] / (double)A->T.n;
+      HIPCHK(hipMalloc(&A->d_tau2[l], t2.size() * sizeof(double)));
+      HIPCHK(hipMemcpy(A->d_tau2[l], t2.data(), t2.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     HIPCHK(hipHostMalloc(&A->h_more, 4 * sizeof(int)));
     upload_plan(A);
     upload_resident(A);
@@ -1052,6 +1059,9 @@ h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern,
   } catch (std::bad_alloc&) {
     h2_free(A);
     return fail(H2_ENOMEM, "host allocation failed");
+  } catch (std::runtime_error& e) {
+    h2_free(A);
+    return fail(H2_EDEVICE, e.what());
   }
   const Tree& T = A->T;
   A->st.n = T.n;
@@ -1306,6 +1316,41 @@ h2_status h2_tree_perm(h2_matrix A, int64_t* perm) {
   return H2_OK;
 }
 
+h2_status h2_basis_ranks(h2_matrix A, int32_t level, int32_t* r) {
+  if (!A || !r) return fail(H2_EINVAL, "NULL argument");
+  if (level < 0 || level > A->T.L) return fail(H2_EINVAL, "level out of range");
+  for (int i = 0; i < (1 << level); ++i) r[i] = A->B.r[level][i];
+  return H2_OK;
+}
+
+h2_status h2_matvec(h2_matrix A, const double* x, double* y) {
+  if (!A || !x || !y) return fail(H2_EINVAL, "NULL argument");
+  Busy b(A);
+  if (!b.ok) return fail(H2_EBUSY, "handle in use by another thread");
+  try {
+    h2_matvec_host(A->T, A->kern, A->B, x, y);
+  } catch (std::bad_alloc&) {
+    return fail(H2_ENOMEM, "host allocation failed");
+  }
+  return H2_OK;
+}
+
+h2_status h2_kernel_matvec(h2_matrix A, const double* x, double* y) {
+  if (!A || !x || !y) return fail(H2_EINVAL, "NULL argument");
+  Busy b(A);
+  if (!b.ok) return fail(H2_EBUSY, "handle in use by another thread");
+  try {
+    HIPCHK(hipSetDevice(A->device));
+    kernel_matvec_gpu(A->T.X.data(), A->T.n, A->T.dim, A->kern.kind, A->kern.diag, A->kern.p0, A->kern.p1, x, y,
+                      A->stream);
+  } catch (HipError& e) {
+    return fail(H2_EDEVICE, e.where + ": " + hipGetErrorString(e.e));
+  } catch (std::runtime_error& e) {
+    return fail(H2_EDEVICE, e.what());
+  }
+  return H2_OK;
+}
+
 h2_status h2_profile_enable(h2_matrix A, int32_t enable) {
   if (!A) return fail(H2_EINVAL, "NULL handle");
   try {
@@ -1361,6 +1406,8 @@ void h2_free(h2_matrix A) {
   if (A->d_plan) (void)hipFree(A->d_plan);
   A->prof.release();
   if (A->d_more) (void)hipFree(A->d_more);
+  for (double* p : A->d_tau2)
+    if (p) (void)hipFree(p);
   if (A->h_more) (void)hipHostFree(A->h_more);
   if (A->own_stream) (void)hipStreamDestroy(A->own_stream);
   delete A;

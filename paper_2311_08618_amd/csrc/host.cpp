@@ -1,7 +1,8 @@
 // Host construction of the H^2 matrix (Sec. 3.1 of the paper): cluster tree,
 // strong-admissibility block tree, colouring of the near graph, nested
 // orthonormal shared bases and transfer matrices by an interpolative
-// decomposition (column-pivoted QR) of sampled far fields, and couplings.
+// decomposition of each cluster's whole far field (the rank-revealing step
+// runs on the GPU, construct.hip), and couplings.
 //
 // Readings (the paper leaves these open):
 //  * split every cluster at the median of its longest bounding-box axis
@@ -10,18 +11,19 @@
 //  * admissible iff i != j, |c_i - c_j| > 0 and eta*|c_i - c_j| >= rho_i + rho_j
 //    (bounding-box centres and half diagonals);
 //  * greedy colouring of each level's near graph in ascending index;
-//  * far field of cluster i at level l = points of every cluster in the
-//    interaction list of i (at most `cap` of them per cluster) or of an
-//    ancestor (at most `cap_anc`); a far cluster with more points than its cap
-//    contributes the points at positions floor(k*size/cap) in tree order.
-//    Defaults: every point when n <= 16384, else cap = 2*leaf and
-//    cap_anc = max(16, leaf/4);
+//  * far field of cluster i at level l = every point of every cluster in the
+//    interaction list of i or of one of its ancestors;
 //  * rank-revealing step: column-pivoted QR of the far-field block's
-//    transpose, pivots by largest remaining norm (recomputed every step, first
-//    index wins ties), stop when it is <= tau = eps*normA;
+//    transpose, pivots by largest remaining norm, stop when the Frobenius norm
+//    of the remaining block is <= tau_i = tau * sqrt(|cluster i| / n),
+//    tau = eps*normA (so the interpolation error of the block row is at most
+//    tau_i, the criterion of Sec. 3.1, and the block rows of one level err by
+//    at most tau together);
 //  * orthonormal completion ordered [redundant | skeleton]; couplings
 //    C_ij = T_i A(s_i, s_j) T_j^T.
 #include "host.hpp"
+
+#include "construct.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -198,58 +200,6 @@ void build_tree(Tree& T, const double* pts, int64_t n, int dim, int leaf, double
 }
 
 // ---------------------------------------------------------------- dense helpers
-// Column-pivoted Householder QR on A (nr x nc, col-major, lda = nr), in place.
-// Pivot = largest remaining column norm (fresh), first index on ties; stops when
-// it is <= tol.  Returns the rank; perm holds the column order; A holds R in its
-// upper triangle (first `rank` rows).
-static int cpqr(double* A, int64_t nr, int nc, double tol, std::vector<int>& perm) {
-  perm.resize(nc);
-  std::iota(perm.begin(), perm.end(), 0);
-  int kmax = (int)std::min<int64_t>(nr, nc);
-  std::vector<double> nrm(nc), v(nr), w(nc);
-  int rank = 0;
-  for (int k = 0; k < kmax; ++k) {
-    int jbest = -1;
-    double best = -1.0;
-    for (int j = k; j < nc; ++j) {
-      const double* c = A + (int64_t)j * nr;
-      double s = 0.0;
-      for (int64_t i = k; i < nr; ++i) s += c[i] * c[i];
-      double q = std::sqrt(s);
-      if (q > best) { best = q; jbest = j; }
-    }
-    if (!(best > tol)) break;
-    if (jbest != k) {
-      std::swap_ranges(A + (int64_t)k * nr, A + (int64_t)(k + 1) * nr, A + (int64_t)jbest * nr);
-      std::swap(perm[k], perm[jbest]);
-    }
-    double* x = A + (int64_t)k * nr;
-    double xn = 0.0;
-    for (int64_t i = k; i < nr; ++i) xn += x[i] * x[i];
-    xn = std::sqrt(xn);
-    double alpha = -std::copysign(xn, x[k] != 0.0 ? x[k] : 1.0);
-    for (int64_t i = k; i < nr; ++i) v[i] = x[i];
-    v[k] -= alpha;
-    double vn = 0.0;
-    for (int64_t i = k; i < nr; ++i) vn += v[i] * v[i];
-    if (vn > 0.0) {
-      for (int j = k; j < nc; ++j) {
-        const double* c = A + (int64_t)j * nr;
-        double s = 0.0;
-        for (int64_t i = k; i < nr; ++i) s += v[i] * c[i];
-        w[j] = s * (2.0 / vn);
-      }
-      for (int j = k; j < nc; ++j) {
-        double* c = A + (int64_t)j * nr;
-        double f = w[j];
-        for (int64_t i = k; i < nr; ++i) c[i] -= v[i] * f;
-      }
-    }
-    rank = k + 1;
-  }
-  return rank;
-}
-
 // Householder QR of Y (m x r, col-major), completed to a square orthonormal Q
 // (m x m) ordered [redundant | skeleton]; T = upper r x r factor with
 // Y = Q[:, m-r:] T.
@@ -307,23 +257,23 @@ static std::vector<int64_t> cluster_points(const Tree& T, int l, int i) {
   return v;
 }
 
-static std::vector<int64_t> far_columns(const Tree& T, int l, int i, int cap, int cap_anc) {
-  std::vector<int64_t> cols;
+// Far field of cluster i at level l as ranges of point positions in tree order:
+// the clusters of the interaction lists of i and of its ancestors, sorted, with
+// touching ranges merged.
+static std::vector<std::pair<int64_t, int64_t>> far_ranges(const Tree& T, int l, int i) {
+  std::vector<std::pair<int64_t, int64_t>> r;
   int a = i;
   for (int lv = l; lv >= 1; --lv) {
-    const int c = lv == l ? cap : cap_anc;
-    for (int q : T.far[lv][a]) {
-      int64_t s0 = T.start[lv][q], sz = T.size[lv][q];
-      const int cap = c;
-      if (sz > cap) {
-        for (int k = 0; k < cap; ++k) cols.push_back(T.perm[s0 + ((int64_t)k * sz) / cap]);
-      } else {
-        for (int64_t k = 0; k < sz; ++k) cols.push_back(T.perm[s0 + k]);
-      }
-    }
+    for (int q : T.far[lv][a]) r.push_back({T.start[lv][q], T.start[lv][q] + T.size[lv][q]});
     a >>= 1;
   }
-  return cols;
+  std::sort(r.begin(), r.end());
+  std::vector<std::pair<int64_t, int64_t>> out;
+  for (auto& x : r) {
+    if (!out.empty() && x.first <= out.back().second) out.back().second = std::max(out.back().second, x.second);
+    else out.push_back(x);
+  }
+  return out;
 }
 
 double estimate_norm(const Tree& T, const KernelSpec& k) {
@@ -342,12 +292,8 @@ double estimate_norm(const Tree& T, const KernelSpec& k) {
   return std::max(tot / (double)nrows, std::fabs(k.diag));
 }
 
-void build_basis(const Tree& T, const BuildParams& P, double tau, Basis& B) {
+void build_basis(const Tree& T, const BuildParams& P, double tau, Basis& B, hipStream_t st) {
   int L = T.L;
-  const bool exact = T.n <= 16384;
-  int cap = P.sample_cap > 0 ? P.sample_cap : (exact ? (int)std::min<int64_t>(T.n, 1 << 30) : 2 * T.leaf);
-  int cap_anc = P.sample_cap_anc > 0 ? P.sample_cap_anc
-                                     : (exact ? (int)std::min<int64_t>(T.n, 1 << 30) : std::max(16, T.leaf / 4));
   int nth = P.nthreads > 0 ? P.nthreads : default_threads();
   B.m.assign(L + 1, {});
   B.r.assign(L + 1, {});
@@ -355,6 +301,12 @@ void build_basis(const Tree& T, const BuildParams& P, double tau, Basis& B) {
   B.Tf.assign(L + 1, {});
   B.Q.assign(L + 1, {});
   B.C.assign(L + 1, {});
+  FarIdPoints FP;
+  far_points_upload(FP, T.X.data(), T.perm.data(), T.n, T.dim, st);
+  struct Guard {
+    FarIdPoints& p;
+    ~Guard() { far_points_free(p); }
+  } guard{FP};
   for (int l = L; l >= 0; --l) {
     int N = 1 << l;
     B.m[l].assign(N, 0);
@@ -362,39 +314,61 @@ void build_basis(const Tree& T, const BuildParams& P, double tau, Basis& B) {
     B.skel[l].assign(N, {});
     B.Tf[l].assign(N, {});
     B.Q[l].assign(N, {});
-    parallel_for(N, nth, [&](int64_t ii) {
-      int i = (int)ii;
-      std::vector<int64_t> rows;
+    // rows of every cluster: its points at the leaf level, its children's
+    // skeleton points above
+    std::vector<std::vector<int64_t>> rows_of(N);
+    FarIdLevel lev;
+    lev.N = N;
+    lev.m.assign(N, 0);
+    lev.tau2.assign(N, 0.0);
+    lev.fptr.assign(N + 1, 0);
+    for (int i = 0; i < N; ++i) {
+      auto& rows = rows_of[i];
       if (l == L) rows = T.idx[L][i];
       else {
         rows = B.skel[l + 1][2 * i];
         rows.insert(rows.end(), B.skel[l + 1][2 * i + 1].begin(), B.skel[l + 1][2 * i + 1].end());
       }
+      lev.m[i] = (int)rows.size();
+      lev.tau2[i] = tau * tau * (double)T.size[l][i] / (double)T.n;
+      for (int64_t v : rows) {
+        lev.rx.push_back(T.X[v * T.dim]);
+        lev.ry.push_back(T.dim > 1 ? T.X[v * T.dim + 1] : 0.0);
+        lev.rz.push_back(T.dim > 2 ? T.X[v * T.dim + 2] : 0.0);
+      }
+      for (auto& fr : far_ranges(T, l, i)) {
+        lev.fr0.push_back(fr.first);
+        lev.fr1.push_back(fr.second);
+      }
+      lev.fptr[i + 1] = (int64_t)lev.fr0.size();
+    }
+    FarIdResult ids;
+    far_field_ids(FP, P.kern.kind, P.kern.p0, P.kern.p1, lev, ids, st);
+    parallel_for(N, nth, [&](int64_t ii) {
+      int i = (int)ii;
+      const std::vector<int64_t>& rows = rows_of[i];
       int m = (int)rows.size();
-      std::vector<int64_t> cols = far_columns(T, l, i, cap, cap_anc);
-      int64_t nc = (int64_t)cols.size();
-      int r = 0;
-      std::vector<int> perm;
-      std::vector<double> X;   // m x r interpolation matrix
-      if (nc > 0 && m > 0) {
-        // At = M^T: nc x m col-major; column j = kernel(rows[j], cols[:])
-        std::vector<double> At((size_t)nc * m);
-        for (int j = 0; j < m; ++j)
-          for (int64_t c = 0; c < nc; ++c)
-            At[c + (size_t)j * nc] = rows[j] == cols[c] ? P.kern.diag : kernel_f(P.kern, dist(T, rows[j], cols[c]));
-        r = cpqr(At.data(), nc, m, tau, perm);
-        X.assign((size_t)m * r, 0.0);
-        // X[perm[:r]] = I ; X[perm[r:]] = (R11^{-1} R12)^T
-        for (int a = 0; a < r; ++a) X[perm[a] + (size_t)a * m] = 1.0;
-        for (int j = r; j < m; ++j) {
-          // solve R11 z = R12[:, j-r]  (back substitution), R at At (ld nc)
-          std::vector<double> z(r);
+      int r = ids.r[i];
+      const std::vector<int>& piv = ids.piv[i];
+      const std::vector<double>& Lf = ids.Lf[i];   // m x r: L(j, a) = R(a, j)
+      std::vector<double> X((size_t)m * r, 0.0);   // m x r interpolation matrix, X[piv] = I
+      if (r > 0) {
+        // R11(a, b) = L(piv[b], a) (upper triangular); for a row j not chosen,
+        // X(j, :) solves R11 z = R(:, j)
+        std::vector<char> chosen(m, 0);
+        for (int b = 0; b < r; ++b) {
+          chosen[piv[b]] = 1;
+          X[piv[b] + (size_t)b * m] = 1.0;
+        }
+        std::vector<double> z(r);
+        for (int j = 0; j < m; ++j) {
+          if (chosen[j]) continue;
           for (int a = r - 1; a >= 0; --a) {
-            double s = At[a + (size_t)j * nc];
-            for (int b = a + 1; b < r; ++b) s -= At[a + (size_t)b * nc] * z[b];
-            z[a] = s / At[a + (size_t)a * nc];
+            double s = Lf[j + (size_t)a * m];
+            for (int b = a + 1; b < r; ++b) s -= Lf[piv[b] + (size_t)a * m] * z[b];
+            z[a] = s / Lf[piv[a] + (size_t)a * m];
           }
-          for (int a = 0; a < r; ++a) X[perm[j] + (size_t)a * m] = z[a];
+          for (int a = 0; a < r; ++a) X[j + (size_t)a * m] = z[a];
         }
       }
       std::vector<double> Y;
@@ -423,7 +397,7 @@ void build_basis(const Tree& T, const BuildParams& P, double tau, Basis& B) {
       B.m[l][i] = m;
       B.r[l][i] = r;
       std::vector<int64_t> sk(r);
-      for (int a = 0; a < r; ++a) sk[a] = rows[perm[a]];
+      for (int a = 0; a < r; ++a) sk[a] = rows[piv[a]];
       B.skel[l][i] = sk;
       B.Tf[l][i] = Tm;
       B.Q[l][i] = Q;
@@ -462,6 +436,111 @@ void build_basis(const Tree& T, const BuildParams& P, double tau, Basis& B) {
       }
     });
   }
+}
+
+}  // namespace h2
+
+namespace h2 {
+
+// y = A~ x for the built H^2 matrix (original point order).  Near blocks of the
+// leaf level are kernel blocks, evaluated on the fly; every admissible pair
+// (i, j) of level l contributes U_i C_ij U_j^T x(tau_j), with the nested bases
+// applied by an upward pass (x^_i = U_i^T x) and a downward pass (Sec. 3.1,
+// Eq. notation-example).
+void h2_matvec_host(const Tree& T, const KernelSpec& kern, const Basis& B, const double* x, double* y) {
+  const int L = T.L;
+  const int nth = default_threads();
+  const int64_t n = T.n;
+  std::vector<double> xp(n), yp(n, 0.0);   // leaf order
+  for (int64_t p = 0; p < n; ++p) xp[p] = x[T.perm[p]];
+  // upward pass: xs[l][i] = skeleton coordinates of x on cluster i
+  std::vector<std::vector<std::vector<double>>> xs(L + 1), ys(L + 1);
+  for (int l = L; l >= 1; --l) {
+    const int N = 1 << l;
+    xs[l].assign(N, {});
+    ys[l].assign(N, {});
+    parallel_for(N, nth, [&](int64_t ii) {
+      const int i = (int)ii;
+      const int m = B.m[l][i], r = B.r[l][i];
+      const std::vector<double>& Q = B.Q[l][i];
+      std::vector<double> in(m);
+      if (l == L) {
+        for (int a = 0; a < m; ++a) in[a] = xp[T.start[L][i] + a];
+      } else {
+        const auto& a1 = xs[l + 1][2 * i];
+        const auto& a2 = xs[l + 1][2 * i + 1];
+        std::copy(a1.begin(), a1.end(), in.begin());
+        std::copy(a2.begin(), a2.end(), in.begin() + a1.size());
+      }
+      std::vector<double> out(r, 0.0);
+      for (int c = 0; c < r; ++c) {
+        const double* q = Q.data() + (size_t)(m - r + c) * m;
+        double s = 0.0;
+        for (int a = 0; a < m; ++a) s += q[a] * in[a];
+        out[c] = s;
+      }
+      xs[l][i] = std::move(out);
+      ys[l][i].assign(r, 0.0);
+    });
+  }
+  // couplings
+  for (int l = 1; l <= L; ++l) {
+    const int N = 1 << l;
+    parallel_for(N, nth, [&](int64_t ii) {
+      const int i = (int)ii;
+      const int ri = B.r[l][i];
+      for (const auto& jc : B.C[l][i]) {
+        const int j = jc.first, rj = B.r[l][j];
+        const std::vector<double>& C = jc.second;
+        for (int b = 0; b < rj; ++b) {
+          const double v = xs[l][j][b];
+          for (int a = 0; a < ri; ++a) ys[l][i][a] += C[a + (size_t)b * ri] * v;
+        }
+      }
+    });
+  }
+  // downward pass
+  for (int l = 1; l <= L; ++l) {
+    const int N = 1 << l;
+    parallel_for(N, nth, [&](int64_t ii) {
+      const int i = (int)ii;
+      const int m = B.m[l][i], r = B.r[l][i];
+      const std::vector<double>& Q = B.Q[l][i];
+      std::vector<double> out(m, 0.0);
+      for (int c = 0; c < r; ++c) {
+        const double* q = Q.data() + (size_t)(m - r + c) * m;
+        const double v = ys[l][i][c];
+        for (int a = 0; a < m; ++a) out[a] += q[a] * v;
+      }
+      if (l == L) {
+        for (int a = 0; a < m; ++a) yp[T.start[L][i] + a] += out[a];
+      } else {
+        auto& c1 = ys[l + 1][2 * i];
+        auto& c2 = ys[l + 1][2 * i + 1];
+        for (size_t a = 0; a < c1.size(); ++a) c1[a] += out[a];
+        for (size_t a = 0; a < c2.size(); ++a) c2[a] += out[c1.size() + a];
+      }
+    });
+  }
+  // near field (leaf level, exact kernel blocks)
+  const int N = 1 << L;
+  parallel_for(N, nth, [&](int64_t ii) {
+    const int i = (int)ii;
+    const int64_t si = T.start[L][i], mi = T.size[L][i];
+    for (int j : T.near[L][i]) {
+      const int64_t sj = T.start[L][j], mj = T.size[L][j];
+      for (int64_t a = 0; a < mi; ++a) {
+        const int64_t pa = T.perm[si + a];
+        double s = 0.0;
+        for (int64_t b = 0; b < mj; ++b) {
+          const int64_t pb = T.perm[sj + b];
+          s += (pa == pb ? kern.diag : kernel_f(kern, dist(T, pa, pb))) * xp[sj + b];
+        }
+        yp[si + a] += s;
+      }
+    }
+  });
+  for (int64_t p = 0; p < n; ++p) y[T.perm[p]] = yp[p];
 }
 
 }  // namespace h2

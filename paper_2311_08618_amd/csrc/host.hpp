@@ -1,6 +1,8 @@
 // Host-side structures of the H^2 matrix: cluster tree, block tree, colouring,
 // nested orthonormal bases, transfer matrices and couplings.
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <atomic>
 #include <cstdint>
 #include <functional>
@@ -54,13 +56,11 @@ struct Basis {
 struct BuildParams {
   KernelSpec kern;
   double eps = 1e-8;
-  int sample_cap = 0;
-  int sample_cap_anc = 0;
   int nthreads = 0;
 };
 
-// Computes normA (mean sampled row sum / |diag|), the bases and the couplings.
-void build_basis(const Tree& T, const BuildParams& P, double tau, Basis& B);
+// The nested bases (far-field IDs on the GPU, on stream st) and the couplings.
+void build_basis(const Tree& T, const BuildParams& P, double tau, Basis& B, hipStream_t st);
 double estimate_norm(const Tree& T, const KernelSpec& k);
 
 // small dense helpers (column-major)
@@ -68,6 +68,10 @@ void kernel_block(const Tree& T, const KernelSpec& k, const int64_t* rows, int n
                   const int64_t* cols, int nc, double* out, int ldo);
 
 int default_threads();
+
+// y = A~ x with the built H^2 matrix, on the host (a diagnostic of the
+// construction; x, y in original point order).
+void h2_matvec_host(const Tree& T, const KernelSpec& kern, const Basis& B, const double* x, double* y);
 
 // Dynamic parallel loop over [0, n) on nthreads std::threads.
 inline void parallel_for(int64_t n, int nthreads, const std::function<void(int64_t)>& fn) {

@@ -465,13 +465,15 @@ __global__ void k_pchol_init(const int* __restrict__ clusters, BufTab bt, SizeTa
 constexpr int PC_THREADS = 1024;
 
 __global__ __launch_bounds__(PC_THREADS) void k_pchol_panel(const int* __restrict__ clusters, BufTab bt, SizeTab sz,
-                                                            double tau2, int* __restrict__ more) {
+                                                            const double* __restrict__ tau2c, int* __restrict__ more) {
   extern __shared__ double sh[];
   __shared__ double vp[PC_NB];               // V[p, t0 + l], zero beyond the panel's columns
   __shared__ double redv[PC_THREADS / 64];
+  __shared__ double reds[PC_THREADS / 64];
   __shared__ int redi[PC_THREADS / 64];
   const int s = blockIdx.z;
   const int i = clusters[blockIdx.y];
+  const double tau2 = tau2c[i];
   const int N = sz.N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (sz.a1[s * N + i] == 0) {                // finished: no new columns for the update
@@ -491,23 +493,31 @@ __global__ __launch_bounds__(PC_THREADS) void k_pchol_panel(const int* __restric
   int t = t0;
   bool stop = false;
   for (int j = 0; j < PC_NB && t < R; ++j) {
-    // pivot: largest remaining diagonal, first index on ties
-    double bv = -INFINITY;
+    // pivot: largest remaining diagonal, first index on ties; stop once the
+    // remaining diagonal (the squared Frobenius norm of the part of the
+    // fill-in not yet spanned) sums to <= tau2
+    double bv = -INFINITY, sum = 0.0;
     int bi = R;
-    for (int a = tid; a < R; a += PC_THREADS)
-      if (d[a] > bv) { bv = d[a]; bi = a; }
+    for (int a = tid; a < R; a += PC_THREADS) {
+      const double v = d[a];
+      if (v != -INFINITY) sum += v;
+      if (v > bv) { bv = v; bi = a; }
+    }
     for (int off = 32; off > 0; off >>= 1) {
       const double ov = __shfl_xor(bv, off, 64);
       const int oi = __shfl_xor(bi, off, 64);
+      sum += __shfl_xor(sum, off, 64);
       if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
     }
-    if (lane == 0) { redv[wave] = bv; redi[wave] = bi; }
+    if (lane == 0) { redv[wave] = bv; redi[wave] = bi; reds[wave] = sum; }
     __syncthreads();
-    double dmax = redv[0];
+    double dmax = redv[0], rem = reds[0];
     int p = redi[0];
-    for (int w2 = 1; w2 < PC_THREADS / 64; ++w2)
+    for (int w2 = 1; w2 < PC_THREADS / 64; ++w2) {
+      rem += reds[w2];
       if (redv[w2] > dmax || (redv[w2] == dmax && redi[w2] < p)) { dmax = redv[w2]; p = redi[w2]; }
-    if (!(dmax > tau2)) {
+    }
+    if (!(rem > tau2) || !(dmax > 0.0)) {
       stop = true;
       break;
     }
@@ -1562,11 +1572,11 @@ void launch_pchol_init(const int* clusters, int n, const BufTab& bt, const SizeT
   hipLaunchKernelGGL(k_pchol_init, dim3(1, n, nshift), dim3(256), 0, st, clusters, bt, sz);
 }
 
-void launch_pchol_panel(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, double tau2, int* more, int cap,
-                        int nshift, hipStream_t st) {
+void launch_pchol_panel(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, const double* tau2c, int* more,
+                        int cap, int nshift, hipStream_t st) {
   if (n <= 0) return;
   size_t shmem = (size_t)cap * sizeof(double);
-  hipLaunchKernelGGL(k_pchol_panel, dim3(1, n, nshift), dim3(PC_THREADS), shmem, st, clusters, bt, sz, tau2, more);
+  hipLaunchKernelGGL(k_pchol_panel, dim3(1, n, nshift), dim3(PC_THREADS), shmem, st, clusters, bt, sz, tau2c, more);
 }
 
 void launch_pchol_finish(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st) {

@@ -26,8 +26,9 @@ void launch_copyback_t(const CopyItem* items, int n, const BufTab& bt, const Siz
 void launch_matsum(const SumItem* items, int nitems, const int* src, const BufTab& bt, const SizeTab& sz, int cap,
                    int nshift, hipStream_t st);
 void launch_pchol_init(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st);
-void launch_pchol_panel(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, double tau2, int* more, int cap,
-                        int nshift, hipStream_t st);
+// tau2c: squared truncation budget of every cluster of the level
+void launch_pchol_panel(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, const double* tau2c, int* more,
+                        int cap, int nshift, hipStream_t st);
 void launch_pchol_finish(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int nshift, hipStream_t st);
 void launch_hqr_panel(const int* clusters, int n, const BufTab& bt, const SizeTab& sz, int it, int* more, int nshift,
                       hipStream_t st);

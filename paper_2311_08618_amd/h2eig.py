@@ -32,7 +32,7 @@ class _Kernel(C.Structure):
 
 
 class _Opts(C.Structure):
-    _fields_ = [("sample_cap", C.c_int32), ("sample_cap_anc", C.c_int32), ("max_shifts", C.c_int32),
+    _fields_ = [("reserved0", C.c_int32), ("reserved1", C.c_int32), ("max_shifts", C.c_int32),
                 ("reserved", C.c_int32 * 5)]
 
 
@@ -65,6 +65,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.h2_set_stream.argtypes = [C.c_void_p, C.c_void_p]
     lib.h2_tree_perm.restype = C.c_int
     lib.h2_tree_perm.argtypes = [C.c_void_p, P(C.c_int64)]
+    lib.h2_basis_ranks.restype = C.c_int
+    lib.h2_basis_ranks.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32)]
+    lib.h2_matvec.restype = C.c_int
+    lib.h2_matvec.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
+    lib.h2_kernel_matvec.restype = C.c_int
+    lib.h2_kernel_matvec.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
     lib.h2_profile_enable.restype = C.c_int
     lib.h2_profile_enable.argtypes = [C.c_void_p, C.c_int32]
     lib.h2_profile_classes.restype = C.c_int32
@@ -115,6 +121,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
 _lib = load_library()
 
 EXPORTED = ["h2_build", "h2_inertia", "h2_inertia_f32", "h2_set_mixed", "h2_kth_eig", "h2_norm", "h2_stats", "h2_set_stream", "h2_tree_perm",
+            "h2_basis_ranks", "h2_matvec", "h2_kernel_matvec",
             "h2_profile_enable", "h2_profile_classes", "h2_profile_class_name", "h2_profile_read",
             "h2_profile_level_ms", "h2_interval", "h2_capacity", "h2_set_max_shifts", "h2_level_dims",
             "h2_set_gemm_tuning", "h2_get_gemm_tuning", "h2_free", "h2_last_error",
@@ -161,13 +168,12 @@ class H2Matrix:
     """A built H^2 matrix resident on the GPU (h2_build)."""
 
     def __init__(self, points, kind: int, diag: float, leaf: int, eta: float, eps: float,
-                 p0: float = 0.0, p1: float = 0.0, sample_cap: int = 0, sample_cap_anc: int = 0,
-                 max_shifts: int = 0):
+                 p0: float = 0.0, p1: float = 0.0, max_shifts: int = 0):
         X = np.ascontiguousarray(points, dtype=np.float64)
         if X.ndim == 1:
             X = X.reshape(-1, 1)
         n, dim = X.shape
-        opts = _Opts(int(sample_cap), int(sample_cap_anc), int(max_shifts), (C.c_int32 * 5)())
+        opts = _Opts(0, 0, int(max_shifts), (C.c_int32 * 5)())
         h = C.c_void_p()
         _check(_lib.h2_build(_dptr(X), n, dim, _Kernel(int(kind), float(diag), float(p0), float(p1)), int(leaf),
                              float(eta), float(eps), C.byref(opts), C.byref(h)))
@@ -220,6 +226,25 @@ class H2Matrix:
         p = np.zeros(self.n, dtype=np.int64)
         _check(_lib.h2_tree_perm(self._h, p.ctypes.data_as(C.POINTER(C.c_int64))))
         return p
+
+    def basis_ranks(self, level: int) -> np.ndarray:
+        r = np.zeros(1 << int(level), dtype=np.int32)
+        _check(_lib.h2_basis_ranks(self._h, int(level), r.ctypes.data_as(C.POINTER(C.c_int32))))
+        return r
+
+    def matvec(self, x) -> np.ndarray:
+        """y = A~ x with the built H^2 matrix (original point order)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros(self.n)
+        _check(_lib.h2_matvec(self._h, _dptr(x), _dptr(y)))
+        return y
+
+    def kernel_matvec(self, x) -> np.ndarray:
+        """y = A x with the exact kernel matrix, on the GPU."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros(self.n)
+        _check(_lib.h2_kernel_matvec(self._h, _dptr(x), _dptr(y)))
+        return y
 
     def profile_enable(self, on=True):
         """True/1: every launch timed; 2: GEMM launches only; False/0: off."""

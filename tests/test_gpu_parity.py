@@ -41,7 +41,7 @@ def _shifts_with_near_eigs(lam, count=33, seed=3):
 @pytest.mark.parametrize("n,leaf", [(256, 16), (300, 16), (97, 8), (1024, 64)])
 def test_tridiag_closed_form(lib, n, leaf, eta):
     print("case tridiag n=%d leaf=%d eta=%.1f" % (n, leaf, eta), flush=True)
-    A = lib.H2Matrix(W.line_points(n), W.K_TRIDIAG_1D, 2.0, leaf, eta, 1e-12, p0=1.0, sample_cap=n)
+    A = lib.H2Matrix(W.line_points(n), W.K_TRIDIAG_1D, 2.0, leaf, eta, 1e-12, p0=1.0)
     lam = tridiag_eigs(n)
     sig = _shifts_with_near_eigs(lam)
     nu = A.inertia(sig)
