@@ -134,6 +134,27 @@ h2_status h2_inertia_f32(h2_matrix A, const double* sigma, int64_t nshift,
 h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol,
                      const double* ab, double* lambda, double* bracket);
 
+/*
+ * Slicing the spectrum beyond one index (Sec. 2: nu(b) - nu(a) eigenvalues lie
+ * in [a, b); Sec. 4.2: several eigenvalues share one interval and its inertia
+ * records; Sec. 5.1 computes every eigenvalue this way, Sec. 5.2 the gap
+ * between the highest occupied and the lowest unoccupied state).
+ * h2_count   : *count = nu(b) - nu(a), the number of eigenvalues of A~ in
+ *              [a, b) (two inertia evaluations; finite a <= b).
+ * h2_eigs_in : every eigenvalue of A~ in [a, b), ascending, each by
+ *              Algorithm 1 to absolute tolerance tol inside [a, b); lambda is a
+ *              host array of cap doubles.  *count receives the number of
+ *              eigenvalues in [a, b) even when it exceeds cap, in which case
+ *              nothing else is computed and H2_EINVAL is returned.
+ * h2_gap     : lambda_{k+1} - lambda_k for 1 <= k < n, both to tolerance tol
+ *              (starting interval as h2_kth_eig with ab = NULL); lambda2, if
+ *              not NULL, receives the two eigenvalues.
+ * Errors as h2_inertia and h2_kth_eig.
+ */
+h2_status h2_count(h2_matrix A, double a, double b, int64_t* count);
+h2_status h2_eigs_in(h2_matrix A, double a, double b, double tol, int64_t cap, double* lambda, int64_t* count);
+h2_status h2_gap(h2_matrix A, int64_t k, double tol, double* lambda2, double* gap);
+
 /* normA used for tau = eps*normA: max(mean row sum of A over rows i = 0 mod s,
  * |A_ii|), s = max(1, n/16384). */
 h2_status h2_norm(h2_matrix A, double* normA);
@@ -178,6 +199,12 @@ h2_status h2_set_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_
                              int32_t tile);
 h2_status h2_get_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_t* grid, int32_t* group_m,
                              int32_t* tile);
+
+/* Free the handle's factorization workspace (it is allocated again, at the
+ * size the next h2_inertia needs, by that call); the resident H^2 data stays.
+ * The serving loop calls it when a matrix has nothing in flight.  H2_EBUSY,
+ * H2_EDEVICE. */
+h2_status h2_release_workspace(h2_matrix A);
 
 /* Cap on the shifts factored together in one launch (0 = automatic, from the
  * free device memory at each call); larger batches are split.  H2_EINVAL for
@@ -228,6 +255,13 @@ h2_status h2_tree_perm(h2_matrix A, int64_t* perm);
  * H2_EBUSY, H2_EDEVICE.
  */
 h2_status h2_basis_ranks(h2_matrix A, int32_t level, int32_t* r);
+/* Rank growth of the last factorization (Secs. 3.2-3.4): for shift `shift` of
+ * the last h2_inertia call (0-based position in its batch) and every level
+ * l < nlev, out[4l .. 4l+3] = (sum over the level's clusters of the directions
+ * t added by recompression, sum of the cluster dimensions m, largest m, sum of
+ * the pivot block sizes R); zeros for levels the factorization did not reach.
+ * out: host, 4*nlev int64.  H2_EINVAL for a shift outside the last batch. */
+h2_status h2_level_stats(h2_matrix A, int32_t shift, int32_t nlev, int64_t* out);
 h2_status h2_matvec(h2_matrix A, const double* x, double* y);
 h2_status h2_kernel_matvec(h2_matrix A, const double* x, double* y);
 
@@ -258,37 +292,50 @@ void h2_free(h2_matrix A);
 /*
  * Serving loop (continuous batching of k-th eigenvalue queries over resident
  * matrices).  Every resident matrix gets a worker thread; each tick the worker
- * admits queued queries up to the matrix's slot count, merges the next
- * bisection midpoint of every in-flight query (Algorithm 1, Sec. 2) into one
- * h2_inertia call on the matrix's stream, narrows every bracket with every new
- * inertia record (inertia reuse, Sec. 4.2) and completes queries whose bracket
- * is below their tolerance.  Matrices are served concurrently.  The server does
- * not own the matrices: free them after h2s_destroy.  A matrix added to a
- * server must not be used by the caller until h2s_destroy.
+ * admits queued queries, merges the next bisection midpoint of every in-flight
+ * query (Algorithm 1, Sec. 2) into one h2_inertia call on the matrix's stream,
+ * narrows every bracket with every new inertia record (inertia reuse,
+ * Sec. 4.2) and completes queries whose bracket is below their tolerance.
+ * Matrices are served concurrently.
+ * Admission by memory: the server holds one budget of device bytes for the
+ * factorization workspace of all its matrices.  A matrix's workspace per shift
+ * is measured when it is added; a worker admits a queued query only while the
+ * budget holds one more shift of its matrix, else the query waits in the
+ * queue, and a worker with nothing in flight frees its workspace and returns
+ * its share to the budget.  The server does not own the matrices: free them
+ * after h2s_destroy.  A matrix added to a server must not be used by the
+ * caller until h2s_destroy.
  */
 typedef struct h2_server_s* h2_server;
-/* max_slots: in-flight queries per matrix (0 = h2_capacity of each matrix). */
-h2_status h2s_create(int32_t max_slots, h2_server* out);
-/* Make A resident with `slots` in-flight queries (0 = the smaller of the
- * server's max_slots, if set, and h2_capacity); id: index used by h2s_submit.
- * Admission by memory: the call caps A's batch at `slots` shifts and reserves
- * their device workspace now by running the first step of every future query
- * (the starting interval h2_interval cut at `slots` equally spaced shifts,
- * whose counts seed the matrix's records), since the workspace of a shift is
- * known only once its ranks are.  H2_ENOMEM if even that does not fit. */
+/* budget_bytes: device bytes for the workspace of all matrices (0 = 85% of the
+ * free device memory now); max_slots: in-flight queries per matrix (0 = 64). */
+h2_status h2s_create(int64_t budget_bytes, int32_t max_slots, h2_server* out);
+/* Make A resident with at most `slots` queries in flight (0 = the server's
+ * max_slots); id: index used by h2s_submit.  Runs one factorization (the
+ * midpoint of the starting interval h2_interval, whose count seeds the
+ * matrix's records) to measure the workspace of a shift, then frees it.
+ * H2_ENOMEM if one shift needs more than the server's budget. */
 h2_status h2s_add(h2_server S, h2_matrix A, int32_t slots, int32_t* id);
 /* Queue a query for lambda_k (1-based, ascending) of matrix id to absolute
  * tolerance tol; returns immediately with a ticket.  H2_EINVAL for a bad id,
  * k outside [1, n] or tol <= 0. */
 h2_status h2s_submit(h2_server S, int32_t id, int64_t k, double tol, int64_t* ticket);
 /* done = 1 and lambda set once the query has finished; the status of a failed
- * factorization is returned for its queries. */
+ * factorization is returned for its queries.  A finished ticket is read once:
+ * the call that reports it done (or failed) forgets it. */
 h2_status h2s_poll(h2_server S, int64_t ticket, double* lambda, int32_t* done);
-/* Block until the query has finished (H2_EINVAL if the server stops first). */
+/* Block until the query has finished (H2_EINVAL if the server stops first);
+ * forgets the ticket as h2s_poll does. */
 h2_status h2s_wait(h2_server S, int64_t ticket, double* lambda);
 /* Latency percentiles (submission to completion, ms) of the finished queries,
  * and the numbers of finished and submitted queries. */
 h2_status h2s_stats(h2_server S, double* p50_ms, double* p99_ms, int64_t* served, int64_t* submitted);
+/* Censored latency: percentiles over every submitted query, an unfinished one
+ * counted at its time since submission (a lower bound of its latency);
+ * unfinished = queries queued or in flight now; the budget and the bytes of
+ * it held now.  Any output may be NULL. */
+h2_status h2s_latency(h2_server S, double* p50_ms, double* p99_ms, int64_t* unfinished, int64_t* budget_bytes,
+                      int64_t* used_bytes);
 /* Stop the workers (in-flight queries are abandoned; a worker inside a
  * factorization finishes it first) and free the server.  No other h2s_ call
  * on S may be running or follow: join the threads that poll or wait first. */

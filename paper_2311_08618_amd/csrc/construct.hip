@@ -242,7 +242,6 @@ __global__ __launch_bounds__(256) void k_far_pchol(const int* __restrict__ mrow,
   __shared__ int s_p;
   __shared__ int s_stop;
   __shared__ double s_lkk_hi, s_lkk_lo;
-  extern __shared__ double lp[];   // L(p, 0..k-1), hi then lo (2 * m doubles)
   const int cl = blockIdx.x;
   const int m = mrow[cl];
   const double tau2 = tau2c[cl];
@@ -313,16 +312,12 @@ __global__ __launch_bounds__(256) void k_far_pchol(const int* __restrict__ mrow,
     if (s_stop) break;
     const int p = s_p;
     const dd lkk{s_lkk_hi, s_lkk_lo};
-    for (int q = tid; q < k; q += 256) {
-      lp[q] = lh[p + (int64_t)q * m];
-      lp[m + q] = ll[p + (int64_t)q * m];
-    }
-    __syncthreads();
     for (int j = tid; j < m; j += 256) {
       if (stp[j] != 0) continue;
       double ch = gh[j + (int64_t)p * m], cl_ = gl[j + (int64_t)p * m];
       for (int q = 0; q < k; ++q)
-        dd_msub(ch, cl_, dd{lh[j + (int64_t)q * m], ll[j + (int64_t)q * m]}, dd{lp[q], lp[m + q]});
+        dd_msub(ch, cl_, dd{lh[j + (int64_t)q * m], ll[j + (int64_t)q * m]},
+                dd{lh[p + (int64_t)q * m], ll[p + (int64_t)q * m]});
       const dd c = fast_norm(ch, cl_);
       const dd v = dd_div(c, lkk);
       lh[j + (int64_t)k * m] = v.hi;
@@ -419,13 +414,11 @@ void far_field_ids(const FarIdPoints& P, int kind, double p0, double p1, const F
     std::vector<double> rx, ry, rz;
     std::vector<FarItem> items;
     int64_t go = 0, ro = 0;
-    int mmax = 0;
     for (int b = 0; b < nb; ++b) {
       const int i = todo[t0 + b];
       const int m = lev.m[i];
       mb[b] = m;
       t2b[b] = lev.tau2[i];
-      mmax = std::max(mmax, m);
       rob[b] = ro;
       gob[b] = go;
       for (int a = 0; a < m; ++a) {
@@ -483,9 +476,7 @@ void far_field_ids(const FarIdPoints& P, int kind, double p0, double p1, const F
       }
       FCHK(hipGetLastError());
     }
-    const size_t lds = (size_t)2 * mmax * sizeof(double);
-    if (lds > 64 * 1024) throw std::invalid_argument("cluster dimension too large for the far-field factorization");
-    hipLaunchKernelGGL(k_far_pchol, dim3(nb), dim3(256), lds, st, dm, dro, dgo, Gh, Gl, Lh, Ll, dh, dl, stp, piv, rk,
+    hipLaunchKernelGGL(k_far_pchol, dim3(nb), dim3(256), 0, st, dm, dro, dgo, Gh, Gl, Lh, Ll, dh, dl, stp, piv, rk,
                        dt2, Lo);
     FCHK(hipGetLastError());
     std::vector<int> rh(nb), ph(ro > 0 ? ro : 1);
@@ -519,22 +510,27 @@ namespace h2 {
 namespace {
 
 // y_i = sum_j A_ij x_j for the exact kernel matrix (A_ii = diag), one row per
-// thread, the column points and x streaming through LDS in tiles of 256.
+// thread, the column points (X row-major n x dim) and x streaming through LDS
+// in tiles of 256.
 template <int KIND>
-__global__ __launch_bounds__(256) void k_kernel_matvec(const double* __restrict__ px, const double* __restrict__ py,
-                                                       const double* __restrict__ pz, const double* __restrict__ x,
-                                                       int64_t n, double diag, double p0, double p1,
-                                                       double* __restrict__ y) {
+__global__ __launch_bounds__(256) void k_kernel_matvec(const double* __restrict__ X, int dim,
+                                                       const double* __restrict__ x, int64_t n, double diag, double p0,
+                                                       double p1, double* __restrict__ y) {
   __shared__ double tx[256], ty[256], tz[256], tv[256];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const double xi = i < n ? px[i] : 0.0, yi = i < n ? py[i] : 0.0, zi = i < n ? pz[i] : 0.0;
+  double xi = 0.0, yi = 0.0, zi = 0.0;
+  if (i < n) {
+    xi = X[i * dim];
+    if (dim > 1) yi = X[i * dim + 1];
+    if (dim > 2) zi = X[i * dim + 2];
+  }
   double acc = 0.0;
   for (int64_t j0 = 0; j0 < n; j0 += 256) {
     __syncthreads();
     const int64_t j = j0 + threadIdx.x;
-    tx[threadIdx.x] = j < n ? px[j] : 0.0;
-    ty[threadIdx.x] = j < n ? py[j] : 0.0;
-    tz[threadIdx.x] = j < n ? pz[j] : 0.0;
+    tx[threadIdx.x] = j < n ? X[j * dim] : 0.0;
+    ty[threadIdx.x] = (j < n && dim > 1) ? X[j * dim + 1] : 0.0;
+    tz[threadIdx.x] = (j < n && dim > 2) ? X[j * dim + 2] : 0.0;
     tv[threadIdx.x] = j < n ? x[j] : 0.0;
     __syncthreads();
     const int jn = (int)min<int64_t>(256, n - j0);
@@ -549,33 +545,38 @@ __global__ __launch_bounds__(256) void k_kernel_matvec(const double* __restrict_
 
 }  // namespace
 
-void kernel_matvec_gpu(const double* X, int64_t n, int dim, int kind, double diag, double p0, double p1,
-                       const double* x, double* y, hipStream_t st) {
-  std::vector<int64_t> id(n);
-  for (int64_t p = 0; p < n; ++p) id[p] = p;
-  FarIdPoints P;
-  far_points_upload(P, X, id.data(), n, dim, st);
-  struct Guard {
-    FarIdPoints& p;
-    ~Guard() { far_points_free(p); }
-  } guard{P};
-  std::vector<double> xv(x, x + n);
-  double* dx = dev_copy(xv, st);
-  double* dy = nullptr;
-  FCHK(hipMalloc(&dy, std::max<int64_t>(1, n) * 8));
+void launch_kernel_matvec(const double* dX, int64_t n, int dim, int kind, double diag, double p0, double p1,
+                          const double* dx, double* dy, hipStream_t st) {
+  if (n <= 0) return;
   const dim3 g((unsigned)((n + 255) / 256)), b(256);
   switch (kind) {
-    case 0: hipLaunchKernelGGL(k_kernel_matvec<0>, g, b, 0, st, P.px, P.py, P.pz, dx, n, diag, p0, p1, dy); break;
-    case 1: hipLaunchKernelGGL(k_kernel_matvec<1>, g, b, 0, st, P.px, P.py, P.pz, dx, n, diag, p0, p1, dy); break;
-    case 2: hipLaunchKernelGGL(k_kernel_matvec<2>, g, b, 0, st, P.px, P.py, P.pz, dx, n, diag, p0, p1, dy); break;
-    case 3: hipLaunchKernelGGL(k_kernel_matvec<3>, g, b, 0, st, P.px, P.py, P.pz, dx, n, diag, p0, p1, dy); break;
-    default: hipLaunchKernelGGL(k_kernel_matvec<4>, g, b, 0, st, P.px, P.py, P.pz, dx, n, diag, p0, p1, dy); break;
+    case 0: hipLaunchKernelGGL(k_kernel_matvec<0>, g, b, 0, st, dX, dim, dx, n, diag, p0, p1, dy); break;
+    case 1: hipLaunchKernelGGL(k_kernel_matvec<1>, g, b, 0, st, dX, dim, dx, n, diag, p0, p1, dy); break;
+    case 2: hipLaunchKernelGGL(k_kernel_matvec<2>, g, b, 0, st, dX, dim, dx, n, diag, p0, p1, dy); break;
+    case 3: hipLaunchKernelGGL(k_kernel_matvec<3>, g, b, 0, st, dX, dim, dx, n, diag, p0, p1, dy); break;
+    default: hipLaunchKernelGGL(k_kernel_matvec<4>, g, b, 0, st, dX, dim, dx, n, diag, p0, p1, dy); break;
   }
+}
+
+void kernel_matvec_gpu(const double* X, int64_t n, int dim, int kind, double diag, double p0, double p1,
+                       const double* x, double* y, hipStream_t st) {
+  double *dX = nullptr, *dx = nullptr, *dy = nullptr;
+  struct Guard {
+    double** p[3];
+    ~Guard() {
+      for (double** q : p)
+        if (*q) (void)hipFree(*q);
+    }
+  } guard{{&dX, &dx, &dy}};
+  FCHK(hipMalloc(&dX, std::max<int64_t>(1, n * dim) * 8));
+  FCHK(hipMalloc(&dx, std::max<int64_t>(1, n) * 8));
+  FCHK(hipMalloc(&dy, std::max<int64_t>(1, n) * 8));
+  FCHK(hipMemcpyAsync(dX, X, n * dim * 8, hipMemcpyHostToDevice, st));
+  FCHK(hipMemcpyAsync(dx, x, n * 8, hipMemcpyHostToDevice, st));
+  launch_kernel_matvec(dX, n, dim, kind, diag, p0, p1, dx, dy, st);
   FCHK(hipGetLastError());
   FCHK(hipMemcpyAsync(y, dy, n * 8, hipMemcpyDeviceToHost, st));
   FCHK(hipStreamSynchronize(st));
-  FCHK(hipFree(dx));
-  FCHK(hipFree(dy));
 }
 
 }  // namespace h2

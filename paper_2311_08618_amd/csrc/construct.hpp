@@ -61,4 +61,8 @@ void far_field_ids(const FarIdPoints& P, int kind, double p0, double p1, const F
 void kernel_matvec_gpu(const double* X, int64_t n, int dim, int kind, double diag, double p0, double p1,
                        const double* x, double* y, hipStream_t st);
 
+// Exact-kernel matvec on device arrays (X row-major n x dim, x and y of n).
+void launch_kernel_matvec(const double* dX, int64_t n, int dim, int kind, double diag, double p0, double p1,
+                          const double* dx, double* dy, hipStream_t st);
+
 }  // namespace h2

@@ -80,7 +80,7 @@ struct Arena {
       p = nullptr;
       cap = 0;
     }
-    size_t want = bytes + bytes / 8 + 4096;
+    size_t want = bytes + bytes / 32 + 4096;
     if (hipMalloc(&p, want) != hipSuccess) {
       (void)hipGetLastError();
       p = nullptr;
@@ -242,6 +242,8 @@ struct h2_matrix_s {
   std::vector<std::pair<double, int64_t>> cache;
   bool have_gersh = false;
   double mixed_rel = 0.0;
+  std::vector<std::vector<int64_t>> lstats;   // per level, per shift of the last factorization: sum t, sum m, max m, sum R
+  int lstats_shifts = 0;
   std::vector<int32_t> last_cap;   // block capacity of each level in the last factorization (0 = not reached)   // h2_kth_eig: FP32 steps while a bracket is >= mixed_rel * normA wide
   double g_lo = 0, g_hi = 0;
   h2_stats_t st{};
@@ -612,6 +614,8 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
   int maxdim = cap;
   std::vector<int> hpm;
   A->last_cap.assign(L + 1, 0);
+  A->lstats.assign(L + 1, {});
+  A->lstats_shifts = S;
   for (int l = L; l >= 0; --l) {
     const LevelPlan& lp = A->plan[l];
     const DevLevel& dl = A->dlev[l];
@@ -811,12 +815,35 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
       gl(PC_GRAM, GEMM_NT, dc.gg);
     }
     HIPCHK(hipGetLastError());
+    // per-level statistics of the factorization (rank growth): m, R and t of
+    // every cluster, read back with the merge sizes below
+    std::vector<int> lm((size_t)S * N), lR((size_t)S * N), lt((size_t)S * N);
+    HIPCHK(hipMemcpyAsync(lm.data(), w.m, lm.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(lR.data(), w.R, lR.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(lt.data(), w.t, lt.size() * 4, hipMemcpyDeviceToHost, st));
+    auto record_stats = [&]() {
+      A->lstats[l].assign((size_t)S * 4, 0);
+      for (int s2 = 0; s2 < S; ++s2) {
+        int64_t* o = &A->lstats[l][(size_t)s2 * 4];
+        for (int i = 0; i < N; ++i) {
+          const size_t k = (size_t)s2 * N + i;
+          o[0] += lt[k];
+          o[1] += lm[k];
+          o[2] = std::max<int64_t>(o[2], lm[k]);
+          o[3] += lR[k];
+        }
+      }
+    };
     if (debug_level()) {
       debug_dump_level(l, N, S, w, st);
       std::fprintf(stderr, "[h2eig]   cap %d arenas GB: sf %.2f %.2f lvl %.2f mrg %.2f\n", cap, A->sf[0].cap / 1e9,
                    A->sf[1].cap / 1e9, A->lvl.cap / 1e9, A->mrg.cap / 1e9);
     }
-    if (l == 0) break;
+    if (l == 0) {
+      HIPCHK(hipStreamSynchronize(st));
+      record_stats();
+      break;
+    }
     // ---- merge into level l-1
     const LevelPlan& pp = A->plan[l - 1];
     const int Np = N >> 1;
@@ -824,6 +851,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
     hpm.resize((size_t)S * Np);
     HIPCHK(hipMemcpyAsync(hpm.data(), w.pm, (size_t)S * Np * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    record_stats();
     int pmax = 0;
     for (int v : hpm) pmax = std::max(pmax, v);
     if (pmax == 0) break;  // nothing left above this level
@@ -1239,6 +1267,66 @@ h2_status h2_interval(h2_matrix A, double* ab) {
   return H2_OK;
 }
 
+h2_status h2_release_workspace(h2_matrix A) {
+  if (!A) return fail(H2_EINVAL, "NULL handle");
+  Busy b(A);
+  if (!b.ok) return fail(H2_EBUSY, "handle in use by another thread");
+  try {
+    HIPCHK(hipSetDevice(A->device));
+    HIPCHK(hipStreamSynchronize(A->stream));
+  } catch (HipError& e) {
+    return fail(H2_EDEVICE, e.where + ": " + hipGetErrorString(e.e));
+  }
+  for (auto& a : A->sf) a.release();
+  A->lvl.release();
+  A->mrg.release();
+  A->rs.release();
+  return H2_OK;
+}
+
+h2_status h2_count(h2_matrix A, double a, double b, int64_t* count) {
+  if (!A || !count) return fail(H2_EINVAL, "NULL argument");
+  if (!(std::isfinite(a) && std::isfinite(b) && a <= b)) return fail(H2_EINVAL, "need finite a <= b");
+  const double sig[2] = {a, b};
+  int64_t nu[2];
+  const h2_status r = h2_inertia(A, sig, 2, nu, nullptr);
+  if (r != H2_OK) return r;
+  *count = nu[1] - nu[0];
+  return H2_OK;
+}
+
+h2_status h2_eigs_in(h2_matrix A, double a, double b, double tol, int64_t cap, double* lambda, int64_t* count) {
+  if (!A || !count || (cap > 0 && !lambda)) return fail(H2_EINVAL, "NULL argument");
+  if (!(std::isfinite(a) && std::isfinite(b) && a < b)) return fail(H2_EINVAL, "need finite a < b");
+  if (!(tol > 0.0)) return fail(H2_EINVAL, "tol must be > 0");
+  const double sig[2] = {a, b};
+  int64_t nu[2];
+  h2_status r = h2_inertia(A, sig, 2, nu, nullptr);
+  if (r != H2_OK) return r;
+  *count = nu[1] - nu[0];
+  if (*count > cap) return fail(H2_EINVAL, "more eigenvalues in [a, b) than cap (count returned)");
+  if (*count == 0) return H2_OK;
+  std::vector<int64_t> ks((size_t)*count);
+  for (int64_t j = 0; j < *count; ++j) ks[j] = nu[0] + 1 + j;
+  const double ab[2] = {a, b};
+  return h2_kth_eig(A, ks.data(), *count, tol, ab, lambda, nullptr);
+}
+
+h2_status h2_gap(h2_matrix A, int64_t k, double tol, double* lambda2, double* gap) {
+  if (!A || !gap) return fail(H2_EINVAL, "NULL argument");
+  if (k < 1 || k >= A->T.n) return fail(H2_EINVAL, "k must be in [1, n-1]");
+  const int64_t ks[2] = {k, k + 1};
+  double lam[2];
+  const h2_status r = h2_kth_eig(A, ks, 2, tol, nullptr, lam, nullptr);
+  if (r != H2_OK) return r;
+  if (lambda2) {
+    lambda2[0] = lam[0];
+    lambda2[1] = lam[1];
+  }
+  *gap = lam[1] - lam[0];
+  return H2_OK;
+}
+
 h2_status h2_set_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_t grid, int32_t group_m,
                              int32_t tile) {
   if (layout < 0 || layout > 3 || f32 < 0 || f32 > 1 || bucket < 0 || bucket >= GEMM_BUCKETS)
@@ -1313,6 +1401,16 @@ h2_status h2_set_stream(h2_matrix A, void* hip_stream) {
 h2_status h2_tree_perm(h2_matrix A, int64_t* perm) {
   if (!A || !perm) return fail(H2_EINVAL, "NULL argument");
   std::copy(A->T.perm.begin(), A->T.perm.end(), perm);
+  return H2_OK;
+}
+
+h2_status h2_level_stats(h2_matrix A, int32_t shift, int32_t nlev, int64_t* out) {
+  if (!A || !out) return fail(H2_EINVAL, "NULL argument");
+  if (shift < 0 || shift >= A->lstats_shifts) return fail(H2_EINVAL, "shift out of range of the last factorization");
+  for (int l = 0; l < nlev; ++l)
+    for (int k = 0; k < 4; ++k)
+      out[l * 4 + k] = (l <= A->T.L && (size_t)shift * 4 + k < A->lstats[l].size()) ? A->lstats[l][(size_t)shift * 4 + k]
+                                                                                : 0;
   return H2_OK;
 }
 

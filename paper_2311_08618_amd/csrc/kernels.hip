@@ -99,9 +99,11 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const GItem* __restrict__ it
 // sharing panels of A or B meet in the same L2.  Operands and results are FP64
 // in memory; F32 converts the operands to FP32 on their way into LDS and
 // multiplies them on FP32 MFMA with FP32 accumulation (the early bisection
-// steps), else everything is FP64.  Output tiles are T x T (64 or 128): four
-// waves in a 2 x 2 layout, each computing (T/2) x (T/2) as (T/32)^2 MFMA blocks.
-template <bool TA, bool TB, bool F32, int T>
+// steps), else everything is FP64.  Output tiles are T x T (64 or 128), WM x WN
+// waves (64 x 64: 2 x 2 waves of 32 x 32; 128 x 128: 2 x 4 waves of 64 x 32, so
+// that two workgroups of eight waves share a CU), each wave computing its part
+// as FWM x FWN MFMA blocks of 16 x 16.
+template <bool TA, bool TB, bool F32, int T, int WM, int WN>
 __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int nitems, const GTerm* __restrict__ terms,
                                           const BufTab& bt, const SizeTab& sz, const int* __restrict__ prefix,
                                           int slot_base) {
@@ -112,9 +114,13 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
   const int total = pre[nitems];
   const int G = gridDim.x;
   const int lw = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);   // G is a multiple of 8
-  constexpr int FW = T / 32;     // MFMA blocks per wave and dimension
-  constexpr int HT = T / 2;      // rows (columns) of a wave's part of the tile
-  constexpr int NE = T / 16;     // elements of each operand tile a thread stages
+  constexpr int NT = 64 * WM * WN;  // threads
+  constexpr int HM = T / WM;        // rows of a wave's part of the tile
+  constexpr int HN = T / WN;        // columns of a wave's part of the tile
+  constexpr int FWM = HM / 16;      // MFMA blocks per wave, rows
+  constexpr int FWN = HN / 16;      // MFMA blocks per wave, columns
+  constexpr int NE = T * GK / NT;   // elements of each operand tile a thread stages
+  static_assert(NE * NT == T * GK, "operand tile must split evenly over the threads");
   __shared__ CT As[2][GK][T + 1];
   __shared__ CT Bs[2][GK][T + 1];
   for (int tile = lw; tile < total; tile += G) {
@@ -147,10 +153,10 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
     if (bt.fck) atomicAdd(bt.fck, 2ull * (unsigned long long)M * (unsigned long long)N * kk);
   }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  VT acc[FW][FW];
-  for (int i = 0; i < FW; ++i)
-    for (int j = 0; j < FW; ++j) acc[i][j] = VT{0, 0, 0, 0};
+  const int wm = wave / WN, wn = wave % WN;
+  VT acc[FWM][FWN];
+  for (int i = 0; i < FWM; ++i)
+    for (int j = 0; j < FWN; ++j) acc[i][j] = VT{0, 0, 0, 0};
 
   for (int tt = 0; tt < it.nt; ++tt) {
     const GTerm tm = terms[it.t0 + tt];
@@ -170,7 +176,7 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
       const int k0 = kt * GK;
 #pragma unroll
       for (int r = 0; r < NE; ++r) {
-        const int e = tid + 256 * r;
+        const int e = tid + NT * r;
         int mm, kk;
         if (TA) { kk = e % GK; mm = e / GK; } else { mm = e % T; kk = e / T; }
         const int gm = m0 + mm, gk = k0 + kk;
@@ -189,7 +195,7 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
     auto sstore = [&](int buf) {
 #pragma unroll
       for (int r = 0; r < NE; ++r) {
-        const int e = tid + 256 * r;
+        const int e = tid + NT * r;
         int mm, kk;
         if (TA) { kk = e % GK; mm = e / GK; } else { mm = e % T; kk = e / T; }
         As[buf][kk][mm] = (CT)ra[r];
@@ -207,16 +213,15 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
 #pragma unroll
       for (int kk = 0; kk < GK; kk += 4) {
         const int kr = kk + (lane >> 4);
-        CT a[FW], b[FW];
+        CT a[FWM], b[FWN];
 #pragma unroll
-        for (int f = 0; f < FW; ++f) {
-          a[f] = As[cur][kr][wm * HT + f * 16 + (lane & 15)];
-          b[f] = Bs[cur][kr][wn * HT + f * 16 + (lane & 15)];
-        }
+        for (int f = 0; f < FWM; ++f) a[f] = As[cur][kr][wm * HM + f * 16 + (lane & 15)];
 #pragma unroll
-        for (int i = 0; i < FW; ++i)
+        for (int f = 0; f < FWN; ++f) b[f] = Bs[cur][kr][wn * HN + f * 16 + (lane & 15)];
 #pragma unroll
-          for (int j = 0; j < FW; ++j) {
+        for (int i = 0; i < FWM; ++i)
+#pragma unroll
+          for (int j = 0; j < FWN; ++j) {
             if constexpr (F32) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
             else acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
           }
@@ -243,13 +248,13 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
     C2 = addr(bt, it.c2.buf, it.c2.blk, s, r2, c2);
     ldc2 = bt.ld[it.c2.buf];
   }
-  for (int i = 0; i < FW; ++i)
-    for (int j = 0; j < FW; ++j)
+  for (int i = 0; i < FWM; ++i)
+    for (int j = 0; j < FWN; ++j)
       for (int v = 0; v < 4; ++v) {
         // output row of register v: FP64 MFMA puts D[i][j] in lane j + 16*(i%4),
         // register i/4; FP32 MFMA in lane j + 16*(i/4), register i%4
-        int r = m0 + wm * HT + i * 16 + (F32 ? 4 * (lane >> 4) + v : (lane >> 4) + 4 * v);
-        int c = n0 + wn * HT + j * 16 + (lane & 15);
+        int r = m0 + wm * HM + i * 16 + (F32 ? 4 * (lane >> 4) + v : (lane >> 4) + 4 * v);
+        int c = n0 + wn * HN + j * 16 + (lane & 15);
         if (r < M && c < N) {
           double x = it.alpha * (double)acc[i][j][v];
           const int dr = r < rs ? cr + r : r2o + (r - rs), dcol = c < cs ? cc + c : c2o + (c - cs);
@@ -268,29 +273,30 @@ template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, int nitems,
                                               const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
                                               const int* __restrict__ prefix, int slot_base) {
-  gemm_body<TA, TB, false, 64>(items, nitems, terms, bt, sz, prefix, slot_base);
+  gemm_body<TA, TB, false, 64, 2, 2>(items, nitems, terms, bt, sz, prefix, slot_base);
 }
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm_f32(const GItem* __restrict__ items, int nitems,
                                                   const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
                                                   const int* __restrict__ prefix, int slot_base) {
-  gemm_body<TA, TB, true, 64>(items, nitems, terms, bt, sz, prefix, slot_base);
+  gemm_body<TA, TB, true, 64, 2, 2>(items, nitems, terms, bt, sz, prefix, slot_base);
 }
 
-// 128 x 128 output tiles: twice the arithmetic per operand byte, for large blocks
+// 128 x 128 output tiles on eight waves: twice the arithmetic per operand byte
+// of the 64 x 64 tile, at two resident workgroups per CU, for large blocks
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm128(const GItem* __restrict__ items, int nitems,
+__global__ __launch_bounds__(512, 4) void k_gemm128(const GItem* __restrict__ items, int nitems,
                                                  const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
                                                  const int* __restrict__ prefix, int slot_base) {
-  gemm_body<TA, TB, false, 128>(items, nitems, terms, bt, sz, prefix, slot_base);
+  gemm_body<TA, TB, false, 128, 2, 4>(items, nitems, terms, bt, sz, prefix, slot_base);
 }
 
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm128_f32(const GItem* __restrict__ items, int nitems,
+__global__ __launch_bounds__(512, 4) void k_gemm128_f32(const GItem* __restrict__ items, int nitems,
                                                      const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
                                                      const int* __restrict__ prefix, int slot_base) {
-  gemm_body<TA, TB, true, 128>(items, nitems, terms, bt, sz, prefix, slot_base);
+  gemm_body<TA, TB, true, 128, 2, 4>(items, nitems, terms, bt, sz, prefix, slot_base);
 }
 
 // Transposed copy of a scratch slot, or of a source block, into a block:
@@ -1495,8 +1501,8 @@ template <bool TA, bool TB>
 void launch_variant(int f32, int T, dim3 grid, const GItem* items, int nitems, const GTerm* terms, const BufTab& bt,
                     const SizeTab& sz, int* prefix, hipStream_t st) {
   if (T == 128) {
-    if (f32) hipLaunchKernelGGL((k_gemm128_f32<TA, TB>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0);
-    else hipLaunchKernelGGL((k_gemm128<TA, TB>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0);
+    if (f32) hipLaunchKernelGGL((k_gemm128_f32<TA, TB>), grid, dim3(512), 0, st, items, nitems, terms, bt, sz, prefix, 0);
+    else hipLaunchKernelGGL((k_gemm128<TA, TB>), grid, dim3(512), 0, st, items, nitems, terms, bt, sz, prefix, 0);
   } else {
     if (f32) hipLaunchKernelGGL((k_gemm_f32<TA, TB>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0);
     else hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(256), 0, st, items, nitems, terms, bt, sz, prefix, 0);

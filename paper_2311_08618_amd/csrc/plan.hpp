@@ -52,7 +52,7 @@ struct ColourPlan {
 
 // Merge outputs are processed in chunks of MERGE_CHUNK parent blocks, which
 // share the B_HAT / B_TMP slots (slot = output index % MERGE_CHUNK).
-constexpr int MERGE_CHUNK = 512;
+constexpr int MERGE_CHUNK = 64;
 
 struct MergeChunk {
   int g0, g1, f0, f1, a0, a1, b0, b1;   // item ranges in gather, fill, tr1, tr2

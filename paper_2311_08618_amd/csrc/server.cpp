@@ -7,8 +7,16 @@
 // the matrix's record cache), narrows every bracket with every new record and
 // completes the queries whose bracket is narrower than their tolerance.
 // Latency is taken from submission to completion.
+//
+// Admission by memory: the server owns one device-memory budget for the
+// factorization workspace of all its matrices.  Each matrix's workspace per
+// shift is measured when it is added (one factorization), and a worker holds
+// budget for as many shifts as it has admitted queries: it grows its share at
+// each tick while the budget allows, queues the rest, and gives its share
+// (and its workspace) back when it has nothing in flight.
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -18,6 +26,8 @@
 #include <string>
 #include <thread>
 #include <vector>
+
+#include <hip/hip_runtime.h>
 
 #include "../../include/h2eig.h"
 
@@ -45,11 +55,13 @@ struct Query {
 struct Resident {
   h2_matrix A = nullptr;
   int64_t n = 0;
-  int32_t slots = 1;
+  int32_t slots = 1;        // most queries in flight
   double a0 = 0.0, b0 = 0.0;
+  int64_t per_shift = 0;    // workspace bytes of one shift (measured at admission of the matrix, +10%)
+  int64_t held = 0;         // budget held: per_shift times the shifts it can factor together now
   std::deque<int64_t> queue;
   std::vector<int64_t> active;
-  std::vector<std::pair<double, int64_t>> records;
+  std::vector<std::pair<double, int64_t>> records;   // (mu, nu), sorted by mu
   std::thread worker;
 };
 
@@ -60,6 +72,8 @@ struct h2_server_s {
   std::condition_variable cv_work, cv_done;
   bool stop = false;
   int32_t max_slots = 0;
+  int64_t budget = 0, used = 0;   // device bytes for workspace, shared by all matrices
+  int waiting = 0;                // workers blocked until the budget has room
   std::vector<std::unique_ptr<Resident>> mats;
   std::map<int64_t, Query> q;
   int64_t next_ticket = 1;
@@ -72,6 +86,26 @@ namespace {
 h2_status fail(h2_status s, const char* msg) {
   h2::set_last_error(msg);
   return s;
+}
+
+void add_record(Resident& R, double mu, int64_t nu) {
+  auto it = std::lower_bound(R.records.begin(), R.records.end(), std::make_pair(mu, (int64_t)INT64_MIN));
+  if (it != R.records.end() && it->first == mu) return;
+  R.records.insert(it, {mu, nu});
+}
+
+// the starting bracket of a query for lambda_k from the matrix's records: the
+// record of largest mu with nu < k and the next record with nu >= k, found by
+// binary search (counts grow with mu) and each end checked on its own
+void seed_bracket(const Resident& R, Query& x) {
+  x.lo = R.a0;
+  x.hi = R.b0;
+  const auto& v = R.records;
+  const size_t p = std::partition_point(v.begin(), v.end(), [&](const std::pair<double, int64_t>& r) {
+                     return r.second < x.k;
+                   }) - v.begin();
+  if (p > 0 && v[p - 1].second < x.k && v[p - 1].first > x.lo && v[p - 1].first < x.hi) x.lo = v[p - 1].first;
+  if (p < v.size() && v[p].second >= x.k && v[p].first > x.lo && v[p].first < x.hi) x.hi = v[p].first;
 }
 
 // narrow [lo, hi] of every in-flight query of the matrix by the record (mu, nu)
@@ -115,21 +149,37 @@ void complete(h2_server S, Resident& R) {
 void worker_loop(h2_server S, Resident* R) {
   std::unique_lock<std::mutex> lk(S->mu);
   for (;;) {
-    S->cv_work.wait(lk, [&] { return S->stop || !R->queue.empty() || !R->active.empty(); });
+    // wake for work: queries in flight, or queued ones and budget for one
+    // shift (already held, or free)
+    auto runnable = [&] {
+      return S->stop || !R->active.empty() ||
+             (!R->queue.empty() && (R->held >= R->per_shift || S->budget - S->used >= R->per_shift));
+    };
+    if (!runnable()) {
+      ++S->waiting;
+      S->cv_work.wait(lk, runnable);
+      --S->waiting;
+    }
     if (S->stop) break;
-    // admission: one bracket per slot
-    while ((int32_t)R->active.size() < R->slots && !R->queue.empty()) {
+    // admission by memory: grow the held share toward the wanted shifts
+    {
+      const int64_t want = std::min<int64_t>(R->slots, (int64_t)(R->active.size() + R->queue.size()));
+      if (want * R->per_shift > R->held) {
+        const int64_t room = S->budget - S->used + R->held;
+        const int64_t can = std::min<int64_t>(want, room / std::max<int64_t>(1, R->per_shift));
+        if (can * R->per_shift > R->held) {
+          S->used += can * R->per_shift - R->held;
+          R->held = can * R->per_shift;
+        }
+      }
+    }
+    const int64_t cap_shifts = R->held / std::max<int64_t>(1, R->per_shift);
+    while ((int64_t)R->active.size() < std::min<int64_t>(R->slots, cap_shifts) && !R->queue.empty()) {
       const int64_t t = R->queue.front();
       R->queue.pop_front();
       Query& x = S->q[t];
       x.state = 1;
-      x.lo = R->a0;
-      x.hi = R->b0;
-      for (auto& rec : R->records)
-        if (rec.first > x.lo && rec.first < x.hi) {
-          if (rec.second >= x.k) x.hi = rec.first;
-          else x.lo = rec.first;
-        }
+      seed_bracket(*R, x);
       R->active.push_back(t);
     }
     complete(S, *R);
@@ -139,12 +189,25 @@ void worker_loop(h2_server S, Resident* R) {
       x.split = x.lo + (x.hi - x.lo) * (0.5 + x.nudge / 64.0);
       mus.push_back(x.split);
     }
-    if (mus.empty()) continue;
+    if (mus.empty()) {
+      // nothing in flight: give the workspace and the budget share back
+      if (R->held > 0) {
+        S->used -= R->held;
+        R->held = 0;
+        lk.unlock();
+        (void)h2_release_workspace(R->A);
+        lk.lock();
+        S->cv_work.notify_all();
+      }
+      continue;
+    }
     std::sort(mus.begin(), mus.end());
     mus.erase(std::unique(mus.begin(), mus.end()), mus.end());
     std::vector<int64_t> nus(mus.size());
     std::vector<int32_t> sts(mus.size());
+    const int32_t batch = (int32_t)std::max<int64_t>(1, cap_shifts);
     lk.unlock();
+    (void)h2_set_max_shifts(R->A, batch);
     const h2_status r = h2_inertia(R->A, mus.data(), (int64_t)mus.size(), nus.data(), sts.data());
     lk.lock();
     if (r != H2_OK && r != H2_ENUMERIC) {   // the in-flight queries fail with the call's status
@@ -171,10 +234,27 @@ void worker_loop(h2_server S, Resident* R) {
     R->active.swap(keep);
     for (size_t j = 0; j < mus.size(); ++j) {
       if (sts[j] != H2_OK) continue;
-      R->records.push_back({mus[j], nus[j]});
+      add_record(*R, mus[j], nus[j]);
       narrow(S, *R, mus[j], nus[j]);
     }
     complete(S, *R);
+    // nothing in flight: give the share back when the queue is empty, or
+    // when another matrix waits for budget (then step aside briefly so that
+    // it can take the share before this worker competes again)
+    if (R->active.empty() && R->held > 0 && (R->queue.empty() || S->waiting > 0)) {
+      const bool yield = !R->queue.empty();
+      S->used -= R->held;
+      R->held = 0;
+      lk.unlock();
+      (void)h2_release_workspace(R->A);
+      S->cv_work.notify_all();
+      if (yield) std::this_thread::sleep_for(std::chrono::milliseconds(2));
+      lk.lock();
+    }
+  }
+  if (R->held > 0) {
+    S->used -= R->held;
+    R->held = 0;
   }
 }
 
@@ -191,11 +271,21 @@ double percentile(std::vector<double> v, double p) {
 
 extern "C" {
 
-h2_status h2s_create(int32_t max_slots, h2_server* out) {
+h2_status h2s_create(int64_t budget_bytes, int32_t max_slots, h2_server* out) {
   if (!out) return fail(H2_EINVAL, "out is NULL");
-  if (max_slots < 0) return fail(H2_EINVAL, "max_slots must be >= 0");
+  if (max_slots < 0 || budget_bytes < 0) return fail(H2_EINVAL, "max_slots and budget_bytes must be >= 0");
+  int64_t budget = budget_bytes;
+  if (budget == 0) {
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(H2_EDEVICE, "hipMemGetInfo failed");
+    }
+    budget = (int64_t)(0.85 * (double)freeb);
+  }
   *out = new h2_server_s();
   (*out)->max_slots = max_slots;
+  (*out)->budget = budget;
   return H2_OK;
 }
 
@@ -207,30 +297,30 @@ h2_status h2s_add(h2_server S, h2_matrix A, int32_t slots, int32_t* id) {
   double ab[2];
   h2_status r = h2_interval(A, ab);
   if (r != H2_OK) return r;
-  int32_t cap = 1;
-  r = h2_capacity(A, &cap);
-  if (r != H2_OK) return r;
   h2_stats_t st;
   r = h2_stats(A, &st);
   if (r != H2_OK) return r;
   R->n = st.n;
   R->a0 = ab[0];
   R->b0 = ab[1];
-  R->slots = slots > 0 ? slots : std::max(1, S->max_slots > 0 ? std::min(S->max_slots, cap) : cap);
-  // reserve the workspace of `slots` shifts: the first step of every query,
-  // a multisection of the starting interval
-  r = h2_set_max_shifts(A, R->slots);
+  R->slots = slots > 0 ? slots : (S->max_slots > 0 ? S->max_slots : 64);
+  // workspace of one shift: one factorization at the middle of the starting
+  // interval (its count seeds the records), then the workspace is released
+  r = h2_set_max_shifts(A, 1);
   if (r != H2_OK) return r;
-  std::vector<double> mus(R->slots);
-  std::vector<int64_t> nus(R->slots);
-  std::vector<int32_t> sts(R->slots);
-  for (int j = 0; j < R->slots; ++j) mus[j] = R->a0 + (R->b0 - R->a0) * (j + 1) / (R->slots + 1);
-  r = h2_inertia(A, mus.data(), R->slots, nus.data(), sts.data());
+  const double mu = 0.5 * (R->a0 + R->b0);
+  int64_t nu = 0;
+  int32_t stv = 0;
+  r = h2_inertia(A, &mu, 1, &nu, &stv);
   if (r != H2_OK && r != H2_ENUMERIC) return r;
-  for (int j = 0; j < R->slots; ++j)
-    if (sts[j] == H2_OK) R->records.push_back({mus[j], nus[j]});
+  if (stv == H2_OK) R->records.push_back({mu, nu});
+  r = h2_stats(A, &st);
+  if (r != H2_OK) return r;
+  R->per_shift = std::max<int64_t>(1, st.last_work_bytes + st.last_work_bytes / 10);
+  (void)h2_release_workspace(A);
   std::lock_guard<std::mutex> g(S->mu);
   if (S->stop) return fail(H2_EINVAL, "server is shutting down");
+  if (R->per_shift > S->budget) return fail(H2_ENOMEM, "one shift of this matrix needs more than the server's budget");
   *id = (int32_t)S->mats.size();
   S->mats.push_back(std::move(R));
   Resident* p = S->mats.back().get();
@@ -264,8 +354,15 @@ h2_status h2s_poll(h2_server S, int64_t ticket, double* lambda, int32_t* done) {
   auto it = S->q.find(ticket);
   if (it == S->q.end()) return fail(H2_EINVAL, "unknown ticket");
   *done = it->second.state >= 2 ? 1 : 0;
-  if (it->second.state == 3) return fail(it->second.status, "the query's factorization failed");
-  if (*done && lambda) *lambda = it->second.lambda;
+  if (it->second.state == 3) {
+    const h2_status st = it->second.status;
+    S->q.erase(it);
+    return fail(st, "the query's factorization failed");
+  }
+  if (*done) {
+    if (lambda) *lambda = it->second.lambda;
+    S->q.erase(it);   // a finished ticket is read once
+  }
   return H2_OK;
 }
 
@@ -275,9 +372,14 @@ h2_status h2s_wait(h2_server S, int64_t ticket, double* lambda) {
   auto it = S->q.find(ticket);
   if (it == S->q.end()) return fail(H2_EINVAL, "unknown ticket");
   S->cv_done.wait(lk, [&] { return it->second.state >= 2 || S->stop; });
-  if (it->second.state == 3) return fail(it->second.status, "the query's factorization failed");
+  if (it->second.state == 3) {
+    const h2_status st = it->second.status;
+    S->q.erase(it);
+    return fail(st, "the query's factorization failed");
+  }
   if (it->second.state != 2) return fail(H2_EINVAL, "server stopped");
   if (lambda) *lambda = it->second.lambda;
+  S->q.erase(it);   // a finished ticket is read once
   return H2_OK;
 }
 
@@ -288,6 +390,26 @@ h2_status h2s_stats(h2_server S, double* p50_ms, double* p99_ms, int64_t* served
   if (p99_ms) *p99_ms = percentile(S->lat_ms, 0.99);
   if (served) *served = S->served;
   if (submitted) *submitted = S->submitted;
+  return H2_OK;
+}
+
+h2_status h2s_latency(h2_server S, double* p50_ms, double* p99_ms, int64_t* unfinished, int64_t* budget_bytes,
+                      int64_t* used_bytes) {
+  if (!S) return fail(H2_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> g(S->mu);
+  std::vector<double> v = S->lat_ms;
+  int64_t open = 0;
+  const auto now = Clock::now();
+  for (const auto& kv : S->q)
+    if (kv.second.state < 2) {
+      v.push_back(std::chrono::duration<double, std::milli>(now - kv.second.t_submit).count());
+      ++open;
+    }
+  if (p50_ms) *p50_ms = percentile(v, 0.50);
+  if (p99_ms) *p99_ms = percentile(v, 0.99);
+  if (unfinished) *unfinished = open;
+  if (budget_bytes) *budget_bytes = S->budget;
+  if (used_bytes) *used_bytes = S->used;
   return H2_OK;
 }
 

@@ -65,6 +65,15 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.h2_set_stream.argtypes = [C.c_void_p, C.c_void_p]
     lib.h2_tree_perm.restype = C.c_int
     lib.h2_tree_perm.argtypes = [C.c_void_p, P(C.c_int64)]
+    lib.h2_count.restype = C.c_int
+    lib.h2_count.argtypes = [C.c_void_p, C.c_double, C.c_double, P(C.c_int64)]
+    lib.h2_eigs_in.restype = C.c_int
+    lib.h2_eigs_in.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int64, P(C.c_double),
+                               P(C.c_int64)]
+    lib.h2_gap.restype = C.c_int
+    lib.h2_gap.argtypes = [C.c_void_p, C.c_int64, C.c_double, P(C.c_double), P(C.c_double)]
+    lib.h2_level_stats.restype = C.c_int
+    lib.h2_level_stats.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(C.c_int64)]
     lib.h2_basis_ranks.restype = C.c_int
     lib.h2_basis_ranks.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32)]
     lib.h2_matvec.restype = C.c_int
@@ -100,7 +109,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.h2_free.restype = None
     lib.h2_free.argtypes = [C.c_void_p]
     lib.h2s_create.restype = C.c_int
-    lib.h2s_create.argtypes = [C.c_int32, P(C.c_void_p)]
+    lib.h2s_create.argtypes = [C.c_int64, C.c_int32, P(C.c_void_p)]
+    lib.h2s_latency.restype = C.c_int
+    lib.h2s_latency.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_int64), P(C.c_int64),
+                                P(C.c_int64)]
+    lib.h2_release_workspace.restype = C.c_int
+    lib.h2_release_workspace.argtypes = [C.c_void_p]
     lib.h2s_add.restype = C.c_int
     lib.h2s_add.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, P(C.c_int32)]
     lib.h2s_submit.restype = C.c_int
@@ -121,11 +135,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
 _lib = load_library()
 
 EXPORTED = ["h2_build", "h2_inertia", "h2_inertia_f32", "h2_set_mixed", "h2_kth_eig", "h2_norm", "h2_stats", "h2_set_stream", "h2_tree_perm",
-            "h2_basis_ranks", "h2_matvec", "h2_kernel_matvec",
+            "h2_basis_ranks", "h2_level_stats", "h2_count", "h2_eigs_in", "h2_gap", "h2_matvec", "h2_kernel_matvec",
             "h2_profile_enable", "h2_profile_classes", "h2_profile_class_name", "h2_profile_read",
             "h2_profile_level_ms", "h2_interval", "h2_capacity", "h2_set_max_shifts", "h2_level_dims",
             "h2_set_gemm_tuning", "h2_get_gemm_tuning", "h2_free", "h2_last_error",
-            "h2s_create", "h2s_add", "h2s_submit", "h2s_poll", "h2s_wait", "h2s_stats", "h2s_destroy"]
+            "h2s_create", "h2s_latency", "h2_release_workspace", "h2s_add", "h2s_submit", "h2s_poll", "h2s_wait", "h2s_stats", "h2s_destroy"]
 
 
 def _check(st: int):
@@ -227,6 +241,39 @@ class H2Matrix:
         _check(_lib.h2_tree_perm(self._h, p.ctypes.data_as(C.POINTER(C.c_int64))))
         return p
 
+    def count(self, a: float, b: float) -> int:
+        """Number of eigenvalues of A~ in [a, b)."""
+        c = C.c_int64()
+        _check(_lib.h2_count(self._h, float(a), float(b), C.byref(c)))
+        return int(c.value)
+
+    def eigs_in(self, a: float, b: float, tol: float, cap: int = 1 << 20) -> np.ndarray:
+        """Every eigenvalue of A~ in [a, b), each to absolute tolerance tol."""
+        c = C.c_int64()
+        st = _lib.h2_count(self._h, float(a), float(b), C.byref(c))
+        _check(st)
+        lam = np.zeros(max(1, min(int(cap), int(c.value))))
+        _check(_lib.h2_eigs_in(self._h, float(a), float(b), float(tol), len(lam), _dptr(lam), C.byref(c)))
+        return lam[:int(c.value)]
+
+    def gap(self, k: int, tol: float):
+        """(lambda_k, lambda_{k+1}, lambda_{k+1} - lambda_k), each eigenvalue to tolerance tol."""
+        lam = np.zeros(2)
+        g = C.c_double()
+        _check(_lib.h2_gap(self._h, int(k), float(tol), _dptr(lam), C.byref(g)))
+        return float(lam[0]), float(lam[1]), float(g.value)
+
+    def release_workspace(self):
+        """Free the factorization workspace (the next inertia call allocates it again)."""
+        _check(_lib.h2_release_workspace(self._h))
+
+    def level_stats(self, shift: int = 0) -> np.ndarray:
+        """Per level of the last factorization: (sum t, sum m, max m, sum R) for one shift of its batch."""
+        nlev = self.stats()["levels"] + 1
+        out = np.zeros((nlev, 4), dtype=np.int64)
+        _check(_lib.h2_level_stats(self._h, int(shift), nlev, out.ctypes.data_as(C.POINTER(C.c_int64))))
+        return out
+
     def basis_ranks(self, level: int) -> np.ndarray:
         r = np.zeros(1 << int(level), dtype=np.int32)
         _check(_lib.h2_basis_ranks(self._h, int(level), r.ctypes.data_as(C.POINTER(C.c_int32))))
@@ -305,9 +352,9 @@ class H2Server:
     k-th eigenvalue queries, one worker per matrix.  Holds references to the
     added matrices until close()."""
 
-    def __init__(self, max_slots: int = 0):
+    def __init__(self, max_slots: int = 0, budget_bytes: int = 0):
         h = C.c_void_p()
-        _check(_lib.h2s_create(int(max_slots), C.byref(h)))
+        _check(_lib.h2s_create(int(budget_bytes), int(max_slots), C.byref(h)))
         self._h = h
         self._mats = []
 
@@ -339,6 +386,15 @@ class H2Server:
         served, submitted = C.c_int64(), C.c_int64()
         _check(_lib.h2s_stats(self._h, C.byref(p50), C.byref(p99), C.byref(served), C.byref(submitted)))
         return {"p50_ms": p50.value, "p99_ms": p99.value, "served": served.value, "submitted": submitted.value}
+
+    def latency(self) -> dict:
+        """Censored latency over every submitted query (unfinished ones at their age)."""
+        p50, p99 = C.c_double(), C.c_double()
+        open_, budget, used = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(_lib.h2s_latency(self._h, C.byref(p50), C.byref(p99), C.byref(open_), C.byref(budget),
+                                C.byref(used)))
+        return {"p50_ms": p50.value, "p99_ms": p99.value, "unfinished": open_.value,
+                "budget_bytes": budget.value, "used_bytes": used.value}
 
     def close(self):
         if getattr(self, "_h", None):

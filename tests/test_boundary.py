@@ -118,9 +118,10 @@ def test_server_argument_errors(mod):
     a server with no matrices starts and stops cleanly."""
     L = mod._lib
     h = C.c_void_p()
-    assert L.h2s_create(-1, C.byref(h)) == mod.H2_EINVAL
-    assert L.h2s_create(0, None) == mod.H2_EINVAL
-    assert L.h2s_create(4, C.byref(h)) == mod.H2_OK and h.value
+    assert L.h2s_create(0, -1, C.byref(h)) == mod.H2_EINVAL
+    assert L.h2s_create(-5, 0, C.byref(h)) == mod.H2_EINVAL
+    assert L.h2s_create(0, 0, None) == mod.H2_EINVAL
+    assert L.h2s_create(1 << 30, 4, C.byref(h)) == mod.H2_OK and h.value   # explicit budget: no device query
     i = C.c_int32()
     t = C.c_int64()
     lam = C.c_double()
@@ -138,6 +139,11 @@ def test_server_argument_errors(mod):
     served, sub = C.c_int64(-1), C.c_int64(-1)
     assert L.h2s_stats(h, C.byref(p50), C.byref(p99), C.byref(served), C.byref(sub)) == mod.H2_OK
     assert (p50.value, p99.value, served.value, sub.value) == (0.0, 0.0, 0, 0)
+    open_, budget, used = C.c_int64(-1), C.c_int64(-1), C.c_int64(-1)
+    assert L.h2s_latency(None, None, None, None, None, None) == mod.H2_EINVAL
+    assert L.h2s_latency(h, C.byref(p50), C.byref(p99), C.byref(open_), C.byref(budget), C.byref(used)) == mod.H2_OK
+    assert (open_.value, budget.value, used.value) == (0, 1 << 30, 0)
+    assert L.h2_release_workspace(None) == mod.H2_EINVAL
     L.h2s_destroy(h)
     L.h2s_destroy(None)   # no-op
 

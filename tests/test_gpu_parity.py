@@ -49,6 +49,29 @@ def test_tridiag_closed_form(lib, n, leaf, eta):
     assert np.array_equal(nu, want), (nu - want)
 
 
+@pytest.mark.parametrize("n,leaf", [(32768, 4096), (36000, 4500), (65536, 8192)])
+def test_tridiag_closed_form_large_blocks(lib, n, leaf):
+    """Cluster dimensions of 4096-8192 (the sizes the top levels of the full
+    benchmark reach): every leaf pivot block is panelled, the recompression's
+    Householder panels take their narrow widths (4 and 2 columns), the GEMMs
+    take their largest capacity buckets.  eta = 0.5 makes every leaf eliminate
+    into an admissible pair (exact rank-1 fill-in), so recompression runs on
+    every leaf; the closed-form spectrum fixes every count."""
+    print("case tridiag large n=%d leaf=%d" % (n, leaf), flush=True)
+    A = lib.H2Matrix(W.line_points(n), W.K_TRIDIAG_1D, 2.0, leaf, 0.5, 1e-12, p0=1.0)
+    lam = tridiag_eigs(n)
+    sig = _shifts_with_near_eigs(lam, count=13, seed=5)
+    nu = A.inertia(sig)
+    want = np.array([tridiag_inertia(n, s) for s in sig])
+    assert np.array_equal(nu, want), (nu - want)
+    st = A.level_stats(0)
+    L = st.shape[0] - 1
+    assert st[L, 2] >= leaf - 1 and st[L, 2] > 2048          # leaf cluster dimension
+    assert st[L, 0] >= 1                                      # recompression added directions
+    assert st[L, 3] > 2048 * (1 << L) // 2                    # pivot blocks above 2048 rows
+    A.close()
+
+
 def _windowed_check(nu_gpu, H, sig, ev=None):
     """Windowed inertia parity; returns the number of exact-window matches."""
     w = 1e3 * H.eps * H.normA

@@ -5,6 +5,8 @@ independently of the path: the closed-form spectrum 2 - 2cos(j pi/(n+1)) of the
 second-difference matrix, LAPACK on the dense cube matrix, and a standalone
 h2_kth_eig on the same handle before it was made resident.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -54,7 +56,8 @@ def test_serve_two_matrices_interleaved(lib):
                 tickets.append(("t", ks_t[j], j, S.submit(it, ks_t[j], tol)))
         for which, k, j, tk in tickets:
             lam = S.wait(tk)
-            assert S.poll(tk) == lam
+            with pytest.raises(lib.H2EigError):      # a finished ticket is read once
+                S.poll(tk)
             if which == "a":
                 assert abs(lam - dense[k - 1]) <= bound_a, (k, lam, dense[k - 1])
                 assert abs(lam - alone_a[j]) <= tol + 10 * 1e-8 * A.norm(), (k, lam, alone_a[j])
@@ -89,5 +92,42 @@ def test_serve_one_slot_queue(lib):
         with pytest.raises(lib.H2EigError):
             S.submit(5, 1, tol)
         assert S.stats()["served"] == len(ks)
+    finally:
+        S.close()
+
+
+def test_serve_shared_memory_budget(lib):
+    """Admission by memory: with a budget of one shift of the larger matrix,
+    the two matrices never hold more than the budget together, queries of the
+    other matrix wait until the share is returned, and every answer is still
+    exact (closed-form spectrum)."""
+    print("case serve budget: two tridiag matrices, budget of one shift", flush=True)
+    n1, n2, tol = 2048, 1024, 1e-9
+    T1 = lib.H2Matrix(W.line_points(n1), W.K_TRIDIAG_1D, 2.0, 64, 1.0, 1e-12, p0=1.0)
+    T2 = lib.H2Matrix(W.line_points(n2), W.K_TRIDIAG_1D, 2.0, 32, 1.0, 1e-12, p0=1.0)
+    T1.inertia(np.array([1.37]))
+    per1 = T1.stats()["last_work_bytes"]
+    T1.release_workspace()
+    budget = int(1.5 * per1)
+    S = lib.H2Server(max_slots=4, budget_bytes=budget)
+    try:
+        i1, i2 = S.add(T1), S.add(T2)
+        ks1, ks2 = [1, 700, n1], [5, 512]
+        tk = [(n1, k, S.submit(i1, k, tol)) for k in ks1] + [(n2, k, S.submit(i2, k, tol)) for k in ks2]
+        peak = 0
+        for n, k, t in tk:
+            while True:
+                lat = S.latency()
+                peak = max(peak, lat["used_bytes"])
+                lam = S.poll(t)
+                if lam is not None:
+                    break
+                time.sleep(0.002)
+            exact = tridiag_eigs(n)
+            assert abs(lam - exact[k - 1]) <= tol / 2 + 10 * 1e-12 * 4.0, (n, k, lam)
+        assert lat["budget_bytes"] == budget
+        assert 0 < peak <= budget
+        assert S.stats()["served"] == len(tk)
+        assert S.latency()["unfinished"] == 0
     finally:
         S.close()
