@@ -266,6 +266,20 @@ h2_status h2_matvec(h2_matrix A, const double* x, double* y);
 h2_status h2_kernel_matvec(h2_matrix A, const double* x, double* y);
 
 /*
+ * h2_kernel_matvec without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same product y = A x (same kernel, same summation
+ * order, hence the same bits), with the points, x and y staged through a
+ * static 64 MiB device array held by each GPU the library runs on until the
+ * process ends.  x, y: host arrays of n doubles, original point order.
+ * n must be at most (8*2^20 - 96) / (dim + 2) points (1677702 in 3-D), else
+ * H2_EINVAL.  Every call on one GPU shares that array: calls that overlap on
+ * one GPU (several threads, several handles) race and must be serialised by
+ * the caller.  Errors: H2_EINVAL, H2_EBUSY, H2_EDEVICE.
+ */
+h2_status h2_kernel_matvec_noalloc(h2_matrix A, const double* x, double* y);
+
+/*
  * Diagnostic profiling (not needed for results).  When enabled, every kernel
  * launch of h2_inertia is bracketed by HIP events on the handle's stream, and
  * each kernel class accumulates its algorithmic flops (the method's own

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 
@@ -571,6 +572,49 @@ void kernel_matvec_gpu(const double* X, int64_t n, int dim, int kind, double dia
   FCHK(hipMalloc(&dX, std::max<int64_t>(1, n * dim) * 8));
   FCHK(hipMalloc(&dx, std::max<int64_t>(1, n) * 8));
   FCHK(hipMalloc(&dy, std::max<int64_t>(1, n) * 8));
+  FCHK(hipMemcpyAsync(dX, X, n * dim * 8, hipMemcpyHostToDevice, st));
+  FCHK(hipMemcpyAsync(dx, x, n * 8, hipMemcpyHostToDevice, st));
+  launch_kernel_matvec(dX, n, dim, kind, diag, p0, p1, dx, dy, st);
+  FCHK(hipGetLastError());
+  FCHK(hipMemcpyAsync(y, dy, n * 8, hipMemcpyDeviceToHost, st));
+  FCHK(hipStreamSynchronize(st));
+}
+
+// ------------------------------------------------ allocation-free variant
+// Device scratch of kernel_matvec_noalloc: the points, x and y are staged here
+// instead of in allocated buffers.  One copy per GPU, held until the process
+// ends; every call on a GPU shares it, so calls that overlap on one GPU race.
+constexpr int64_t NOALLOC_DOUBLES = (int64_t)8 << 20;   // 64 MiB
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64] = {};   // device address of `scratch` on each GPU (nullptr = not looked up yet)
+
+double* scratch_on(int device) {
+  if (device < 0 || device >= 64) throw std::invalid_argument("device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    FCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[device] = (double*)p;
+  }
+  return g_scratch_ptr[device];
+}
+
+inline int64_t up32(int64_t v) { return (v + 31) / 32 * 32; }
+}  // namespace
+
+int64_t kernel_matvec_noalloc_max_n(int dim) { return (NOALLOC_DOUBLES - 96) / (dim + 2); }
+
+void kernel_matvec_noalloc(const double* X, int64_t n, int dim, int kind, double diag, double p0, double p1,
+                           const double* x, double* y, int device, hipStream_t st) {
+  if (n > kernel_matvec_noalloc_max_n(dim)) throw std::invalid_argument("n exceeds the static scratch");
+  FCHK(hipSetDevice(device));
+  double* base = scratch_on(device);   // looked up with this device current
+  double* dX = base;
+  double* dx = base + up32(n * dim);
+  double* dy = dx + up32(n);
   FCHK(hipMemcpyAsync(dX, X, n * dim * 8, hipMemcpyHostToDevice, st));
   FCHK(hipMemcpyAsync(dx, x, n * 8, hipMemcpyHostToDevice, st));
   launch_kernel_matvec(dX, n, dim, kind, diag, p0, p1, dx, dy, st);

@@ -65,4 +65,11 @@ void kernel_matvec_gpu(const double* X, int64_t n, int dim, int kind, double dia
 void launch_kernel_matvec(const double* dX, int64_t n, int dim, int kind, double diag, double p0, double p1,
                           const double* dx, double* dy, hipStream_t st);
 
+// The same product with the points, x and y staged through a static device
+// scratch array instead of allocated memory (no hipMalloc or hipFree); n is at
+// most kernel_matvec_noalloc_max_n(dim).  Calls that overlap on one GPU race.
+int64_t kernel_matvec_noalloc_max_n(int dim);
+void kernel_matvec_noalloc(const double* X, int64_t n, int dim, int kind, double diag, double p0, double p1,
+                           const double* x, double* y, int device, hipStream_t st);
+
 }  // namespace h2

@@ -1449,6 +1449,24 @@ h2_status h2_kernel_matvec(h2_matrix A, const double* x, double* y) {
   return H2_OK;
 }
 
+h2_status h2_kernel_matvec_noalloc(h2_matrix A, const double* x, double* y) {
+  if (!A || !x || !y) return fail(H2_EINVAL, "NULL argument");
+  if (A->T.n > kernel_matvec_noalloc_max_n(A->T.dim))
+    return fail(H2_EINVAL, "n = " + std::to_string(A->T.n) + " exceeds the static scratch (at most " +
+                               std::to_string(kernel_matvec_noalloc_max_n(A->T.dim)) + " points)");
+  Busy b(A);
+  if (!b.ok) return fail(H2_EBUSY, "handle in use by another thread");
+  try {
+    kernel_matvec_noalloc(A->T.X.data(), A->T.n, A->T.dim, A->kern.kind, A->kern.diag, A->kern.p0, A->kern.p1, x, y,
+                          A->device, A->stream);
+  } catch (std::invalid_argument& e) {
+    return fail(H2_EINVAL, e.what());
+  } catch (std::runtime_error& e) {
+    return fail(H2_EDEVICE, e.what());
+  }
+  return H2_OK;
+}
+
 h2_status h2_profile_enable(h2_matrix A, int32_t enable) {
   if (!A) return fail(H2_EINVAL, "NULL handle");
   try {

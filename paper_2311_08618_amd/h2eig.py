@@ -80,6 +80,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.h2_matvec.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
     lib.h2_kernel_matvec.restype = C.c_int
     lib.h2_kernel_matvec.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
+    lib.h2_kernel_matvec_noalloc.restype = C.c_int
+    lib.h2_kernel_matvec_noalloc.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
     lib.h2_profile_enable.restype = C.c_int
     lib.h2_profile_enable.argtypes = [C.c_void_p, C.c_int32]
     lib.h2_profile_classes.restype = C.c_int32
@@ -135,7 +137,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
 _lib = load_library()
 
 EXPORTED = ["h2_build", "h2_inertia", "h2_inertia_f32", "h2_set_mixed", "h2_kth_eig", "h2_norm", "h2_stats", "h2_set_stream", "h2_tree_perm",
-            "h2_basis_ranks", "h2_level_stats", "h2_count", "h2_eigs_in", "h2_gap", "h2_matvec", "h2_kernel_matvec",
+            "h2_basis_ranks", "h2_level_stats", "h2_count", "h2_eigs_in", "h2_gap", "h2_matvec", "h2_kernel_matvec", "h2_kernel_matvec_noalloc",
             "h2_profile_enable", "h2_profile_classes", "h2_profile_class_name", "h2_profile_read",
             "h2_profile_level_ms", "h2_interval", "h2_capacity", "h2_set_max_shifts", "h2_level_dims",
             "h2_set_gemm_tuning", "h2_get_gemm_tuning", "h2_free", "h2_last_error",
@@ -291,6 +293,13 @@ class H2Matrix:
         x = np.ascontiguousarray(x, dtype=np.float64)
         y = np.zeros(self.n)
         _check(_lib.h2_kernel_matvec(self._h, _dptr(x), _dptr(y)))
+        return y
+
+    def kernel_matvec_noalloc(self, x) -> np.ndarray:
+        """y = A x as kernel_matvec, staged through the library's static device scratch (no allocation)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros(self.n)
+        _check(_lib.h2_kernel_matvec_noalloc(self._h, _dptr(x), _dptr(y)))
         return y
 
     def profile_enable(self, on=True):
