@@ -39,11 +39,11 @@ GEMM_CLASSES = {"recompress_w", "rotate", "elimination", "schur", "fillin_gram",
 # step-bench workloads: (default n, points(n), kernel, A_ii, leaf, eps, p0, p1, shift range, default batch)
 WORKLOADS = {
     # n points uniform in the unit cube (seed 0), 1/r: the headline configuration at n = 2^18
-    "cube-laplace": (1 << 18, "cube", 0, 1e3, 256, 1e-8, 0.0, 0.0, (900.0, 1100.0), 2),
+    "cube-laplace": (1 << 18, "cube", 0, 1e3, 256, 1e-8, 0.0, 0.0, (900.0, 1100.0), 0),
     # the same points at n = 131072, exp(-r)/r, eps 1e-10
-    "cube-yukawa": (131072, "cube", 1, 1e3, 256, 1e-10, 0.0, 0.0, (900.0, 1100.0), 2),
+    "cube-yukawa": (131072, "cube", 1, 1e3, 256, 1e-10, 0.0, 0.0, (900.0, 1100.0), 0),
     # 2^20 points on 16 parallel cylinders (seed 0), exp(-r^2/0.01)/(r+0.01), A_ii = 10, leaf 512
-    "cylinders-gauss": (1 << 20, "cylinders", 2, 10.0, 512, 1e-8, 0.01, 0.01, (5.0, 15.0), 1),
+    "cylinders-gauss": (1 << 20, "cylinders", 2, 10.0, 512, 1e-8, 0.01, 0.01, (5.0, 15.0), 0),
 }
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2311_08618_amd", "csrc", "kernels.hip")
@@ -303,9 +303,17 @@ def main():
     n, S = args.n or n0, args.batch or S0
     X = W.cube_points(n, 0) if geom == "cube" else W.cylinder_points(n, 0)
     t0 = time.perf_counter()
-    A = H2Matrix(X, kind, diag, leaf, 1.0, eps, p0=p0, p1=p1, max_shifts=S)
+    A = H2Matrix(X, kind, diag, leaf, 1.0, eps, p0=p0, p1=p1, max_shifts=max(S, 1))
     build_s = time.perf_counter() - t0
     print("bench: built n=%d in %.1f s" % (n, build_s), file=sys.stderr, flush=True)
+    if S == 0:
+        # as many shifts per step as the device holds: one shift measures the
+        # workspace of a shift, then the handle's capacity sets the batch
+        A.inertia(W.shift_grid(srange[0], srange[1], 1, seed=0))
+        A.set_max_shifts(0)
+        S = A.capacity()
+        A.set_max_shifts(S)
+        print("bench: %d shift(s) per step" % S, file=sys.stderr, flush=True)
     sig = W.shift_grid(srange[0], srange[1], S, seed=0)
     for w in range(args.warmup):
         A.inertia(sig)

@@ -66,6 +66,12 @@ struct BufTab {
   int64_t ss[NBUF];  // shift stride (elements)
   int64_t bs[NBUF];  // block stride (elements)
   int ld[NBUF];      // leading dimension
+  // Blocks sized by their own clusters (the near and carried fill-in blocks of
+  // the levels above the leaves): block blk starts boff[buf][blk] elements
+  // into the shift's part and has leading dimension bld[buf][blk].  Null:
+  // every block is bs elements with leading dimension ld.
+  const int64_t* boff[NBUF];
+  const int* bld[NBUF];
   unsigned long long* fc;   // algorithmic flop counter of the launch's kernel class (or null)
   unsigned long long* fck;  // second counter, per kernel symbol (GEMM layouts), or null
   int f32;                  // GEMMs of this launch multiply in FP32 (operands rounded, FP32 accumulation)

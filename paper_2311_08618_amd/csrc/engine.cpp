@@ -238,6 +238,7 @@ struct h2_matrix_s {
   int64_t resident = 0;
   // workspace
   Arena sf[2], lvl, mrg, small, rs;
+  Arena tab[2];   // block offset / leading-dimension tables of the blocks in sf[0] / sf[1]
   // slicing cache and statistics
   std::vector<std::pair<double, int64_t>> cache;
   bool have_gersh = false;
@@ -248,6 +249,8 @@ struct h2_matrix_s {
   double g_lo = 0, g_hi = 0;
   h2_stats_t st{};
   int max_shifts = 0;
+  double ws_per_shift = 0.0;   // workspace bytes per shift, from the arenas and the batch they were sized for
+  int arena_shifts = 0;        // largest batch factored since the arenas were last released
   int max_list = 1;        // longest GEMM list of the plan (tile-count scratch)
   int* d_prefix = nullptr;  // per-shift tile counts of the current GEMM launch (in the small arena)
   Profiler prof;
@@ -610,6 +613,10 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
 
   int cap = A->leafcap;
   int cur = 0;  // which sf arena holds the current level
+  // per arena: byte offsets in tab[] of (S offsets, F offsets, S lds, F lds),
+  // and the elements per shift of the S and F blocks
+  size_t blk_tab[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  int64_t blk_tot[2][2] = {{0, 0}, {0, 0}};
   double flops = 0.0;
   int maxdim = cap;
   std::vector<int> hpm;
@@ -626,8 +633,11 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
       throw NoMem{"cluster dimension " + std::to_string(cap) + " exceeds the supported maximum " +
                   std::to_string(hqr_max_rows())};
     const size_t bsz = (size_t)cap * cap;
-    // level buffers
-    size_t nS = (size_t)S * lp.nblk() * bsz, nF = (size_t)S * lp.nfblk() * bsz;
+    // level buffers: at the leaves every block is cap x cap; above, each block
+    // (i, j) is cap_i x cap_j (tables written by the merge below)
+    const size_t perS = l == L ? (size_t)lp.nblk() * bsz : (size_t)blk_tot[cur][0];
+    const size_t perF = l == L ? (size_t)lp.nfblk() * bsz : (size_t)blk_tot[cur][1];
+    size_t nS = (size_t)S * perS, nF = (size_t)S * perF;
     if (l == L) A->sf[cur].ensure((nS + nF) * 8 + 64, st);
     double* dS = (double*)A->sf[cur].p;
     double* dF = dS + nS;
@@ -650,8 +660,15 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
       bt.bs[id] = (int64_t)blk;
       bt.ld[id] = ld;
     };
-    setb(B_S, dS, (size_t)lp.nblk() * bsz, bsz, cap);
-    setb(B_F, dF, (size_t)lp.nfblk() * bsz, bsz, cap);
+    setb(B_S, dS, perS, bsz, cap);
+    setb(B_F, dF, perF, bsz, cap);
+    if (l < L) {
+      const char* tb = (const char*)A->tab[cur].p;
+      bt.boff[B_S] = (const int64_t*)(tb + blk_tab[cur][0]);
+      bt.boff[B_F] = (const int64_t*)(tb + blk_tab[cur][1]);
+      bt.bld[B_S] = (const int*)(tb + blk_tab[cur][2]);
+      bt.bld[B_F] = (const int*)(tb + blk_tab[cur][3]);
+    }
     setb(B_G, dG, (size_t)N * bsz, bsz, cap);
     setb(B_V, dV, (size_t)N * bsz, bsz, cap);
     setb(B_W, dW, (size_t)N * bsz, bsz, cap);
@@ -859,7 +876,46 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
     const int pcap = round_cap(pmax);
     const size_t pbsz = (size_t)pcap * pcap;
     const int other = 1 - cur;
-    size_t nSN = (size_t)S * pp.nblk() * pbsz, nFN = (size_t)S * pp.nfblk() * pbsz;
+    // each parent block (p, q) is cap_p x cap_q, cap_p the rounded largest
+    // dimension of p over the shifts of the batch
+    std::vector<int> pc(Np, 8);
+    for (int s2 = 0; s2 < S; ++s2)
+      for (int p = 0; p < Np; ++p) pc[p] = std::max(pc[p], round_cap(hpm[(size_t)s2 * Np + p]));
+    std::vector<int64_t> offS(std::max(1, pp.nblk())), offF(std::max(1, pp.nfblk()));
+    std::vector<int> ldS(std::max(1, pp.nblk())), ldF(std::max(1, pp.nfblk()));
+    int64_t totS = 0, totF = 0;
+    for (int p = 0; p < Np; ++p) {
+      for (int k = pp.near_ptr[p]; k < pp.near_ptr[p + 1]; ++k) {
+        offS[k] = totS;
+        ldS[k] = pc[p];
+        totS += (int64_t)pc[p] * pc[pp.near_idx[k]];
+      }
+      for (int k = pp.f_ptr[p]; k < pp.f_ptr[p + 1]; ++k) {
+        offF[k] = totF;
+        ldF[k] = pc[p];
+        totF += (int64_t)pc[p] * pc[pp.f_idx[k]];
+      }
+    }
+    {
+      const size_t o0 = 0, o1 = (offS.size() * 8 + 255) & ~(size_t)255;
+      const size_t o2 = o1 + ((offF.size() * 8 + 255) & ~(size_t)255);
+      const size_t o3 = o2 + ((ldS.size() * 4 + 255) & ~(size_t)255);
+      const size_t o4 = o3 + ((ldF.size() * 4 + 255) & ~(size_t)255);
+      A->tab[other].ensure(o4, st);
+      char* tb = (char*)A->tab[other].p;
+      HIPCHK(hipMemcpyAsync(tb + o0, offS.data(), offS.size() * 8, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(tb + o1, offF.data(), offF.size() * 8, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(tb + o2, ldS.data(), ldS.size() * 4, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(tb + o3, ldF.data(), ldF.size() * 4, hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));   // the host vectors go out of scope
+      blk_tab[other][0] = o0;
+      blk_tab[other][1] = o1;
+      blk_tab[other][2] = o2;
+      blk_tab[other][3] = o3;
+      blk_tot[other][0] = std::max<int64_t>(totS, 1);
+      blk_tot[other][1] = std::max<int64_t>(totF, 1);
+    }
+    size_t nSN = (size_t)S * blk_tot[other][0], nFN = (size_t)S * blk_tot[other][1];
     A->sf[other].ensure((nSN + nFN) * 8 + 64, st);
     double* dSN = (double*)A->sf[other].p;
     double* dFN = dSN + nSN;
@@ -873,8 +929,15 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
     double* dTm = dH + nH;
     setb(B_HAT, dH, (size_t)nslot * pbsz, pbsz, pcap);
     setb(B_TMP, dTm, (size_t)nslot * ebsz, ebsz, emax);
-    setb(B_SN, dSN, (size_t)pp.nblk() * pbsz, pbsz, pcap);
-    setb(B_FN, dFN, (size_t)pp.nfblk() * pbsz, pbsz, pcap);
+    setb(B_SN, dSN, (size_t)blk_tot[other][0], pbsz, pcap);
+    setb(B_FN, dFN, (size_t)blk_tot[other][1], pbsz, pcap);
+    {
+      const char* tb = (const char*)A->tab[other].p;
+      bt.boff[B_SN] = (const int64_t*)(tb + blk_tab[other][0]);
+      bt.boff[B_FN] = (const int64_t*)(tb + blk_tab[other][1]);
+      bt.bld[B_SN] = (const int*)(tb + blk_tab[other][2]);
+      bt.bld[B_FN] = (const int*)(tb + blk_tab[other][3]);
+    }
     setb(B_EMAT, A->d_emat[l - 1], 0, (size_t)A->emat_ld[l - 1] * A->emat_ld[l - 1], A->emat_ld[l - 1]);
     for (const MergeChunk& ch : mp.chunks) {
       run(PC_MERGE, [&] { launch_gather(A->dp<GatherItem>(dl.gather) + ch.g0, ch.g1 - ch.g0, bt, sz, pcap, S, st); });
@@ -945,6 +1008,13 @@ int auto_max_shifts(h2_matrix A) {
     (void)hipGetLastError();
     return 4;
   }
+  if (A->ws_per_shift > 0) {
+    // measured: the workspace of the last factorization per shift, against the
+    // free memory plus what the handle's arenas already hold
+    const double held = (double)(A->sf[0].cap + A->sf[1].cap + A->lvl.cap + A->mrg.cap + A->rs.cap);
+    const int s = (int)std::floor(0.92 * ((double)freeb + held) / (1.04 * A->ws_per_shift));
+    return std::max(1, std::min(s, 64));
+  }
   const LevelPlan& lf = A->plan[A->T.L];
   double per = (double)A->leafcap * A->leafcap * 8.0 * (lf.nblk() + 4.0 * lf.N + lf.max_slot_m + 2.0 * lf.max_slot_p);
   per *= 2.2;  // upper levels and merge buffers
@@ -963,6 +1033,7 @@ h2_status run_inertia(h2_matrix A, const double* sigma, int64_t ns, bool f32, in
     try {
       int md = 0;
       factor_batch(A, sigma + s0, S, f32, nu + s0, status ? status + s0 : nullptr, nullptr, &md);
+      A->arena_shifts = std::max(A->arena_shifts, S);
       A->st.last_rank_max = std::max(A->st.last_rank_max, md);
     } catch (NoMem&) {
       if (S == 1) throw;
@@ -972,6 +1043,8 @@ h2_status run_inertia(h2_matrix A, const double* sigma, int64_t ns, bool f32, in
       A->lvl.release();
       A->mrg.release();
       A->rs.release();
+      for (auto& a : A->tab) a.release();
+      A->arena_shifts = 0;
       continue;
     }
     for (int k = 0; k < S; ++k) {
@@ -985,6 +1058,7 @@ h2_status run_inertia(h2_matrix A, const double* sigma, int64_t ns, bool f32, in
   (void)t0;
   int64_t ws = (int64_t)(A->sf[0].cap + A->sf[1].cap + A->lvl.cap + A->mrg.cap + A->small.cap + A->rs.cap);
   A->st.last_work_bytes = ws;
+  if (A->arena_shifts > 0) A->ws_per_shift = (double)ws / (double)A->arena_shifts;
   return anybad ? H2_ENUMERIC : H2_OK;
 }
 
@@ -1281,6 +1355,8 @@ h2_status h2_release_workspace(h2_matrix A) {
   A->lvl.release();
   A->mrg.release();
   A->rs.release();
+  for (auto& a : A->tab) a.release();
+  A->arena_shifts = 0;
   return H2_OK;
 }
 
@@ -1514,6 +1590,7 @@ void h2_free(h2_matrix A) {
   A->mrg.release();
   A->small.release();
   A->rs.release();
+  for (auto& a : A->tab) a.release();
   if (A->d_bres) (void)hipFree(A->d_bres);
   for (auto p : A->d_cpl)
     if (p) (void)hipFree(p);

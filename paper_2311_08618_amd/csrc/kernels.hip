@@ -17,8 +17,12 @@
 
 namespace h2 {
 
+// leading dimension of block blk of buffer buf
+__device__ inline int ldof(const BufTab& bt, int buf, int blk) { return bt.bld[buf] ? bt.bld[buf][blk] : bt.ld[buf]; }
+
 __device__ inline double* addr(const BufTab& bt, int buf, int blk, int s, int row, int col) {
-  return bt.p[buf] + (int64_t)s * bt.ss[buf] + (int64_t)blk * bt.bs[buf] + row + (int64_t)col * bt.ld[buf];
+  const int64_t off = bt.boff[buf] ? bt.boff[buf][blk] : (int64_t)blk * bt.bs[buf];
+  return bt.p[buf] + (int64_t)s * bt.ss[buf] + off + row + (int64_t)col * ldof(bt, buf, blk);
 }
 
 __device__ inline void ref_origin(const Ref& r, const SizeTab& z, int s, int* row, int* col) {
@@ -167,7 +171,7 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
     ref_origin(tm.b, sz, s, &br, &bc);
     const double* A = addr(bt, tm.a.buf, tm.a.blk, s, ar, ac);
     const double* B = addr(bt, tm.b.buf, tm.b.blk, s, br, bc);
-    const int lda = bt.ld[tm.a.buf], ldb = bt.ld[tm.b.buf];
+    const int lda = ldof(bt, tm.a.buf, tm.a.blk), ldb = ldof(bt, tm.b.buf, tm.b.blk);
     const double* w = tm.wbuf >= 0 ? addr(bt, tm.wbuf, 0, s, 0, 0) + (int64_t)tm.wblk * bt.bs[tm.wbuf] : nullptr;
     const int nk = (K + GK - 1) / GK;
     // this thread's NE elements of each tile: A as (mm, kk), B as (kk, nn)
@@ -232,8 +236,9 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
   }
   int cr, cc;
   ref_origin(it.c, sz, s, &cr, &cc);
-  double* C = addr(bt, it.c.buf, it.c.blk >= 0 ? it.c.blk : idx + slot_base, s, 0, 0);
-  const int ldc = bt.ld[it.c.buf];
+  const int cblk = it.c.blk >= 0 ? it.c.blk : idx + slot_base;
+  double* C = addr(bt, it.c.buf, cblk, s, 0, 0);
+  const int ldc = ldof(bt, it.c.buf, cblk);
   double* C2 = nullptr;
   int ldc2 = 0;
   const bool seg = it.c2.buf == SEG_OUT;
@@ -246,7 +251,7 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
     int r2, c2;
     ref_origin(it.c2, sz, s, &r2, &c2);
     C2 = addr(bt, it.c2.buf, it.c2.blk, s, r2, c2);
-    ldc2 = bt.ld[it.c2.buf];
+    ldc2 = ldof(bt, it.c2.buf, it.c2.blk);
   }
   for (int i = 0; i < FWM; ++i)
     for (int j = 0; j < FWN; ++j)
@@ -313,14 +318,14 @@ __global__ __launch_bounds__(256) void k_copyback_t(const CopyItem* __restrict__
   int r0, c0;
   ref_origin(it.x, sz, s, &r0, &c0);
   double* X = addr(bt, it.x.buf, it.x.blk, s, r0, c0);
-  const int ldx = bt.ld[it.x.buf];
+  const int ldx = ldof(bt, it.x.buf, it.x.blk);
   const double* Sc;
   int lds;
   if (it.src.buf >= 0) {   // from a block
     int sr, sc;
     ref_origin(it.src, sz, s, &sr, &sc);
     Sc = addr(bt, it.src.buf, it.src.blk, s, sr, sc);
-    lds = bt.ld[it.src.buf];
+    lds = ldof(bt, it.src.buf, it.src.blk);
   } else {                 // from the item's scratch slot
     Sc = addr(bt, B_RS, (int)blockIdx.y + slot_base, s, 0, 0);
     lds = bt.ld[B_RS];
@@ -347,7 +352,7 @@ __global__ void k_matsum(const SumItem* __restrict__ items, const int* __restric
   const SumItem it = items[blockIdx.y];
   const int M = dev_eval(it.M, sz, s), N = dev_eval(it.N, sz, s);
   double* C = addr(bt, it.cbuf, it.cblk, s, 0, 0);
-  const int ldc = bt.ld[it.cbuf];
+  const int ldc = ldof(bt, it.cbuf, it.cblk);
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)M * N; e += (int64_t)gridDim.x * blockDim.x) {
     int r = (int)(e % M), c = (int)(e / M);
     double acc = 0.0;
@@ -368,7 +373,7 @@ __global__ void k_copyback(const CopyItem* __restrict__ items, BufTab bt, SizeTa
   int r0, c0;
   ref_origin(it.x, sz, s, &r0, &c0);
   double* X = addr(bt, it.x.buf, it.x.blk, s, r0, c0);
-  const int ldx = bt.ld[it.x.buf];
+  const int ldx = ldof(bt, it.x.buf, it.x.blk);
   const double* Sc = addr(bt, B_RS, (int)blockIdx.y + slot_base, s, 0, 0);
   const int lds = bt.ld[B_RS];
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)M * N; e += (int64_t)gridDim.x * blockDim.x) {
@@ -1008,11 +1013,12 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl_panel(const int* __restrict
     if (tid == 0) { sz.a0[s * N + i] = kstart; sz.a1[s * N + i] = 0; }
     return;
   }
-  const int ld = bt.ld[B_S];
+  const int ld = ldof(bt, B_S, diag_blk[i]);  // the pivot block
+  const int ldw = bt.ld[B_W], ldz = bt.ld[B_Z];
   double* A = addr(bt, B_S, diag_blk[i], s, 0, 0);
   double* Wp = addr(bt, B_W, i, s, 0, 0);     // panel W = L D columns, LDL_NB + 2 columns
   double* pz = addr(bt, B_Z, i, s, 0, 0);     // perm (col 0), pivot sizes (col 1)
-  const int cap = ld;
+  const int cap = ldw;                        // the level's capacity: the panel width the host plans with
   __shared__ double red[16];
   __shared__ int redi[16];
   __shared__ int s_bad;
@@ -1024,9 +1030,9 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl_panel(const int* __restrict
   const int k0 = kstart;
   int k = k0, jw = 0;
   while (jw < NB && k < R) {
-    double* w = Wp + (int64_t)jw * ld;
-    double* u = Wp + (int64_t)(jw + 1) * ld;
-    if (tid < jw) wr[tid] = Wp[k + (int64_t)tid * ld];
+    double* w = Wp + (int64_t)jw * ldw;
+    double* u = Wp + (int64_t)(jw + 1) * ldw;
+    if (tid < jw) wr[tid] = Wp[k + (int64_t)tid * ldw];
     __syncthreads();
     ldl_lazy_col(A, ld, k, k0, jw, k, R, w, wr, tid);
     __syncthreads();
@@ -1039,7 +1045,7 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl_panel(const int* __restrict
     if (fmax(absakk, colmax) == 0.0 || !(absakk == absakk)) {
       if (tid == 0) s_bad = 1;
     } else if (absakk < alpha * colmax) {
-      if (tid < jw) wr[tid] = Wp[imax + (int64_t)tid * ld];
+      if (tid < jw) wr[tid] = Wp[imax + (int64_t)tid * ldw];
       __syncthreads();
       ldl_lazy_col(A, ld, imax, k0, jw, k, R, u, wr, tid);
       __syncthreads();
@@ -1068,9 +1074,9 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl_panel(const int* __restrict
         A[kp + (int64_t)j * ld] = x;
       }
       for (int c = tid; c < jw + 2; c += LDL_THREADS) {
-        double x = Wp[kk + (int64_t)c * ld];
-        Wp[kk + (int64_t)c * ld] = Wp[kp + (int64_t)c * ld];
-        Wp[kp + (int64_t)c * ld] = x;
+        double x = Wp[kk + (int64_t)c * ldw];
+        Wp[kk + (int64_t)c * ldw] = Wp[kp + (int64_t)c * ldw];
+        Wp[kp + (int64_t)c * ldw] = x;
       }
       __syncthreads();
       for (int a = tid; a < R; a += LDL_THREADS) {
@@ -1091,7 +1097,7 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl_panel(const int* __restrict
       for (int a = k + 1 + tid; a < R; a += LDL_THREADS) A[a + (int64_t)k * ld] = w[a] * inv;
       if (tid == 0) {
         A[k + (int64_t)k * ld] = dk;
-        pz[k + ld] = 1.0;
+        pz[k + ldz] = 1.0;
       }
       __syncthreads();
       k += 1;
@@ -1110,8 +1116,8 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl_panel(const int* __restrict
         A[k + (int64_t)k * ld] = a11;
         A[k + 1 + (int64_t)k * ld] = a21;
         A[k + 1 + (int64_t)(k + 1) * ld] = a22;
-        pz[k + ld] = 2.0;
-        pz[k + 1 + ld] = 0.0;
+        pz[k + ldz] = 2.0;
+        pz[k + 1 + ldz] = 0.0;
       }
       __syncthreads();
       k += 2;
@@ -1141,7 +1147,7 @@ __global__ __launch_bounds__(LDL_THREADS) void k_ldl_prep(const int* __restrict_
   const int R = sz.R[s * N + i];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (R <= 0) return;
-  const int ld = bt.ld[B_S];
+  const int ld = ldof(bt, B_S, diag_blk[i]);
   double* A = addr(bt, B_S, diag_blk[i], s, 0, 0);
   double* pz = addr(bt, B_Z, i, s, 0, 0);
   const int ldz = bt.ld[B_Z];
@@ -1206,7 +1212,7 @@ __global__ __launch_bounds__(64) void k_diag_inv(const int* __restrict__ cluster
   const int r0 = blockIdx.x * INV_NB;
   if (r0 >= R) return;
   const int nb = min(INV_NB, R - r0);
-  const int ld = bt.ld[B_S];
+  const int ld = ldof(bt, B_S, diag_blk[i]);
   const double* A = addr(bt, B_S, diag_blk[i], s, r0, r0);
   double* X = addr(bt, B_V, i, s, r0, r0);
   const int ldx = bt.ld[B_V];
@@ -1339,7 +1345,7 @@ __global__ void k_merge_nn(const GatherItem* __restrict__ items, BufTab bt, Size
   const double* H = addr(bt, B_HAT, g.out_blk, s, 0, 0);
   const int ldh = bt.ld[B_HAT];
   double* O = addr(bt, g.dst_buf, g.dst_blk, s, 0, 0);
-  const int ldo = bt.ld[g.dst_buf];
+  const int ldo = ldof(bt, g.dst_buf, g.dst_blk);
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)tnp * tnq; e += (int64_t)gridDim.x * blockDim.x) {
     const int row = (int)(e % tnp), col = (int)(e / tnp);
     O[row + (int64_t)col * ldo] = H[row + (int64_t)col * ldh];
