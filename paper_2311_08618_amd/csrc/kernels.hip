@@ -125,8 +125,9 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
   constexpr int FWN = HN / 16;      // MFMA blocks per wave, columns
   constexpr int NE = T * GK / NT;   // elements of each operand tile a thread stages
   static_assert(NE * NT == T * GK, "operand tile must split evenly over the threads");
-  __shared__ CT As[2][GK][T + 1];
-  __shared__ CT Bs[2][GK][T + 1];
+  __shared__ CT ABs[2][2][GK][T + 1];   // [A or B][LDS buffer][k][m or n], one array: the epilogue reuses all of it
+  CT(&As)[2][GK][T + 1] = ABs[0];
+  CT(&Bs)[2][GK][T + 1] = ABs[1];
   for (int tile = lw; tile < total; tile += G) {
   int lo = 0, hi = nitems - 1;   // the item: the last i with pre[i] <= tile
   while (lo < hi) {
@@ -253,36 +254,117 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
     C2 = addr(bt, it.c2.buf, it.c2.blk, s, r2, c2);
     ldc2 = ldof(bt, it.c2.buf, it.c2.blk);
   }
-  for (int i = 0; i < FWM; ++i)
-    for (int j = 0; j < FWN; ++j)
-      for (int v = 0; v < 4; ++v) {
-        // output row of register v: FP64 MFMA puts D[i][j] in lane j + 16*(i%4),
-        // register i/4; FP32 MFMA in lane j + 16*(i/4), register i%4
-        int r = m0 + wm * HM + i * 16 + (F32 ? 4 * (lane >> 4) + v : (lane >> 4) + 4 * v);
-        int c = n0 + wn * HN + j * 16 + (lane & 15);
-        if (r < M && c < N) {
-          double x = it.alpha * (double)acc[i][j][v];
-          const int dr = r < rs ? cr + r : r2o + (r - rs), dcol = c < cs ? cc + c : c2o + (c - cs);
-          double* p = C + dr + (int64_t)dcol * ldc;
-          *p = it.beta != 0.0 ? it.beta * *p + x : x;
-          if (C2) {
-            double* q = C2 + c + (int64_t)r * ldc2;
-            *q = it.beta != 0.0 ? it.beta * *q + x : x;
+  if constexpr (T == 64) {
+    // Epilogue through LDS (the operand buffers, free after the last K step):
+    // the tile goes to LDS column chunk by column chunk, then every wave reads
+    // back whole columns (C, column-major) or whole row segments (the
+    // transposed twin C2), so that global reads and writes are contiguous; each
+    // thread loads all the old values it updates before it stores any.
+    constexpr int CW = (T == 64 && !F32) ? 64 : 32;  // columns per chunk
+    constexpr int LDT = T + 1;                       // LDS column stride (doubles)
+    constexpr int PER = T * CW / NT;                 // elements per thread per chunk
+    static_assert(CW * LDT * sizeof(double) <= sizeof(ABs), "chunk must fit in the operand buffers");
+    static_assert(PER * NT == T * CW && PER % 8 == 0, "chunk must split evenly over the threads");
+    static_assert(NT % T == 0 && NT % CW == 0, "thread mapping of the epilogue");
+    double* Ls = reinterpret_cast<double*>(&ABs[0][0][0][0]);
+    const double alpha = it.alpha, beta = it.beta;
+    for (int cb = 0; cb < T; cb += CW) {
+      if (n0 + cb >= N) break;
+      // registers -> LDS (local row r, local column c - cb)
+      for (int i = 0; i < FWM; ++i)
+        for (int j = 0; j < FWN; ++j) {
+          const int cl = wn * HN + j * 16 + (lane & 15) - cb;
+          if (cl < 0 || cl >= CW) continue;
+          for (int v = 0; v < 4; ++v) {
+            const int rl = wm * HM + i * 16 + (F32 ? 4 * (lane >> 4) + v : (lane >> 4) + 4 * v);
+            Ls[rl + cl * LDT] = alpha * (double)acc[i][j][v];
+          }
+        }
+      __syncthreads();
+      // C: consecutive threads take consecutive rows of a column
+      {
+        // the row is fixed per thread (NT is a multiple of T); the column steps by NT / T
+        const int rl = tid % T, r = m0 + rl;
+        const int dr = r < rs ? cr + r : r2o + (r - rs);
+        constexpr int CSTEP = NT / T;
+  #pragma unroll
+        for (int h = 0; h < PER; h += 8) {
+          double old[8];
+  #pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int cl = tid / T + (h + u) * CSTEP, c = n0 + cb + cl;
+            old[u] = 0.0;
+            if (beta != 0.0 && r < M && c < N) {
+              const int dcol = c < cs ? cc + c : c2o + (c - cs);
+              old[u] = C[dr + (int64_t)dcol * ldc];
+            }
+          }
+  #pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int cl = tid / T + (h + u) * CSTEP, c = n0 + cb + cl;
+            if (r < M && c < N) {
+              const int dcol = c < cs ? cc + c : c2o + (c - cs);
+              C[dr + (int64_t)dcol * ldc] = beta * old[u] + Ls[rl + cl * LDT];
+            }
           }
         }
       }
+      // C2 = the tile transposed: consecutive threads take consecutive columns of a row
+      if (C2) {
+        // the column is fixed per thread (NT is a multiple of CW); the row steps by NT / CW
+        const int cl = tid % CW, c = n0 + cb + cl;
+        constexpr int RSTEP = NT / CW;
+  #pragma unroll
+        for (int h = 0; h < PER; h += 8) {
+          double old[8];
+  #pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int rl = tid / CW + (h + u) * RSTEP, r = m0 + rl;
+            old[u] = (beta != 0.0 && r < M && c < N) ? C2[c + (int64_t)r * ldc2] : 0.0;
+          }
+  #pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int rl = tid / CW + (h + u) * RSTEP, r = m0 + rl;
+            if (r < M && c < N) C2[c + (int64_t)r * ldc2] = beta * old[u] + Ls[rl + cl * LDT];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  } else {
+    // 128 x 128 tiles: every element read-modified-written from registers
+    // (staging 128 columns through LDS would not fit beside the operands)
+    for (int i = 0; i < FWM; ++i)
+      for (int j = 0; j < FWN; ++j)
+        for (int v = 0; v < 4; ++v) {
+          // output row of register v: FP64 MFMA puts D[i][j] in lane j + 16*(i%4),
+          // register i/4; FP32 MFMA in lane j + 16*(i/4), register i%4
+          const int r = m0 + wm * HM + i * 16 + (F32 ? 4 * (lane >> 4) + v : (lane >> 4) + 4 * v);
+          const int c = n0 + wn * HN + j * 16 + (lane & 15);
+          if (r < M && c < N) {
+            const double x = it.alpha * (double)acc[i][j][v];
+            const int dr = r < rs ? cr + r : r2o + (r - rs), dcol = c < cs ? cc + c : c2o + (c - cs);
+            double* p = C + dr + (int64_t)dcol * ldc;
+            *p = it.beta != 0.0 ? it.beta * *p + x : x;
+            if (C2) {
+              double* q = C2 + c + (int64_t)r * ldc2;
+              *q = it.beta != 0.0 ? it.beta * *q + x : x;
+            }
+          }
+        }
+  }
   }
 }
 
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm(const GItem* __restrict__ items, int nitems,
+__global__ __launch_bounds__(256, 4) void k_gemm(const GItem* __restrict__ items, int nitems,
                                               const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
                                               const int* __restrict__ prefix, int slot_base) {
   gemm_body<TA, TB, false, 64, 2, 2>(items, nitems, terms, bt, sz, prefix, slot_base);
 }
 
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm_f32(const GItem* __restrict__ items, int nitems,
+__global__ __launch_bounds__(256, 4) void k_gemm_f32(const GItem* __restrict__ items, int nitems,
                                                   const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
                                                   const int* __restrict__ prefix, int slot_base) {
   gemm_body<TA, TB, true, 64, 2, 2>(items, nitems, terms, bt, sz, prefix, slot_base);
@@ -291,14 +373,14 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const GItem* __restrict__ item
 // 128 x 128 output tiles on eight waves: twice the arithmetic per operand byte
 // of the 64 x 64 tile, at two resident workgroups per CU, for large blocks
 template <bool TA, bool TB>
-__global__ __launch_bounds__(512, 4) void k_gemm128(const GItem* __restrict__ items, int nitems,
+__global__ __launch_bounds__(512) void k_gemm128(const GItem* __restrict__ items, int nitems,
                                                  const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
                                                  const int* __restrict__ prefix, int slot_base) {
   gemm_body<TA, TB, false, 128, 2, 4>(items, nitems, terms, bt, sz, prefix, slot_base);
 }
 
 template <bool TA, bool TB>
-__global__ __launch_bounds__(512, 4) void k_gemm128_f32(const GItem* __restrict__ items, int nitems,
+__global__ __launch_bounds__(512) void k_gemm128_f32(const GItem* __restrict__ items, int nitems,
                                                      const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
                                                      const int* __restrict__ prefix, int slot_base) {
   gemm_body<TA, TB, true, 128, 2, 4>(items, nitems, terms, bt, sz, prefix, slot_base);
