@@ -108,7 +108,10 @@ h2_status h2_inertia(h2_matrix A, const double* sigma, int64_t nshift,
  * Sec. 3.3) multiplied in FP32 on the matrix cores with FP32 accumulation;
  * operands and results stay FP64 in memory, and the recompression (rank
  * decisions, Sec. 3.4) and the pivot-block LDL with its negative count run in
- * FP64.  Meant for shifts far from every eigenvalue (early bisection steps):
+ * FP64.  Recompression truncates at max(eps, 1e-6) * normA instead of
+ * eps * normA: rounding noise of the FP32 contractions (about 1e-7 of the
+ * fill-in) is not kept as new directions, and the counts are those of a matrix
+ * within about 1e-6 * normA of A~.  Meant for shifts far from every eigenvalue (early bisection steps):
  * a count may differ from h2_inertia's when an eigenvalue lies within the
  * FP32 error of sigma.  Arguments and errors as h2_inertia.  The counts do
  * not join the handle's record cache.

@@ -256,6 +256,7 @@ struct h2_matrix_s {
   Profiler prof;
   int* d_more = nullptr;   // per-iteration "more panels needed" counters + colour maxima
   std::vector<double*> d_tau2;   // per level: squared truncation budget tau^2 * |cluster| / n of every cluster
+  std::vector<double*> d_tau2_f32;   // the same for FP32 factorizations, with tau = max(eps, EPS_F32) * normA
   int* h_more = nullptr;   // pinned host copy (4 ints)
 
   template <class T>
@@ -526,6 +527,15 @@ struct Work {
 
 inline int round_cap(int v) { return std::max(8, (v + 7) & ~7); }
 
+// Truncation budget of FP32 factorizations, relative to normA.  They serve
+// bisection steps on brackets at least switch_rel * normA wide (1e-4 by
+// default), whose decisions a perturbation of the matrix by about 1e-6 * normA
+// changes only for shifts that close to an eigenvalue; the FP64 counts taken
+// at the switch repair such decisions.  A budget near the FP32 rounding level
+// of the contractions (about 1e-7 of the fill-in) would make recompression
+// keep rounding noise as new directions.
+constexpr double EPS_F32 = 1e-6;
+
 // Counters of the blocked factorizations: one "more panels needed" slot per
 // iteration (zeroed once per loop, read back only every few iterations, so
 // that the host rarely waits for the device), then two slots for colour maxima.
@@ -770,7 +780,9 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
         const int nit = std::min(MORE_SLOTS, cap / PCHOL_NB + 2);
         HIPCHK(hipMemsetAsync(A->d_more, 0, nit * sizeof(int), st));
         for (int it = 0; it < nit; ++it) {
-          run(PC_PCHOL, [&] { launch_pchol_panel(cl, dc.ncl, bt, sz, A->d_tau2[l], A->d_more + it, cap, S, st); });
+          run(PC_PCHOL, [&] {
+            launch_pchol_panel(cl, dc.ncl, bt, sz, f32 ? A->d_tau2_f32[l] : A->d_tau2[l], A->d_more + it, cap, S, st);
+          });
           gl(PC_PCHOL_UPD, GEMM_NT, dc.pc_upd);
           if (it % 4 == 3 || it == nit - 1) {
             read_back(A, A->d_more + it, 1, st);
@@ -1138,11 +1150,19 @@ h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern,
     A->leafcap = round_cap(A->leafcap);
     HIPCHK(hipMalloc(&A->d_more, (MORE_SLOTS + 4) * sizeof(int)));
     A->d_tau2.assign(L + 1, nullptr);
+    A->d_tau2_f32.assign(L + 1, nullptr);
+    const double tau32 = std::max(eps, EPS_F32) * A->normA;
     for (int l = 0; l <= L; ++l) {
-      std::vector<double> t2(1 << l);
-      for (int i = 0; i < (1 << l); ++i) t2[i] = A->tau * A->tau * (double)A->T.size[l][i] / (double)A->T.n;
+      std::vector<double> t2(1 << l), t32(1 << l);
+      for (int i = 0; i < (1 << l); ++i) {
+        const double share = (double)A->T.size[l][i] / (double)A->T.n;
+        t2[i] = A->tau * A->tau * share;
+        t32[i] = tau32 * tau32 * share;
+      }
       HIPCHK(hipMalloc(&A->d_tau2[l], t2.size() * sizeof(double)));
       HIPCHK(hipMemcpy(A->d_tau2[l], t2.data(), t2.size() * sizeof(double), hipMemcpyHostToDevice));
+      HIPCHK(hipMalloc(&A->d_tau2_f32[l], t32.size() * sizeof(double)));
+      HIPCHK(hipMemcpy(A->d_tau2_f32[l], t32.data(), t32.size() * sizeof(double), hipMemcpyHostToDevice));
     }
     HIPCHK(hipHostMalloc(&A->h_more, 4 * sizeof(int)));
     upload_plan(A);
@@ -1600,6 +1620,8 @@ void h2_free(h2_matrix A) {
   A->prof.release();
   if (A->d_more) (void)hipFree(A->d_more);
   for (double* p : A->d_tau2)
+    if (p) (void)hipFree(p);
+  for (double* p : A->d_tau2_f32)
     if (p) (void)hipFree(p);
   if (A->h_more) (void)hipHostFree(A->h_more);
   if (A->own_stream) (void)hipStreamDestroy(A->own_stream);
