@@ -4,6 +4,7 @@ and the bench's use of a committed counter record only while it matches the
 kernel, the workload and the kernel source."""
 import hashlib
 import os
+import re
 
 import pytest
 
@@ -67,5 +68,13 @@ def test_committed_traffic_record_matches_committed_kernels():
     h = hashlib.sha256(open(bench.KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
     if h not in txt:
         pytest.skip("counter record predates the current kernels.hip: traffic is reported as null")
-    assert any(bench.measured_traffic(k, n, s) is not None
-               for k in ("h2::k_gemm<false, true>",) for n in (262144,) for s in (1, 2, 3, 4))
+    fields = dict(re.findall(r"^- (\w+): (.+)$", txt, flags=re.M))
+    kernel, n, S = fields["kernel"].strip(), int(fields["n"]), int(fields["shifts_per_step"])
+    assert kernel.startswith("h2::k_gemm")
+    got = bench.measured_traffic(kernel, n, S)
+    assert got is not None and got > 0
+    # the stored total is the two scaled counters
+    want = 1024.0 * (float(fields["fetch_kib_per_dispatch"]) * float(fields["fetch_scale"])
+                     + float(fields["write_kib_per_dispatch"]) * float(fields["write_scale"]))
+    assert abs(got - want) <= 1e-3 * want
+    assert bench.measured_traffic(kernel, n + 1, S) is None and bench.measured_traffic(kernel, n, S + 1) is None
