@@ -104,9 +104,12 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const GItem* __restrict__ it
 // in memory; F32 converts the operands to FP32 on their way into LDS and
 // multiplies them on FP32 MFMA with FP32 accumulation (the early bisection
 // steps), else everything is FP64.  Output tiles are T x T (64 or 128), WM x WN
-// waves (64 x 64: 2 x 2 waves of 32 x 32; 128 x 128: 2 x 4 waves of 64 x 32, so
-// that two workgroups of eight waves share a CU), each wave computing its part
-// as FWM x FWN MFMA blocks of 16 x 16.
+// waves (64 x 64: 2 x 2 waves of 32 x 32; 128 x 128: 2 x 4 waves of 64 x 32),
+// each wave computing its part as FWM x FWN MFMA blocks of 16 x 16.  Per-K
+// weights (the signs of the scaled pivots in the Schur and fill-in products)
+// travel through LDS beside the operand tiles and scale the A fragments there:
+// applied to the values in flight from global memory they would make every
+// slab wait for its loads before the products of the previous slab.
 template <bool TA, bool TB, bool F32, int T, int WM, int WN>
 __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int nitems, const GTerm* __restrict__ terms,
                                           const BufTab& bt, const SizeTab& sz, const int* __restrict__ prefix,
@@ -126,6 +129,7 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
   constexpr int NE = T * GK / NT;   // elements of each operand tile a thread stages
   static_assert(NE * NT == T * GK, "operand tile must split evenly over the threads");
   __shared__ CT ABs[2][2][GK][T + 1];   // [A or B][LDS buffer][k][m or n], one array: the epilogue reuses all of it
+  __shared__ CT Ws[2][GK];              // per-K weights of the current term (1 when it has none), per LDS buffer
   CT(&As)[2][GK][T + 1] = ABs[0];
   CT(&Bs)[2][GK][T + 1] = ABs[1];
   for (int tile = lw; tile < total; tile += G) {
@@ -175,8 +179,12 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
     const int lda = ldof(bt, tm.a.buf, tm.a.blk), ldb = ldof(bt, tm.b.buf, tm.b.blk);
     const double* w = tm.wbuf >= 0 ? addr(bt, tm.wbuf, 0, s, 0, 0) + (int64_t)tm.wblk * bt.bs[tm.wbuf] : nullptr;
     const int nk = (K + GK - 1) / GK;
-    // this thread's NE elements of each tile: A as (mm, kk), B as (kk, nn)
+    // this thread's NE elements of each tile: A as (mm, kk), B as (kk, nn); the
+    // first GK threads also carry the slab's weights.  Loaded values are only
+    // moved into LDS after the products of the current slab, so no arithmetic
+    // may depend on them here (it would wait for the loads in flight).
     double ra[NE], rb[NE];
+    double rw = 1.0;
     auto gload = [&](int kt) {
       const int k0 = kt * GK;
 #pragma unroll
@@ -186,16 +194,14 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
         if (TA) { kk = e % GK; mm = e / GK; } else { mm = e % T; kk = e / T; }
         const int gm = m0 + mm, gk = k0 + kk;
         double v = 0.0;
-        if (gm < M && gk < K) {
-          v = TA ? A[gk + (int64_t)gm * lda] : A[gm + (int64_t)gk * lda];
-          if (w) v *= w[gk];
-        }
+        if (gm < M && gk < K) v = TA ? A[gk + (int64_t)gm * lda] : A[gm + (int64_t)gk * lda];
         ra[r] = v;
         int nn, kb;
         if (TB) { nn = e % T; kb = e / T; } else { kb = e % GK; nn = e / GK; }
         const int gn = n0 + nn, gkb = k0 + kb;
         rb[r] = (gn < N && gkb < K) ? (TB ? B[gn + (int64_t)gkb * ldb] : B[gkb + (int64_t)gn * ldb]) : 0.0;
       }
+      if (w && tid < GK) rw = k0 + tid < K ? w[k0 + tid] : 0.0;
     };
     auto sstore = [&](int buf) {
 #pragma unroll
@@ -208,6 +214,7 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
         if (TB) { nn = e % T; kb = e / T; } else { kb = e % GK; nn = e / GK; }
         Bs[buf][kb][nn] = (CT)rb[r];
       }
+      if (tid < GK) Ws[buf][tid] = (CT)rw;
     };
     gload(0);
     sstore(0);
@@ -221,6 +228,11 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
         CT a[FWM], b[FWN];
 #pragma unroll
         for (int f = 0; f < FWM; ++f) a[f] = As[cur][kr][wm * HM + f * 16 + (lane & 15)];
+        if (w) {   // uniform: the term's weights
+          const CT wk = Ws[cur][kr];
+#pragma unroll
+          for (int f = 0; f < FWM; ++f) a[f] *= wk;
+        }
 #pragma unroll
         for (int f = 0; f < FWN; ++f) b[f] = Bs[cur][kr][wn * HN + f * 16 + (lane & 15)];
 #pragma unroll
@@ -254,13 +266,13 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
     C2 = addr(bt, it.c2.buf, it.c2.blk, s, r2, c2);
     ldc2 = ldof(bt, it.c2.buf, it.c2.blk);
   }
-  if constexpr (T == 64) {
+  {
     // Epilogue through LDS (the operand buffers, free after the last K step):
     // the tile goes to LDS column chunk by column chunk, then every wave reads
     // back whole columns (C, column-major) or whole row segments (the
     // transposed twin C2), so that global reads and writes are contiguous; each
     // thread loads all the old values it updates before it stores any.
-    constexpr int CW = (T == 64 && !F32) ? 64 : 32;  // columns per chunk
+    constexpr int CW = F32 ? 32 : 64;                // columns per chunk: the chunk fills the operand buffers
     constexpr int LDT = T + 1;                       // LDS column stride (doubles)
     constexpr int PER = T * CW / NT;                 // elements per thread per chunk
     static_assert(CW * LDT * sizeof(double) <= sizeof(ABs), "chunk must fit in the operand buffers");
@@ -331,27 +343,6 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
       }
       __syncthreads();
     }
-  } else {
-    // 128 x 128 tiles: every element read-modified-written from registers
-    // (staging 128 columns through LDS would not fit beside the operands)
-    for (int i = 0; i < FWM; ++i)
-      for (int j = 0; j < FWN; ++j)
-        for (int v = 0; v < 4; ++v) {
-          // output row of register v: FP64 MFMA puts D[i][j] in lane j + 16*(i%4),
-          // register i/4; FP32 MFMA in lane j + 16*(i/4), register i%4
-          const int r = m0 + wm * HM + i * 16 + (F32 ? 4 * (lane >> 4) + v : (lane >> 4) + 4 * v);
-          const int c = n0 + wn * HN + j * 16 + (lane & 15);
-          if (r < M && c < N) {
-            const double x = it.alpha * (double)acc[i][j][v];
-            const int dr = r < rs ? cr + r : r2o + (r - rs), dcol = c < cs ? cc + c : c2o + (c - cs);
-            double* p = C + dr + (int64_t)dcol * ldc;
-            *p = it.beta != 0.0 ? it.beta * *p + x : x;
-            if (C2) {
-              double* q = C2 + c + (int64_t)r * ldc2;
-              *q = it.beta != 0.0 ? it.beta * *q + x : x;
-            }
-          }
-        }
   }
   }
 }
@@ -371,7 +362,7 @@ __global__ __launch_bounds__(256, 4) void k_gemm_f32(const GItem* __restrict__ i
 }
 
 // 128 x 128 output tiles on eight waves: twice the arithmetic per operand byte
-// of the 64 x 64 tile, at two resident workgroups per CU, for large blocks
+// of the 64 x 64 tile, at one resident workgroup per CU, for large blocks
 template <bool TA, bool TB>
 __global__ __launch_bounds__(512) void k_gemm128(const GItem* __restrict__ items, int nitems,
                                                  const GTerm* __restrict__ terms, BufTab bt, SizeTab sz,
