@@ -47,7 +47,7 @@ WORKLOADS = {
 }
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2311_08618_amd", "csrc", "kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_gemm128_nt_cube_laplace_n262144.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_gemm_nt_cube_laplace_n262144.md")
 
 
 def kernel_source_hash() -> str:

@@ -654,6 +654,9 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
     size_t nG = (size_t)S * N * bsz, nM = (size_t)S * std::max(1, lp.max_slot_m) * bsz,
            nP = (size_t)S * std::max(1, lp.max_slot_p) * bsz, nSg = (size_t)S * N * cap;
     A->lvl.ensure((4 * nG + nM + 2 * nP + nSg) * 8 + 64, st);
+    if (debug_level())
+      std::fprintf(stderr, "[h2eig] level %d sizes GB: S %.2f F %.2f G/V/W/Z %.2f M/P/T %.2f (N %d cap %d, %d shifts)\n", l,
+                   nS * 8e-9, nF * 8e-9, 4.0 * nG * 8e-9, (nM + 2.0 * nP) * 8e-9, N, cap, S);
     double* dG = (double*)A->lvl.p;
     double* dV = dG + nG;
     double* dW = dV + nG;
@@ -757,6 +760,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
     const int CH = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)max_items, 65535,
                                                                 (int64_t)(2LL << 30) / (int64_t)(bsz * 8)}));
     A->rs.ensure((size_t)S * CH * bsz * 8 + 64, st);
+    if (debug_level()) std::fprintf(stderr, "[h2eig]   scratch slots GB: %.2f (%d slots)\n", S * CH * bsz * 8e-9, CH);
     setb(B_RS, (double*)A->rs.p, (size_t)CH * bsz, bsz, cap);
     auto chunked = [&](int cls, int kind, const DevList& gl, size_t copies, size_t tcopies = 0) {
       for (int c0 = 0; c0 < gl.n; c0 += CH) {
@@ -937,6 +941,9 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
     const size_t ebsz = (size_t)emax * emax;
     size_t nH = (size_t)S * nslot * pbsz, nTm = (size_t)S * nslot * ebsz;
     A->mrg.ensure((nH + nTm) * 8 + 64, st);
+    if (debug_level())
+      std::fprintf(stderr, "[h2eig] merge %d -> %d sizes GB: next S %.2f F %.2f, hat %.2f tmp %.2f (pcap %d, %d slots)\n", l,
+                   l - 1, nSN * 8e-9, nFN * 8e-9, nH * 8e-9, nTm * 8e-9, pcap, nslot);
     double* dH = (double*)A->mrg.p;
     double* dTm = dH + nH;
     setb(B_HAT, dH, (size_t)nslot * pbsz, pbsz, pcap);
