@@ -181,54 +181,123 @@ def serve_bench(args):
     print(json.dumps(line))
 
 
+QUERY_FORMS = {"plain_f64_1shift": (1, 0.0), "batched_f64": (0, 0.0), "batched_mixed": (0, 1e-4)}
+
+
 def queries_bench(args):
-    """k-th eigenvalue queries in three forms on fresh handles (no shared
-    records): one shift per factorization in FP64 (plain), every open bracket
-    in one batched factorization per step in FP64, and batched with FP32
-    contractions while a bracket is at least 1e-4 normA wide.  Prints one JSON
-    line with the eigenvalues per second of each form and the largest
-    difference of their results."""
+    """k-th eigenvalue queries, measured, in three forms on fresh handles (no
+    records shared between forms): one shift per factorization in FP64
+    (plain), every open bracket in one batched factorization per step in FP64,
+    and batched with FP32 contractions while a bracket is at least 1e-4 normA
+    wide.  For the tolerance ladder --tol t1,t2,... each form runs Algorithm 1
+    to t1, then continues on the same handle to t2 and so on: the later calls
+    start from the brackets the record cache holds, which are the brackets the
+    uninterrupted bisection to t2 has once it passes t1, so the cumulative time
+    at each tolerance is that of a run straight to it.  Prints one JSON line
+    with the cumulative seconds and eigenvalues per second of every form at
+    every tolerance, the eigenvalues, and their largest difference from the
+    plain form when it ran."""
     import numpy as np
     from paper_2311_08618_amd import workloads as W
     from paper_2311_08618_amd.h2eig import H2Matrix
 
-    n, nq, tol = args.n, args.nq, args.tol
-    ks = [max(1, j * n // nq) for j in range(nq)]
+    n = args.n or 262144
+    tols = [float(t) for t in str(args.tol).split(",")]
+    ks = [int(k) for k in args.ks.split(",")] if args.ks else [max(1, j * n // args.nq) for j in range(args.nq)]
+    forms = args.forms.split(",") if args.forms else list(QUERY_FORMS)
+    os.environ["H2EIG_PROGRESS"] = "1"       # one stderr line per bisection step
     X = W.cube_points(n, 0)
-    forms = {"plain_f64_1shift": (1, 0.0), "batched_f64": (0, 0.0), "batched_mixed": (0, 1e-4)}
-    out, lam = {}, {}
-    for name, (maxs, mixed) in forms.items():
+    out, norm, interval = {}, None, None
+    for name in forms:
+        maxs, mixed = QUERY_FORMS[name]
+        t0 = time.perf_counter()
         A = H2Matrix(X, W.K_LAPLACE, 1e3, 256, 1.0, 1e-8)
+        print("queries: %s: built in %.1f s" % (name, time.perf_counter() - t0), file=sys.stderr, flush=True)
         if maxs:
             A.set_max_shifts(maxs)
         A.set_mixed(mixed)
-        A.interval()                      # the starting interval, outside the timed region
-        t0 = time.perf_counter()
-        lam[name], _ = A.kth_eig(ks, tol)
-        dt = time.perf_counter() - t0
-        st = A.stats()
-        out[name] = {"seconds": dt, "eigvals_per_s": nq / dt, "evals_f64": st["evals_f64"],
-                     "evals_f32": st["evals_f32"], "evals_per_s": (st["evals_f64"] + st["evals_f32"]) / dt}
-        print("queries: %s done in %.1f s" % (name, dt), file=sys.stderr, flush=True)
+        interval = A.interval()           # the starting interval, outside the timed region
+        norm = A.norm()
+        rec, total = {}, 0.0
+        for tol in tols:
+            t0 = time.perf_counter()
+            lam, br = A.kth_eig(ks, tol)
+            total += time.perf_counter() - t0
+            st = A.stats()
+            rec["tol=%g" % tol] = {"seconds": total, "eigvals_per_s": len(ks) / total, "lambda": lam.tolist(),
+                                   "max_bracket": float(np.max(br[:, 1] - br[:, 0])),
+                                   "evals_f64": st["evals_f64"], "evals_f32": st["evals_f32"]}
+            print("queries: %s at tol %g after %.1f s (%d FP64 + %d FP32 shifts)"
+                  % (name, tol, total, st["evals_f64"], st["evals_f32"]), file=sys.stderr, flush=True)
+        out[name] = rec
         A.close()
-    ref = lam["plain_f64_1shift"]
-    norm = H2Matrix(X, W.K_LAPLACE, 1e3, 256, 1.0, 1e-8).norm()
     line = {
-        "metric": "k-th eigenvalues/sec, batched and mixed-precision forms vs plain one-shift FP64",
-        "value": out["batched_mixed"]["eigvals_per_s"],
-        "unit": "eigvals/s",
-        "n_gpus": 1,
-        "higher_is_better": True,
-        "dtype": "f64 (FP32 contractions in early steps for batched_mixed)",
-        "data": "synthetic",
+        "metric": "k-th eigenvalues/sec at n=%d: plain one-shift FP64, batched FP64, batched + FP32 early steps" % n,
+        "value": None, "unit": "eigvals/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f64 (FP32 contractions in early steps for batched_mixed)", "data": "synthetic",
         "forms": out,
-        "speedup_vs_plain": {k: out[k]["eigvals_per_s"] / out["plain_f64_1shift"]["eigvals_per_s"] for k in out},
-        "max_abs_dlambda_vs_plain": {k: float(np.max(np.abs(lam[k] - ref))) for k in out},
-        "max_rel_dlambda_vs_plain": {k: float(np.max(np.abs(lam[k] - ref)) / norm) for k in out},
-        "config": {"workload": "cube-laplace n=%d leaf=256 eta=1 eps=1e-8 A_ii=1e3; %d eigenvalues "
-                               "k = j*n/%d (j=0..%d, k=1 for j=0), tol %g" % (n, nq, nq, nq - 1, tol),
-                   "n": n, "ks": ks, "tol": tol, "normA": norm},
+        "config": {"workload": "cube-laplace n=%d leaf=256 eta=1 eps=1e-8 A_ii=1e3" % n, "n": n, "ks": ks,
+                   "tols": tols, "normA": norm, "interval": list(interval)},
     }
+    summarize_queries(line)
+    print(json.dumps(line))
+
+
+def summarize_queries(line):
+    """Fills value (the best form at the finest tolerance), the speedups over the
+    plain form and |delta lambda| against it, per tolerance, where the plain
+    form is present."""
+    import numpy as np
+    forms = line["forms"]
+    tols = line["config"]["tols"]
+    key = "tol=%g" % tols[-1]
+    line["value"] = max(f[key]["eigvals_per_s"] for f in forms.values() if key in f)
+    if "plain_f64_1shift" not in forms:
+        return
+    ref = forms["plain_f64_1shift"]
+    line["speedup_vs_plain"], line["max_abs_dlambda_vs_plain"] = {}, {}
+    for tol in tols:
+        k = "tol=%g" % tol
+        for name, f in forms.items():
+            if k not in f or k not in ref:
+                continue
+            line["speedup_vs_plain"].setdefault(name, {})[k] = f[k]["eigvals_per_s"] / ref[k]["eigvals_per_s"]
+            d = np.abs(np.array(f[k]["lambda"]) - np.array(ref[k]["lambda"]))
+            line["max_abs_dlambda_vs_plain"].setdefault(name, {})[k] = float(np.max(d))
+
+
+def merge_queries(paths):
+    """One query record from the JSON lines of separate --queries runs on the
+    same workload and tolerances (forms, or groups of k of one form, run in
+    separate processes).  Groups of k of one form add their seconds: the form
+    then answered all of them in that time, without the records the groups
+    could have shared."""
+    lines = [json.loads(open(p).read().strip().splitlines()[-1]) for p in paths]
+    base = lines[0]
+    tols = base["config"]["tols"]
+    ks_all = sorted({k for ln in lines for k in ln["config"]["ks"]})
+    forms = {}
+    for ln in lines:
+        assert ln["config"]["tols"] == tols and ln["config"]["n"] == base["config"]["n"]
+        for name, rec in ln["forms"].items():
+            dst = forms.setdefault(name, {})
+            for k, r in rec.items():
+                d = dst.setdefault(k, {"seconds": 0.0, "lam": {}, "evals_f64": 0, "evals_f32": 0, "max_bracket": 0.0})
+                d["seconds"] += r["seconds"]
+                d["evals_f64"] += r["evals_f64"]
+                d["evals_f32"] += r["evals_f32"]
+                d["max_bracket"] = max(d["max_bracket"], r["max_bracket"])
+                d["lam"].update(dict(zip(ln["config"]["ks"], r["lambda"])))
+    for name, rec in forms.items():
+        for k, d in rec.items():
+            assert sorted(d["lam"]) == ks_all, (name, k)
+            d["lambda"] = [d["lam"][q] for q in ks_all]
+            del d["lam"]
+            d["eigvals_per_s"] = len(ks_all) / d["seconds"]
+    line = dict(base)
+    line["forms"] = forms
+    line["config"] = dict(base["config"], ks=ks_all, merged_from=len(paths))
+    summarize_queries(line)
     print(json.dumps(line))
 
 
@@ -271,8 +340,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--queries", action="store_true",
                     help="k-th eigenvalue queries: plain one-shift FP64 vs batched vs batched+mixed (uses --n)")
-    ap.add_argument("--nq", type=int, default=16, help="eigenvalues for --queries")
-    ap.add_argument("--tol", type=float, default=1e-8, help="absolute tolerance for --queries")
+    ap.add_argument("--nq", type=int, default=4, help="eigenvalues for --queries (k = j n / nq)")
+    ap.add_argument("--ks", default="", help="explicit comma list of k for --queries")
+    ap.add_argument("--forms", default="", help="comma list of query forms (default: all): " + ",".join(QUERY_FORMS))
+    ap.add_argument("--tol", default="1e-6,1e-10", help="comma list of absolute tolerances for --queries")
+    ap.add_argument("--queries-merge", nargs="+", metavar="JSON", help="merge the lines of separate --queries runs")
     ap.add_argument("--serve", action="store_true", help="serving-loop measurement instead of the step bench")
     ap.add_argument("--serve-sizes", default="262144,131072,65536,16384")
     ap.add_argument("--serve-slots-max", type=int, default=16, help="most in-flight queries per matrix")
@@ -291,6 +363,9 @@ def main():
         return
     if args.serve:
         serve_bench(args)
+        return
+    if args.queries_merge:
+        merge_queries(args.queries_merge)
         return
     if args.queries:
         queries_bench(args)

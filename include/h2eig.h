@@ -133,6 +133,7 @@ h2_status h2_inertia_f32(h2_matrix A, const double* sigma, int64_t nshift,
  * A split point whose factorization meets an exactly singular pivot block is
  * moved inside its bracket (by 1/64 of the width, up to 8 times, then
  * H2_ENUMERIC).  With h2_set_mixed, wide brackets use h2_inertia_f32.
+ * Environment H2EIG_PROGRESS=1: one line per bisection step on stderr.
  */
 h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol,
                      const double* ab, double* lambda, double* bracket);

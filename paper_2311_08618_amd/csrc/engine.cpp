@@ -1286,11 +1286,15 @@ h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol, cons
     hi[j] = H;
   };
   for (auto& rec : A->cache) narrow(rec.first, rec.second, false);
-  for (;;) {
+  const char* pe = std::getenv("H2EIG_PROGRESS");
+  const bool progress = pe && pe[0] == '1';
+  for (int step = 1;; ++step) {
     std::vector<double> m32, m64;
     std::vector<char> act(nk, 0), verify(nk, 0);
     for (int64_t j = 0; j < nk; ++j) {
-      if (phase[j] == 0 && hi[j] - lo[j] < thr) phase[j] = 1;
+      // to FP64 below thr, or before the bracket would end at tol with ends
+      // that only FP32 counts set (tol >= thr)
+      if (phase[j] == 0 && hi[j] - lo[j] < std::max(thr, tol)) phase[j] = 1;
       if (phase[j] == 1) {
         if (lo[j] != a0 && !has64(lo[j])) m64.push_back(lo[j]), verify[j] = 1;
         if (hi[j] != b0 && !has64(hi[j])) m64.push_back(hi[j]), verify[j] = 1;
@@ -1330,6 +1334,12 @@ h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol, cons
       } else if (++nudge[j] > 8) {
         return fail(H2_ENUMERIC, "singular pivot block at every split point tried");
       }
+    }
+    if (progress) {
+      int64_t open = 0;
+      for (int64_t j = 0; j < nk; ++j) open += act[j] || verify[j];
+      std::fprintf(stderr, "[h2eig] kth_eig step %d: %zu FP64 + %zu FP32 shifts for %lld open brackets\n", step,
+                   m64.size(), m32.size(), (long long)open);
     }
     for (size_t q = 0; q < m64.size(); ++q)
       if (s64[q] == H2_OK) narrow(m64[q], n64[q], false);

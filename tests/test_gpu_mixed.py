@@ -83,6 +83,26 @@ def test_mixed_kth_eig_catches_wrong_f32_decisions(lib):
     assert T.stats()["evals_f32"] > 0
 
 
+def test_mixed_tolerance_above_switch_width_ends_in_fp64(lib):
+    """tol >= switch_rel * normA: a bracket reaches tol while still wider than
+    the switch width; its ends must still be counted in FP64 before it is
+    returned."""
+    n, tol = 4096, 1e-4
+    print("case mixed tol above switch tridiag n=%d" % n, flush=True)
+    T = lib.H2Matrix(W.line_points(n), W.K_TRIDIAG_1D, 2.0, 64, 1.0, 1e-12, p0=1.0)
+    T.set_mixed(1e-6)
+    assert tol > 1e-6 * T.norm()
+    lam = tridiag_eigs(n)
+    ks = [1, 2, n // 2, n]
+    got, br = T.kth_eig(ks, tol)
+    st = T.stats()
+    assert st["evals_f32"] > 0 and st["evals_f64"] > 0, st
+    bound = tol / 2 + 10 * 1e-12 * T.norm()
+    for k, g in zip(ks, got):
+        assert abs(g - lam[k - 1]) <= bound, (k, g, lam[k - 1])
+    assert np.all(br[:, 1] - br[:, 0] < tol)
+
+
 def test_mixed_argument_errors(lib, cube):
     A, _ = cube
     for v in (-1.0, float("nan"), float("inf")):
