@@ -116,8 +116,10 @@ def serve_bench(args):
         add_s = time.perf_counter() - t0
         print("serve: resident, workspace per shift measured in %.1f s" % add_s, file=sys.stderr, flush=True)
         rng = np.random.default_rng(7)
-        arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * args.serve_window * 2) + 16))
-        arr = arr[arr < args.serve_window]
+        window = max(args.serve_window, 4.0 / rate)      # at least ~4 arrivals at low rates
+        cap = window + args.serve_cap                    # drain after the last possible arrival
+        arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * window * 2) + 16))
+        arr = arr[arr < window]
         which = rng.integers(0, len(sizes), len(arr))
         tols = np.where(rng.random(len(arr)) < 0.5, 1e-6, 1e-10)
         ks = [int(rng.integers(1, sizes[w] + 1)) for w in which]
@@ -128,11 +130,11 @@ def serve_bench(args):
             if dt > 0:
                 time.sleep(dt)
             tickets.append(srv.submit(ids[w], k, float(tol)))
-        print("serve: %d queries submitted over %.1f s at %g/s" % (len(tickets), args.serve_window, rate),
+        print("serve: %d queries submitted over %.1f s at %g/s" % (len(tickets), window, rate),
               file=sys.stderr, flush=True)
         done = {}
         t_last = time.perf_counter()
-        while len(done) < len(tickets) and time.perf_counter() - t0 < args.serve_cap:
+        while len(done) < len(tickets) and time.perf_counter() - t0 < cap:
             for tk in tickets:
                 if tk not in done:
                     lam = srv.poll(tk)
@@ -152,7 +154,8 @@ def serve_bench(args):
             per[str(n)] = {"offered": len(idx), "served": sum(1 for j in idx if tickets[j] in done)}
         srv.close()
         sweep.append({
-            "offered_rate": len(tickets) / args.serve_window, "offered": len(tickets), "served": st["served"],
+            "rate": rate, "window_s": window, "cap_s": cap,
+            "offered_rate": len(tickets) / window, "offered": len(tickets), "served": st["served"],
             "served_rate": st["served"] / elapsed, "elapsed_s": round(elapsed, 1),
             "p50_ms_finished": st["p50_ms"], "p99_ms_finished": st["p99_ms"],
             "p50_ms_censored": cen["p50_ms"], "p99_ms_censored": cen["p99_ms"],
@@ -173,9 +176,9 @@ def serve_bench(args):
         "p99_ms_censored": best["p99_ms_censored"],
         "sweep": sweep,
         "config": {"workload": "cube-laplace resident n=%s leaf=256 eta=1 eps=1e-8 A_ii=1e3; Poisson arrivals "
-                               "(seed 7) at %s/s for %g s, k uniform in [1,n], tol 1e-6 or 1e-10 (p=0.5); drain "
-                               "cap %g s; admission by one shared HBM budget (85%% of free memory)"
-                               % (sizes, rates, args.serve_window, args.serve_cap),
+                               "(seed 7) at %s/s for max(%g s, 4/rate), k uniform in [1,n], tol 1e-6 or 1e-10 "
+                               "(p=0.5); drain %g s after the arrival window; admission by one shared HBM budget "
+                               "(85%% of free memory)" % (sizes, rates, args.serve_window, args.serve_cap),
                    "max_slots": args.serve_slots_max, "build_s": round(build_s, 1)},
     }
     print(json.dumps(line))
@@ -350,7 +353,8 @@ def main():
     ap.add_argument("--serve-slots-max", type=int, default=16, help="most in-flight queries per matrix")
     ap.add_argument("--serve-rate", default="200", help="Poisson arrivals per second (comma list: a sweep)")
     ap.add_argument("--serve-window", type=float, default=1.0, help="seconds of arrivals")
-    ap.add_argument("--serve-cap", type=float, default=120.0, help="seconds until the measurement stops")
+    ap.add_argument("--serve-cap", type=float, default=120.0,
+                    help="seconds of drain after the arrival window until the measurement stops")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()

@@ -180,7 +180,8 @@ struct GatherItem {
   int out_blk;              // slot in B_HAT
   int dst_buf, dst_blk;     // output block (B_SN or B_FN): receives the new-new part
   int p, q;                 // parent clusters
-  int src_kind[4];          // 0 none, 1 near block (B_S), 2 carried fill-in (B_F)
+  int src_kind[4];          // 0 none, 1 near block (B_S), 2 carried fill-in (B_F), 3 carried fill-in
+                            // stored as the other orientation (read transposed)
   int src_blk[4];
   int cpl_blk[4];           // coupling slot in B_CPL or -1
 };

@@ -117,8 +117,8 @@ struct DevColour {
   size_t clusters = 0;
   int ncl = 0;
   DevList pc_upd, ut_s, ut_t, ut_x, ut_u, ut_w, ldl_upd, inv_t, inv_x;
-  DevList rot_rows, rot_cols, trsm;
-  size_t rr_copy = 0, rc_copy = 0, tr_copy = 0, rr_copyt = 0;
+  DevList rot_rows, rot_cols, rot_cols_t, trsm;
+  size_t rr_copy = 0, rc_copy = 0, tr_copy = 0, rr_copyt = 0, rct_copy = 0;
   DevList schur, gm, gt, gg;
   size_t gp_items = 0, gp_src = 0;
   int ngp = 0;
@@ -128,7 +128,7 @@ struct DevLevel {
   std::vector<DevColour> colours;
   size_t diag_blk = 0, r0 = 0, pr0 = 0, gather = 0, mirror = 0;
   int ngather = 0, nmirror = 0;
-  DevList gram_init, fill, tr1, tr2;
+  DevList gram_init, gram_init_t, fill, tr1, tr2;
 };
 
 // Kernel classes of the level engine, for the diagnostic profiler.
@@ -239,6 +239,7 @@ struct h2_matrix_s {
   // workspace
   Arena sf[2], lvl, mrg, small, rs;
   Arena tab[2];   // block offset / leading-dimension tables of the blocks in sf[0] / sf[1]
+  Arena stab;     // offset / leading-dimension tables of the current level's fill-in Gram slots
   // slicing cache and statistics
   std::vector<std::pair<double, int64_t>> cache;
   bool have_gersh = false;
@@ -319,6 +320,8 @@ void upload_plan(h2_matrix A) {
       dc.inv_x = put_list(b, cp.inv_x);
       dc.rot_rows = put_list(b, cp.rot_rows);
       dc.rot_cols = put_list(b, cp.rot_cols);
+      dc.rot_cols_t = put_list(b, cp.rot_cols_t);
+      dc.rct_copy = b.put(cp.rot_cols_t_copy);
       dc.trsm = put_list(b, cp.trsm);
       dc.rr_copy = b.put(cp.rot_rows_copy);
       dc.rr_copyt = b.put(cp.rot_rows_copyt);
@@ -333,6 +336,7 @@ void upload_plan(h2_matrix A) {
       dc.ngp = (int)cp.gram_p.items.size();
     }
     dl.gram_init = put_list(b, lp.gram_init);
+    dl.gram_init_t = put_list(b, lp.gram_init_t);
     if (l >= 1) {
       const MergePlan& mp = lp.merge;
       dl.pr0 = b.put(mp.pr0);
@@ -633,6 +637,9 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
   A->last_cap.assign(L + 1, 0);
   A->lstats.assign(L + 1, {});
   A->lstats_shifts = S;
+  // per-cluster bound on the dimension m over the shifts of the batch at the
+  // current level (the merge sets it for the next level)
+  std::vector<int> mb(A->plan[L].N, cap);
   for (int l = L; l >= 0; --l) {
     const LevelPlan& lp = A->plan[l];
     const DevLevel& dl = A->dlev[l];
@@ -651,20 +658,48 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
     if (l == L) A->sf[cur].ensure((nS + nF) * 8 + 64, st);
     double* dS = (double*)A->sf[cur].p;
     double* dF = dS + nS;
-    size_t nG = (size_t)S * N * bsz, nM = (size_t)S * std::max(1, lp.max_slot_m) * bsz,
-           nP = (size_t)S * std::max(1, lp.max_slot_p) * bsz, nSg = (size_t)S * N * cap;
-    A->lvl.ensure((4 * nG + nM + 2 * nP + nSg) * 8 + 64, st);
+    // Scratch slots of the fill-in Gram, per colour class, each sized by its
+    // clusters: an M slot (j,i) and a P slot (k,i) hold R_i x R_i, a T slot
+    // (k,i) R_k x R_i, and R <= m - r0 before and after the recompression.
+    // Offsets run over one region per shift shared by the three buffers.
+    std::vector<int64_t> soff;
+    std::vector<int> sld, cslot0(lp.colours.size());
+    int64_t mpt = 1;
+    for (size_t c = 0; c < lp.colours.size(); ++c) {
+      const ColourPlan& cp = lp.colours[c];
+      cslot0[c] = (int)soff.size();
+      auto rt = [&](int i) { return std::max(1, mb[i] - lp.r0[i]); };
+      int64_t o = 0;
+      for (int i : cp.slot_m_i) { soff.push_back(o); sld.push_back(rt(i)); o += (int64_t)rt(i) * rt(i); }
+      for (int i : cp.slot_p_i) { soff.push_back(o); sld.push_back(rt(i)); o += (int64_t)rt(i) * rt(i); }
+      for (size_t q = 0; q < cp.slot_p_k.size(); ++q) {
+        const int k = cp.slot_p_k[q], i = cp.slot_p_i[q];
+        soff.push_back(o);
+        sld.push_back(rt(k));
+        o += (int64_t)rt(k) * rt(i);
+      }
+      mpt = std::max(mpt, o);
+    }
+    const size_t soff_b = (soff.size() * 8 + 255) & ~(size_t)255;
+    A->stab.ensure(soff_b + sld.size() * 4 + 64, st);
+    if (!soff.empty()) {
+      HIPCHK(hipMemcpyAsync(A->stab.p, soff.data(), soff.size() * 8, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync((char*)A->stab.p + soff_b, sld.data(), sld.size() * 4, hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));   // the host vectors go out of scope
+    }
+    const int64_t* d_soff = (const int64_t*)A->stab.p;
+    const int* d_sld = (const int*)((const char*)A->stab.p + soff_b);
+    size_t nG = (size_t)S * N * bsz, nMPT = (size_t)S * mpt, nSg = (size_t)S * N * cap;
+    A->lvl.ensure((4 * nG + nMPT + nSg) * 8 + 64, st);
     if (debug_level())
       std::fprintf(stderr, "[h2eig] level %d sizes GB: S %.2f F %.2f G/V/W/Z %.2f M/P/T %.2f (N %d cap %d, %d shifts)\n", l,
-                   nS * 8e-9, nF * 8e-9, 4.0 * nG * 8e-9, (nM + 2.0 * nP) * 8e-9, N, cap, S);
+                   nS * 8e-9, nF * 8e-9, 4.0 * nG * 8e-9, nMPT * 8e-9, N, cap, S);
     double* dG = (double*)A->lvl.p;
     double* dV = dG + nG;
     double* dW = dV + nG;
     double* dZ = dW + nG;
-    double* dM = dZ + nG;
-    double* dP = dM + nM;
-    double* dT = dP + nP;
-    double* dSg = dT + nP;
+    double* dMPT = dZ + nG;
+    double* dSg = dMPT + nMPT;
     BufTab bt{};
     for (int k = 0; k < NBUF; ++k) { bt.p[k] = nullptr; bt.ss[k] = 0; bt.bs[k] = (int64_t)bsz; bt.ld[k] = cap; }
     auto setb = [&](int id, double* p, size_t perShift, size_t blk, int ld) {
@@ -686,9 +721,9 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
     setb(B_V, dV, (size_t)N * bsz, bsz, cap);
     setb(B_W, dW, (size_t)N * bsz, bsz, cap);
     setb(B_Z, dZ, (size_t)N * bsz, bsz, cap);
-    setb(B_M, dM, (size_t)std::max(1, lp.max_slot_m) * bsz, bsz, cap);
-    setb(B_P, dP, (size_t)std::max(1, lp.max_slot_p) * bsz, bsz, cap);
-    setb(B_T, dT, (size_t)std::max(1, lp.max_slot_p) * bsz, bsz, cap);
+    setb(B_M, dMPT, (size_t)mpt, 0, 0);
+    setb(B_P, dMPT, (size_t)mpt, 0, 0);
+    setb(B_T, dMPT, (size_t)mpt, 0, 0);
     setb(B_SIGN, dSg, (size_t)N * cap, (size_t)cap, cap);
     if (l >= 1) {
       const LevelPlan& lpl = A->plan[l];
@@ -753,25 +788,39 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
     };
     gemm(PC_GRAM, GEMM_NT, A->dp<GItem>(dl.gram_init.items), dl.gram_init.n, A->dp<GTerm>(dl.gram_init.terms), cap,
          cap);
+    gemm(PC_GRAM, GEMM_TN, A->dp<GItem>(dl.gram_init_t.items), dl.gram_init_t.n,
+         A->dp<GTerm>(dl.gram_init_t.terms), cap, cap);
     // scratch slots of the out-of-place products: about 2 GB per shift at most
     int max_items = 1;
     for (const DevColour& dc : dl.colours)
-      max_items = std::max({max_items, dc.rot_rows.n, dc.rot_cols.n, dc.trsm.n});
+      max_items = std::max({max_items, dc.rot_rows.n, dc.rot_cols.n, dc.rot_cols_t.n, dc.trsm.n});
     const int CH = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)max_items, 65535,
                                                                 (int64_t)(2LL << 30) / (int64_t)(bsz * 8)}));
     A->rs.ensure((size_t)S * CH * bsz * 8 + 64, st);
     if (debug_level()) std::fprintf(stderr, "[h2eig]   scratch slots GB: %.2f (%d slots)\n", S * CH * bsz * 8e-9, CH);
     setb(B_RS, (double*)A->rs.p, (size_t)CH * bsz, bsz, cap);
-    auto chunked = [&](int cls, int kind, const DevList& gl, size_t copies, size_t tcopies = 0) {
+    // out-of-place products in chunks of CH scratch slots, each chunk copied
+    // back (plain copies and/or transposed copies, parallel to the items)
+    auto chunked = [&](int cls, int kind, const DevList& gl, size_t copies, size_t tcopies = 0, bool plain = true) {
       for (int c0 = 0; c0 < gl.n; c0 += CH) {
         int nc = std::min(CH, gl.n - c0);
         gemm(cls, kind, A->dp<GItem>(gl.items) + c0, nc, A->dp<GTerm>(gl.terms), cap, cap);
-        run(PC_COPY, [&] { launch_copyback(A->dp<CopyItem>(copies) + c0, nc, bt, sz, cap, S, st); });
+        if (plain) run(PC_COPY, [&] { launch_copyback(A->dp<CopyItem>(copies) + c0, nc, bt, sz, cap, S, st); });
         if (tcopies) run(PC_COPY, [&] { launch_copyback_t(A->dp<CopyItem>(tcopies) + c0, nc, bt, sz, S, st); });
       }
     };
     for (size_t c = 0; c < dl.colours.size(); ++c) {
       const DevColour& dc = dl.colours[c];
+      {   // this class's Gram slots
+        const ColourPlan& cp = lp.colours[c];
+        const int m0 = cslot0[c], p0 = m0 + (int)cp.slot_m_i.size(), t0 = p0 + (int)cp.slot_p_i.size();
+        bt.boff[B_M] = d_soff + m0;
+        bt.bld[B_M] = d_sld + m0;
+        bt.boff[B_P] = d_soff + p0;
+        bt.bld[B_P] = d_sld + p0;
+        bt.boff[B_T] = d_soff + t0;
+        bt.bld[B_T] = d_sld + t0;
+      }
       const int* cl = A->dp<int>(dc.clusters);
       auto gl = [&](int cls, int kind, const DevList& L, int mcap = 0, int ncap = 0) {
         const int mc = mcap > 0 ? mcap : cap, nc = ncap > 0 ? ncap : cap;
@@ -822,6 +871,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
       }
       chunked(PC_ROTATE, GEMM_TN, dc.rot_rows, dc.rr_copy, dc.rr_copyt);
       chunked(PC_ROTATE, GEMM_NN, dc.rot_cols, dc.rc_copy);
+      chunked(PC_ROTATE, GEMM_TT, dc.rot_cols_t, 0, dc.rct_copy, false);
       // pivot LDL, panel by panel (each panel takes at least ldl_panel_min()
       // pivots unless it reaches R), then the elimination operator
       run(PC_LDL, [&] { launch_ldl_init(cl, dc.ncl, bt, sz, S, st); });
@@ -897,6 +947,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
     std::vector<int> pc(Np, 8);
     for (int s2 = 0; s2 < S; ++s2)
       for (int p = 0; p < Np; ++p) pc[p] = std::max(pc[p], round_cap(hpm[(size_t)s2 * Np + p]));
+    mb = pc;
     std::vector<int64_t> offS(std::max(1, pp.nblk())), offF(std::max(1, pp.nfblk()));
     std::vector<int> ldS(std::max(1, pp.nblk())), ldF(std::max(1, pp.nfblk()));
     int64_t totS = 0, totF = 0;
@@ -1063,6 +1114,8 @@ h2_status run_inertia(h2_matrix A, const double* sigma, int64_t ns, bool f32, in
       A->mrg.release();
       A->rs.release();
       for (auto& a : A->tab) a.release();
+  A->stab.release();
+      A->stab.release();
       A->arena_shifts = 0;
       continue;
     }
@@ -1393,6 +1446,7 @@ h2_status h2_release_workspace(h2_matrix A) {
   A->mrg.release();
   A->rs.release();
   for (auto& a : A->tab) a.release();
+  A->stab.release();
   A->arena_shifts = 0;
   return H2_OK;
 }
@@ -1628,6 +1682,7 @@ void h2_free(h2_matrix A) {
   A->small.release();
   A->rs.release();
   for (auto& a : A->tab) a.release();
+  A->stab.release();
   if (A->d_bres) (void)hipFree(A->d_bres);
   for (auto p : A->d_cpl)
     if (p) (void)hipFree(p);

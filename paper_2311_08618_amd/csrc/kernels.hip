@@ -1399,6 +1399,7 @@ __global__ void k_gather(const GatherItem* __restrict__ items, BufTab bt, SizeTa
     double v = 0.0;
     if (g.src_kind[slot] == 1) v = addr(bt, B_S, g.src_blk[slot], s, Rc + rr, Rd + cc)[0];
     else if (g.src_kind[slot] == 2) v = addr(bt, B_F, g.src_blk[slot], s, Rc + rr, Rd + cc)[0];
+    else if (g.src_kind[slot] == 3) v = addr(bt, B_F, g.src_blk[slot], s, Rd + cc, Rc + rr)[0];
     if (g.cpl_blk[slot] >= 0) {
       const int tc = sz.t[s * N + c], td = sz.t[s * N + d];
       if (rr >= tc && cc >= td) v += bt.p[B_CPL][(int64_t)g.cpl_blk[slot] * bt.bs[B_CPL] + (rr - tc) + (int64_t)(cc - td) * ldc];

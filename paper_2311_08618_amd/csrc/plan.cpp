@@ -78,7 +78,8 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
     for (int i = 0; i < N; ++i) {
       for (int j : T.near[l][i]) lp.near_idx.push_back(j);
       lp.near_ptr.push_back((int)lp.near_idx.size());
-      for (int j : carried[l][i]) lp.f_idx.push_back(j);
+      for (int j : carried[l][i])
+        if (j > i) lp.f_idx.push_back(j);
       lp.f_ptr.push_back((int)lp.f_idx.size());
       for (int j : T.far[l][i]) lp.far_idx.push_back(j);
       lp.far_ptr.push_back((int)lp.far_idx.size());
@@ -161,9 +162,29 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
           cp.rot_cols_copy.push_back(cc);
         }
       };
+      // Carried fill-in is stored once per pair, as F(i,q) with i < q: its rows
+      // are rotated when i is, its columns when q is, each by one product (the
+      // two passes run one after the other, so blocks between two clusters of
+      // one class receive both).
+      auto rot_f = [&](int i, int q) {
+        if (i < q) {
+          const int fb = lp.fblk(i, q);
+          GItem g = item(ref(B_RS, -1), noref(), dx(DK_RT, i), dx(DK_M, q), 1.0, 0.0);
+          g.guard = dx(DK_T, i);
+          cp.rot_rows.add(g, {term(ref(B_W, i), ref(B_F, fb), dx(DK_RT, i))});
+          cp.rot_rows_copy.push_back(CopyItem{ref(B_F, fb), dx(DK_RT, i), dx(DK_M, q), dx(DK_T, i)});
+          cp.rot_rows_copyt.push_back(CopyItem{ref(B_F, fb), dx(DK_M, q), dx(DK_RT, i), dconst(0)});   // no mirror
+        } else {
+          const int fb = lp.fblk(q, i);
+          GItem g = item(ref(B_RS, -1), noref(), dx(DK_RT, i), dx(DK_M, q), 1.0, 0.0);
+          g.guard = dx(DK_T, i);
+          cp.rot_cols_t.add(g, {term(ref(B_W, i), ref(B_F, fb), dx(DK_RT, i))});
+          cp.rot_cols_t_copy.push_back(CopyItem{ref(B_F, fb), dx(DK_M, q), dx(DK_RT, i), dx(DK_T, i)});
+        }
+      };
       for (int i : cp.clusters) {
         for (int k : T.near[l][i]) rot(B_S, lp.blk(i, k), lp.blk(k, i), i, dx(DK_M, k), k == i);
-        for (int q : carried[l][i]) rot(B_F, lp.fblk(i, q), lp.fblk(q, i), i, dx(DK_M, q), col[q] == col[i]);
+        for (int q : carried[l][i]) rot_f(i, q);
         for (int k : T.near[l][i]) {
           GItem g = item(ref(B_RS, -1), noref(), nrows(k), dx(DK_R, i), 1.0, 0.0);
           g.guard = dx(DK_R, i);
@@ -201,12 +222,15 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
           if (J.empty()) continue;
           int sp = (int)slot_p.size();
           slot_p[{k, i}] = sp;
+          cp.slot_p_k.push_back(k);
+          cp.slot_p_i.push_back(i);
           std::vector<int> src;
           for (int j : J) {
             auto key = std::make_pair(j, i);
             if (!slot_m.count(key)) {
               int sm = (int)slot_m.size();
               slot_m[key] = sm;
+              cp.slot_m_i.push_back(i);
               Ref a = ref(B_S, lp.blk(j, i), row0(j), 0);
               cp.gram_m.add(item(ref(B_M, sm), noref(), dx(DK_R, i), dx(DK_R, i), 1.0, 0.0),
                             {term(a, a, nrows(j))});
@@ -235,15 +259,22 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
       lp.max_slot_m = std::max(lp.max_slot_m, cp.nslot_m);
       lp.max_slot_p = std::max(lp.max_slot_p, cp.nslot_p);
     }
-    // Gram of carried fill-in at the start of the level
+    // Gram of carried fill-in at the start of the level: F(p,q) F(p,q)^T for
+    // the blocks stored with p as row cluster, F(q,p)^T F(q,p) for the others
     for (int p = 0; p < N; ++p) {
       if (carried[l][p].empty()) continue;
-      std::vector<GTerm> ts;
+      std::vector<GTerm> up, lo;
       for (int q : carried[l][p]) {
-        Ref a = ref(B_F, lp.fblk(p, q));
-        ts.push_back(term(a, a, dx(DK_M, q)));
+        if (q > p) {
+          Ref a = ref(B_F, lp.fblk(p, q));
+          up.push_back(term(a, a, dx(DK_M, q)));
+        } else {
+          Ref a = ref(B_F, lp.fblk(q, p));
+          lo.push_back(term(a, a, dx(DK_M, q)));
+        }
       }
-      lp.gram_init.add(item(ref(B_G, p), noref(), dx(DK_R, p), dx(DK_R, p), 1.0, 1.0), ts);
+      if (!up.empty()) lp.gram_init.add(item(ref(B_G, p), noref(), dx(DK_R, p), dx(DK_R, p), 1.0, 1.0), up);
+      if (!lo.empty()) lp.gram_init_t.add(item(ref(B_G, p), noref(), dx(DK_R, p), dx(DK_R, p), 1.0, 1.0), lo);
     }
   }
   // merge plans (need both levels' CSR)
@@ -293,7 +324,8 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
           g.src_blk[s] = 0;
           g.cpl_blk[s] = -1;
           if (lp.blk(c, d) >= 0) { g.src_kind[s] = 1; g.src_blk[s] = lp.blk(c, d); }
-          else if (lp.fblk(c, d) >= 0) { g.src_kind[s] = 2; g.src_blk[s] = lp.fblk(c, d); }
+          else if (c < d && lp.fblk(c, d) >= 0) { g.src_kind[s] = 2; g.src_blk[s] = lp.fblk(c, d); }
+          else if (c > d && lp.fblk(d, c) >= 0) { g.src_kind[s] = 3; g.src_blk[s] = lp.fblk(d, c); }
           if (is_near && lp.cslot(c, d) >= 0) g.cpl_blk[s] = lp.cslot(c, d);
           if (lp.blk(c, d) < 0) {
             // generator fill-in from common near neighbours of c and d
@@ -335,30 +367,26 @@ std::vector<LevelPlan> build_plan(const Tree& T, const Basis& B) {
       ch.b1 = (int)mp.tr2.items.size();
       ++h;
     };
-    // Both orientations of a parent pair are stored and (p,q) = (q,p)^T: the
-    // products run for q >= p only, and (p,q) with q < p is a transposed copy
-    // of the finished (q,p).
-    auto mirror_of = [&](int p, int q, bool is_near) {
-      const int dst = is_near ? pp.blk(p, q) : pp.fblk(p, q), src = is_near ? pp.blk(q, p) : pp.fblk(q, p);
+    // Both orientations of a near parent pair are stored and (p,q) = (q,p)^T:
+    // the products run for q >= p only, and (p,q) with q < p is a transposed
+    // copy of the finished (q,p).  Carried fill-in has one block per pair
+    // (q > p) and no mirror.
+    auto mirror_of = [&](int p, int q) {
+      const int dst = pp.blk(p, q), src = pp.blk(q, p);
       if (src < 0) {
-        add_out(p, q, is_near);
+        add_out(p, q, true);
         return;
       }
-      const int buf = is_near ? B_SN : B_FN;
-      CopyItem c{ref(buf, dst), dx(DK_PM, p), dx(DK_PM, q), -1};
-      c.src = ref(buf, src);
+      CopyItem c{ref(B_SN, dst), dx(DK_PM, p), dx(DK_PM, q), -1};
+      c.src = ref(B_SN, src);
       mp.mirror.push_back(c);
     };
     for (int p = 0; p < Np; ++p) {
       for (int q : T.near[l - 1][p]) {
         if (q >= p) add_out(p, q, true);
-        else mirror_of(p, q, true);
+        else mirror_of(p, q);
       }
-      for (int k = pp.f_ptr[p]; k < pp.f_ptr[p + 1]; ++k) {
-        const int q = pp.f_idx[k];
-        if (q >= p) add_out(p, q, false);
-        else mirror_of(p, q, false);
-      }
+      for (int k = pp.f_ptr[p]; k < pp.f_ptr[p + 1]; ++k) add_out(p, pp.f_idx[k], false);
     }
     mp.nhat = h;
   }
