@@ -281,7 +281,8 @@ def merge_queries(paths):
     ks_all = sorted({k for ln in lines for k in ln["config"]["ks"]})
     forms = {}
     for ln in lines:
-        assert ln["config"]["tols"] == tols and ln["config"]["n"] == base["config"]["n"]
+        if ln["config"]["tols"] != tols or ln["config"]["n"] != base["config"]["n"]:
+            raise ValueError("query records of different workloads or tolerances")
         for name, rec in ln["forms"].items():
             dst = forms.setdefault(name, {})
             for k, r in rec.items():
@@ -293,7 +294,8 @@ def merge_queries(paths):
                 d["lam"].update(dict(zip(ln["config"]["ks"], r["lambda"])))
     for name, rec in forms.items():
         for k, d in rec.items():
-            assert sorted(d["lam"]) == ks_all, (name, k)
+            if sorted(d["lam"]) != ks_all:
+                raise ValueError("form %s at %s does not cover every k" % (name, k))
             d["lambda"] = [d["lam"][q] for q in ks_all]
             del d["lam"]
             d["eigvals_per_s"] = len(ks_all) / d["seconds"]

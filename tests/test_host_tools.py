@@ -78,3 +78,56 @@ def test_committed_traffic_record_matches_committed_kernels():
                      + float(fields["write_kib_per_dispatch"]) * float(fields["write_scale"]))
     assert abs(got - want) <= 1e-3 * want
     assert bench.measured_traffic(kernel, n + 1, S) is None and bench.measured_traffic(kernel, n, S + 1) is None
+
+
+def _query_line(forms, ks, tols=(1e-6, 1e-10)):
+    return {"metric": "q", "value": None, "forms": forms,
+            "config": {"n": 1000, "ks": list(ks), "tols": list(tols), "normA": 1.0, "interval": [0.0, 1.0]}}
+
+
+def _rec(seconds, lam, f64=10, f32=0):
+    return {"seconds": seconds, "eigvals_per_s": len(lam) / seconds, "lambda": list(lam), "max_bracket": 1e-12,
+            "evals_f64": f64, "evals_f32": f32}
+
+
+def test_query_merge_adds_groups_and_orders_by_k(tmp_path, capsys):
+    """Groups of k of one form run in separate processes add their seconds and
+    their eigenvalues land at their k; the largest |delta lambda| and the
+    speedups are taken against the plain form at every tolerance."""
+    import json
+    import bench
+    a = _query_line({"plain_f64_1shift": {"tol=1e-06": _rec(10.0, [1.0, 3.0]), "tol=1e-10": _rec(14.0, [1.0, 3.0])}},
+                    [1, 500])
+    b = _query_line({"plain_f64_1shift": {"tol=1e-06": _rec(20.0, [2.0, 4.0]), "tol=1e-10": _rec(26.0, [2.0, 4.0])}},
+                    [250, 750])
+    c = _query_line({"batched_f64": {"tol=1e-06": _rec(15.0, [1.0, 2.0, 3.0, 4.5]),
+                                     "tol=1e-10": _rec(20.0, [1.0, 2.0, 3.0, 4.0])}}, [1, 250, 500, 750])
+    paths = []
+    for name, ln in (("a", a), ("b", b), ("c", c)):
+        p = tmp_path / (name + ".json")
+        p.write_text(json.dumps(ln) + "\n")
+        paths.append(str(p))
+    bench.merge_queries(paths)
+    out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert out["config"]["ks"] == [1, 250, 500, 750]
+    plain = out["forms"]["plain_f64_1shift"]
+    assert plain["tol=1e-06"]["seconds"] == 30.0 and plain["tol=1e-10"]["seconds"] == 40.0
+    assert plain["tol=1e-06"]["lambda"] == [1.0, 2.0, 3.0, 4.0]
+    assert plain["tol=1e-06"]["evals_f64"] == 20
+    d = out["max_abs_dlambda_vs_plain"]["batched_f64"]
+    assert d["tol=1e-06"] == 0.5 and d["tol=1e-10"] == 0.0
+    sp = out["speedup_vs_plain"]["batched_f64"]
+    assert abs(sp["tol=1e-06"] - 2.0) < 1e-12 and abs(sp["tol=1e-10"] - 2.0) < 1e-12
+    assert out["value"] == 4 / 20.0
+
+
+def test_query_merge_rejects_mixed_workloads(tmp_path):
+    import json
+    import bench
+    a = _query_line({"batched_f64": {"tol=1e-06": _rec(1.0, [1.0])}}, [1], tols=(1e-6,))
+    b = _query_line({"batched_f64": {"tol=1e-06": _rec(1.0, [1.0])}}, [2], tols=(1e-8,))
+    pa, pb = tmp_path / "a.json", tmp_path / "b.json"
+    pa.write_text(json.dumps(a))
+    pb.write_text(json.dumps(b))
+    with pytest.raises(ValueError):
+        bench.merge_queries([str(pa), str(pb)])
