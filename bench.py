@@ -301,7 +301,7 @@ def merge_queries(paths):
             d["eigvals_per_s"] = len(ks_all) / d["seconds"]
     line = dict(base)
     line["forms"] = forms
-    line["config"] = dict(base["config"], ks=ks_all, merged_from=len(paths))
+    line["config"] = dict(base["config"], ks=ks_all, merged_from=[os.path.basename(p) for p in paths])
     summarize_queries(line)
     print(json.dumps(line))
 
@@ -373,6 +373,7 @@ def main():
     if args.queries_merge:
         merge_queries(args.queries_merge)
         return
+    os.environ["H2EIG_PROGRESS"] = "1"       # the build reports each level (large builds run for minutes)
     if args.queries:
         queries_bench(args)
         return

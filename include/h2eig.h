@@ -80,6 +80,8 @@ typedef struct {
  * Errors: H2_EINVAL (n < 1, dim not in 1..3, leaf < 2 with n > 1, eta <= 0,
  * eps <= 0, non-finite points, a singular kernel at coincident points),
  * H2_ENOMEM, H2_EDEVICE.
+ * Environment H2EIG_PROGRESS=1: one line per tree level of the basis
+ * construction on stderr.
  */
 h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern,
                    int32_t leaf, double eta, double eps, const h2_opts* opts,

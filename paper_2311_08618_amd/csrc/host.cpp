@@ -26,6 +26,8 @@
 #include "construct.hpp"
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -344,6 +346,8 @@ void build_basis(const Tree& T, const BuildParams& P, double tau, Basis& B, hipS
     }
     FarIdResult ids;
     far_field_ids(FP, P.kern.kind, P.kern.p0, P.kern.p1, lev, ids, st);
+    if (const char* pe = std::getenv("H2EIG_PROGRESS"); pe && pe[0] == '1')
+      std::fprintf(stderr, "[h2eig] build: far-field interpolative decompositions of level %d done\n", l);
     parallel_for(N, nth, [&](int64_t ii) {
       int i = (int)ii;
       const std::vector<int64_t>& rows = rows_of[i];
