@@ -441,12 +441,17 @@ def main():
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP64_TFLOPS,
         "traffic": measured_traffic("h2::" + kname, n, S),
+        # the bytes its products must move at least (operands once, weights,
+        # outputs read and written), per launch, from the device counters
+        "algorithmic_bytes": krec.get("bytes", 0.0) / max(1, krec["launches"]),
         "launches": krec["launches"],
         "avg_launch_ms": krec["ms"] / max(1, krec["launches"]),
         "share_of_step": krec["ms"] / (dt * 1e3),
         "largest_role": {"name": cname, "ms": round(crec["ms"], 1),
                          "bound": "mfma" if cname in GEMM_CLASSES else "latency"},
     }
+    if roofline["traffic"] and roofline["algorithmic_bytes"] > 0:
+        roofline["traffic_over_algorithmic"] = roofline["traffic"] / roofline["algorithmic_bytes"]
     # algorithmic flops of the timed steps (the device counters run in both modes)
     total_flops = sum(v["flops"] for k, v in prof.items() if not k.startswith("kernel:"))
     # k-th eigenvalues per second implied by this rate: one query takes

@@ -303,6 +303,11 @@ int32_t h2_profile_classes(void);
 const char* h2_profile_class_name(int32_t cls);
 /* launches: events pairs recorded; ms: summed event time; flops: algorithmic flops */
 h2_status h2_profile_read(h2_matrix A, int32_t cls, int64_t* launches, double* ms, double* flops);
+/* Algorithmic bytes of the GEMM launches of kernel symbol `cls` (a "kernel:"
+ * class; 0 for the roles): per product, each operand read once, the per-K
+ * weights, the output written (and read when accumulated) and its transposed
+ * twin likewise, 8 bytes per element.  H2_EINVAL for a bad class or NULL. */
+h2_status h2_profile_bytes(h2_matrix A, int32_t cls, double* bytes);
 /* Diagnostic: milliseconds of class `cls` spent at tree level `level` (0 = root)
  * since profiling was enabled.  H2_EINVAL for a bad class, level (>= 32) or NULL. */
 h2_status h2_profile_level_ms(h2_matrix A, int32_t cls, int32_t level, double* ms);
@@ -357,8 +362,9 @@ h2_status h2s_stats(h2_server S, double* p50_ms, double* p99_ms, int64_t* served
 h2_status h2s_latency(h2_server S, double* p50_ms, double* p99_ms, int64_t* unfinished, int64_t* budget_bytes,
                       int64_t* used_bytes);
 /* Stop the workers (in-flight queries are abandoned; a worker inside a
- * factorization finishes it first) and free the server.  No other h2s_ call
- * on S may be running or follow: join the threads that poll or wait first. */
+ * factorization finishes it first), free the factorization workspace of every
+ * added matrix and free the server.  No other h2s_ call on S may be running
+ * or follow: join the threads that poll or wait first. */
 void h2s_destroy(h2_server S);
 
 const char* h2_last_error(void);

@@ -74,6 +74,7 @@ struct BufTab {
   const int* bld[NBUF];
   unsigned long long* fc;   // algorithmic flop counter of the launch's kernel class (or null)
   unsigned long long* fck;  // second counter, per kernel symbol (GEMM layouts), or null
+  unsigned long long* fbk;  // algorithmic bytes per kernel symbol (GEMM layouts), or null
   int f32;                  // GEMMs of this launch multiply in FP32 (operands rounded, FP32 accumulation)
   int grid;                 // GEMM workgroups per shift (0 = from the tuning table), a multiple of 8
   int group_m;              // GEMM tile order inside an item: groups of group_m tile rows,

@@ -172,7 +172,8 @@ struct Profiler {
   double ms[PROF_N] = {0};              // classes, then the GEMM kernel symbols
   long long launches[PROF_N] = {0};
   unsigned long long flops[PROF_N] = {0};
-  unsigned long long* d_fc = nullptr;
+  unsigned long long bytes[PROF_N] = {0};   // algorithmic bytes (GEMM kernel symbols)
+  unsigned long long* d_fc = nullptr;       // flop counters [PROF_N], then byte counters [PROF_N]
   hipEvent_t get() {
     if (used == pool.size()) {
       hipEvent_t e;
@@ -183,7 +184,7 @@ struct Profiler {
   }
   void reset() {
     for (int c = 0; c < PROF_N; ++c) {
-      ms[c] = 0; launches[c] = 0; flops[c] = 0;
+      ms[c] = 0; launches[c] = 0; flops[c] = 0; bytes[c] = 0;
       for (int l = 0; l < 32; ++l) ms_level[c][l] = 0;
     }
   }
@@ -200,9 +201,12 @@ struct Profiler {
     recs.clear();
     used = 0;
     if (d_fc) {
-      unsigned long long h[PROF_N];
+      unsigned long long h[2 * PROF_N];
       HIPCHK(hipMemcpy(h, d_fc, sizeof(h), hipMemcpyDeviceToHost));
-      for (int c = 0; c < PROF_N; ++c) flops[c] += h[c];
+      for (int c = 0; c < PROF_N; ++c) {
+        flops[c] += h[c];
+        bytes[c] += h[PROF_N + c];
+      }
       HIPCHK(hipMemset(d_fc, 0, sizeof(h)));
     }
   }
@@ -737,6 +741,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
       if (tag >= 0 && bt.f32) tag += 4;   // the FP32 kernel symbols follow the FP64 ones
       bt.fc = prof.on ? prof.d_fc + cls : nullptr;
       bt.fck = prof.on && tag >= 0 ? prof.d_fc + PC_N + tag : nullptr;
+      bt.fbk = prof.on && tag >= 0 ? prof.d_fc + PROF_N + PC_N + tag : nullptr;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       const bool ev = prof.on && (!prof.gemm_only || tag >= 0);
       if (ev) {
@@ -752,6 +757,7 @@ void factor_batch(h2_matrix A, const double* sig, int S, bool f32, int64_t* nu_o
       }
       bt.fc = nullptr;
       bt.fck = nullptr;
+      bt.fbk = nullptr;
       bt.f32 = 0;
     };
     SizeTab sz{};
@@ -1639,8 +1645,8 @@ h2_status h2_profile_enable(h2_matrix A, int32_t enable) {
   try {
     HIPCHK(hipSetDevice(A->device));
     if (enable && !A->prof.d_fc) {
-      HIPCHK(hipMalloc(&A->prof.d_fc, (PROF_N) * sizeof(unsigned long long)));
-      HIPCHK(hipMemset(A->prof.d_fc, 0, (PROF_N) * sizeof(unsigned long long)));
+      HIPCHK(hipMalloc(&A->prof.d_fc, 2 * PROF_N * sizeof(unsigned long long)));
+      HIPCHK(hipMemset(A->prof.d_fc, 0, 2 * PROF_N * sizeof(unsigned long long)));
     }
   } catch (HipError& e) {
     return fail(H2_EDEVICE, e.where + ": " + hipGetErrorString(e.e));
@@ -1664,6 +1670,12 @@ h2_status h2_profile_read(h2_matrix A, int32_t cls, int64_t* launches, double* m
   if (launches) *launches = A->prof.launches[cls];
   if (ms) *ms = A->prof.ms[cls];
   if (flops) *flops = (double)A->prof.flops[cls];
+  return H2_OK;
+}
+
+h2_status h2_profile_bytes(h2_matrix A, int32_t cls, double* bytes) {
+  if (!A || cls < 0 || cls >= PROF_N || !bytes) return fail(H2_EINVAL, "bad arguments");
+  *bytes = (double)A->prof.bytes[cls];
   return H2_OK;
 }
 

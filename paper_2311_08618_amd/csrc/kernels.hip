@@ -156,10 +156,21 @@ __device__ __forceinline__ void gemm_body(const GItem* __restrict__ items, int n
   }
   const int m0 = mi * T, n0 = ni * T;
   if (bt.fc && local == 0 && threadIdx.x == 0) {
-    unsigned long long kk = 0;
-    for (int tt = 0; tt < it.nt; ++tt) kk += (unsigned long long)max(0, dev_eval(terms[it.t0 + tt].K, sz, s));
+    unsigned long long kk = 0, kw = 0;
+    for (int tt = 0; tt < it.nt; ++tt) {
+      const unsigned long long k = (unsigned long long)max(0, dev_eval(terms[it.t0 + tt].K, sz, s));
+      kk += k;
+      if (terms[it.t0 + tt].wbuf >= 0) kw += k;
+    }
     atomicAdd(bt.fc, 2ull * (unsigned long long)M * (unsigned long long)N * kk);
     if (bt.fck) atomicAdd(bt.fck, 2ull * (unsigned long long)M * (unsigned long long)N * kk);
+    // the bytes the product must move at least: each operand once, the
+    // weights, C written (and read when accumulated), the twin likewise
+    if (bt.fbk && kk > 0) {
+      const unsigned long long mn = (unsigned long long)M * (unsigned long long)N;
+      const unsigned long long outs = (it.beta != 0.0 ? 2ull : 1ull) * (it.c2.buf >= 0 ? 2ull : 1ull);
+      atomicAdd(bt.fbk, 8ull * ((unsigned long long)(M + N) * kk + kw + outs * mn));
+    }
   }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;

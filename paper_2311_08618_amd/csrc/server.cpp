@@ -252,10 +252,14 @@ void worker_loop(h2_server S, Resident* R) {
       lk.lock();
     }
   }
+  // stopping: the share goes back and the matrix's workspace is freed, so that
+  // a later server (or the caller) finds the memory free
   if (R->held > 0) {
     S->used -= R->held;
     R->held = 0;
   }
+  lk.unlock();
+  (void)h2_release_workspace(R->A);
 }
 
 double percentile(std::vector<double> v, double p) {

@@ -90,6 +90,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.h2_profile_class_name.argtypes = [C.c_int32]
     lib.h2_profile_read.restype = C.c_int
     lib.h2_profile_read.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double)]
+    lib.h2_profile_bytes.restype = C.c_int
+    lib.h2_profile_bytes.argtypes = [C.c_void_p, C.c_int32, P(C.c_double)]
     lib.h2_profile_level_ms.restype = C.c_int
     lib.h2_profile_level_ms.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(C.c_double)]
     lib.h2_inertia_f32.restype = C.c_int
@@ -138,7 +140,7 @@ _lib = load_library()
 
 EXPORTED = ["h2_build", "h2_inertia", "h2_inertia_f32", "h2_set_mixed", "h2_kth_eig", "h2_norm", "h2_stats", "h2_set_stream", "h2_tree_perm",
             "h2_basis_ranks", "h2_level_stats", "h2_count", "h2_eigs_in", "h2_gap", "h2_matvec", "h2_kernel_matvec", "h2_kernel_matvec_noalloc",
-            "h2_profile_enable", "h2_profile_classes", "h2_profile_class_name", "h2_profile_read",
+            "h2_profile_enable", "h2_profile_classes", "h2_profile_class_name", "h2_profile_read", "h2_profile_bytes",
             "h2_profile_level_ms", "h2_interval", "h2_capacity", "h2_set_max_shifts", "h2_level_dims",
             "h2_set_gemm_tuning", "h2_get_gemm_tuning", "h2_free", "h2_last_error",
             "h2s_create", "h2s_latency", "h2_release_workspace", "h2s_add", "h2s_submit", "h2s_poll", "h2s_wait", "h2s_stats", "h2s_destroy"]
@@ -313,7 +315,10 @@ class H2Matrix:
             ms = C.c_double()
             fl = C.c_double()
             _check(_lib.h2_profile_read(self._h, c, C.byref(n), C.byref(ms), C.byref(fl)))
-            out[_lib.h2_profile_class_name(c).decode()] = {"launches": n.value, "ms": ms.value, "flops": fl.value}
+            by = C.c_double()
+            _check(_lib.h2_profile_bytes(self._h, c, C.byref(by)))
+            out[_lib.h2_profile_class_name(c).decode()] = {"launches": n.value, "ms": ms.value, "flops": fl.value,
+                                                           "bytes": by.value}
         return out
 
     def profile_levels(self, levels: int = 32) -> dict:
