@@ -115,7 +115,7 @@ def serve_bench(args):
         ids = [srv.add(A) for A in mats]
         add_s = time.perf_counter() - t0
         print("serve: resident, workspace per shift measured in %.1f s" % add_s, file=sys.stderr, flush=True)
-        rng = np.random.default_rng(7 + ri)               # its own arrivals and queries per rate
+        rng = np.random.default_rng(args.serve_seed + ri)  # its own arrivals and queries per rate
         window = max(args.serve_window, 4.0 / rate)      # at least ~4 arrivals at low rates
         cap = window + args.serve_cap                    # drain after the last possible arrival
         arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * window * 2) + 16))
@@ -176,9 +176,9 @@ def serve_bench(args):
         "p99_ms_censored": best["p99_ms_censored"],
         "sweep": sweep,
         "config": {"workload": "cube-laplace resident n=%s leaf=256 eta=1 eps=1e-8 A_ii=1e3; Poisson arrivals "
-                               "(seed 7 + index of the rate) at %s/s for max(%g s, 4/rate), k uniform in [1,n], tol 1e-6 or 1e-10 "
+                               "(seed %d + index of the rate) at %s/s for max(%g s, 4/rate), k uniform in [1,n], tol 1e-6 or 1e-10 "
                                "(p=0.5); drain %g s after the arrival window; admission by one shared HBM budget "
-                               "(85%% of free memory)" % (sizes, rates, args.serve_window, args.serve_cap),
+                               "(85%% of free memory)" % (sizes, args.serve_seed, rates, args.serve_window, args.serve_cap),
                    "max_slots": args.serve_slots_max, "build_s": round(build_s, 1)},
     }
     print(json.dumps(line))
@@ -355,6 +355,7 @@ def main():
     ap.add_argument("--serve-slots-max", type=int, default=16, help="most in-flight queries per matrix")
     ap.add_argument("--serve-rate", default="200", help="Poisson arrivals per second (comma list: a sweep)")
     ap.add_argument("--serve-window", type=float, default=1.0, help="seconds of arrivals")
+    ap.add_argument("--serve-seed", type=int, default=7, help="seed of the arrivals of the first rate")
     ap.add_argument("--serve-cap", type=float, default=120.0,
                     help="seconds of drain after the arrival window until the measurement stops")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
