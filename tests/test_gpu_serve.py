@@ -131,3 +131,42 @@ def test_serve_shared_memory_budget(lib):
         assert S.latency()["unfinished"] == 0
     finally:
         S.close()
+
+
+def _free_device_bytes():
+    """hipMemGetInfo of the current device, through the HIP runtime the library
+    already initialised in this process."""
+    import ctypes
+    try:
+        hip = ctypes.CDLL("libamdhip64.so.7")       # the runtime libh2eig.so loaded
+    except OSError:
+        hip = ctypes.CDLL("/opt/rocm/lib/libamdhip64.so")
+    free, total = ctypes.c_size_t(), ctypes.c_size_t()
+    assert hip.hipMemGetInfo(ctypes.byref(free), ctypes.byref(total)) == 0
+    return free.value
+
+
+def test_serve_destroy_frees_workspace(lib):
+    """A server destroyed while its queries are in flight frees the
+    factorization workspace of its matrices: the device memory held before the
+    server existed is all that remains held."""
+    print("case serve destroy: cube n=16384 with queries in flight", flush=True)
+    A = lib.H2Matrix(W.cube_points(16384, 3), W.K_LAPLACE, 1e3, 256, 1.0, 1e-8)
+    A.interval()
+    free0 = _free_device_bytes()
+    S = lib.H2Server(max_slots=4)
+    try:
+        i = S.add(A)
+        for k in (1, 4000, 8000, 16000):
+            S.submit(i, k, 1e-12)
+        t0 = time.time()
+        while S.latency()["used_bytes"] == 0 and time.time() - t0 < 60:
+            time.sleep(0.01)
+        assert S.latency()["used_bytes"] > 0
+        time.sleep(1.0)                     # the first batched factorization has its arenas
+        assert S.latency()["unfinished"] > 0
+    finally:
+        S.close()
+    free1 = _free_device_bytes()
+    assert free1 >= free0 - (64 << 20), (free0, free1)
+    A.close()
