@@ -327,3 +327,127 @@ def test_rrqr_directions_span_and_bound():
     assert t == 5
     Q, _ = np.linalg.qr(At)
     assert np.linalg.norm(X - Q @ (Q.T @ X)) < 1e-9
+
+
+def test_kth_eig_cube_tight_tolerance(cube_h2):
+    """Algorithm 1 on the oracle to tol 1e-9: the factorization truncates the
+    fill-in at the same budget as the construction, so the eigenvalues of both
+    the assembled A~ and the kernel matrix A (LAPACK) lie within
+    tol/2 + 10 eps normA, and the result moves by less than that bound when the
+    tolerance tightens from 1e-6."""
+    H, A, Ah, ev_h, ev_a = cube_h2
+    tol = 1e-9
+    bound = tol / 2 + 10 * H.eps * H.normA
+    for k in (3, 512, 1000):
+        lam = kth_eigs(H, [k], tol)[0]
+        assert abs(lam - ev_h[k - 1]) <= bound, (k, lam, ev_h[k - 1])
+        assert abs(lam - ev_a[k - 1]) <= bound, (k, lam, ev_a[k - 1])
+        assert abs(lam - kth_eigs(H, [k], 1e-6)[0]) <= 1e-6 / 2 + tol / 2
+
+
+# ---------------------------------------------------------------- T0: the trees
+# Properties of the cluster tree, the block tree and the colouring recomputed
+# from the points alone, so that a wrong split axis, half size, admissibility
+# test, list or colour fails one of them.
+
+@pytest.fixture(scope="module")
+def tree3d():
+    from oracle.tree import Tree
+    X = np.random.default_rng(11).random((1000, 3)) * np.array([1.0, 3.0, 0.5])
+    return X, Tree(X, 32, 1.0)
+
+
+def test_tree_partition_and_depth(tree3d):
+    X, T = tree3d
+    n = len(X)
+    assert np.array_equal(np.sort(T.perm()), np.arange(n))
+    sizes = [len(a) for a in T.idx[T.L]]
+    assert max(sizes) <= T.leaf and len(sizes) == 1 << T.L
+    # the depth is the smallest one at which every cluster fits in a leaf
+    assert max(len(a) for a in T.idx[T.L - 1]) > T.leaf
+    for l in range(T.L):
+        for i, a in enumerate(T.idx[l]):
+            assert np.array_equal(np.sort(T.pts(l, i)), np.sort(a))
+
+
+def test_tree_splits_at_the_median_of_the_longest_axis(tree3d):
+    X, T = tree3d
+    for l in range(T.L):
+        for p, a in enumerate(T.idx[l]):
+            P = X[a]
+            ext = P.max(axis=0) - P.min(axis=0)
+            ax = int(np.argmax(ext))
+            left, right = T.idx[l + 1][2 * p], T.idx[l + 1][2 * p + 1]
+            assert len(left) == len(a) // 2 and len(left) + len(right) == len(a)
+            assert X[left, ax].max() <= X[right, ax].min()
+
+
+def _bbox(P):
+    lo, hi = P.min(axis=0), P.max(axis=0)
+    return 0.5 * (lo + hi), 0.5 * np.linalg.norm(hi - lo)
+
+
+def test_block_tree_tiles_the_matrix_once(tree3d):
+    """Near leaf pairs and the interaction lists of every level cover every
+    entry (x, y) exactly once; lists are symmetric; each interaction pair
+    meets the admissibility condition recomputed from its points, each near
+    leaf pair with distinct clusters fails it."""
+    X, T = tree3d
+    n = len(X)
+    cover = np.zeros((n, n), dtype=np.int32)
+    for l in range(1, T.L + 1):
+        for i in range(1 << l):
+            for j in T.far[l][i]:
+                assert i in T.far[l][j]
+                ci, ri = _bbox(X[T.pts(l, i)])
+                cj, rj = _bbox(X[T.pts(l, j)])
+                assert T.eta * np.linalg.norm(ci - cj) >= ri + rj
+                cover[np.ix_(T.pts(l, i), T.pts(l, j))] += 1
+    L = T.L
+    for i in range(1 << L):
+        assert i in T.near[L][i]
+        for j in T.near[L][i]:
+            assert i in T.near[L][j]
+            if j != i:
+                ci, ri = _bbox(X[T.pts(L, i)])
+                cj, rj = _bbox(X[T.pts(L, j)])
+                assert T.eta * np.linalg.norm(ci - cj) < ri + rj
+            cover[np.ix_(T.pts(L, i), T.pts(L, j))] += 1
+    assert cover.min() == 1 and cover.max() == 1
+
+
+def test_colouring_is_valid_and_greedy(tree3d):
+    """No two near clusters share a colour, and every cluster's colour is the
+    smallest one its lower-indexed near neighbours leave free."""
+    X, T = tree3d
+    for l in range(T.L + 1):
+        col = T.colour[l]
+        for i in range(1 << l):
+            for j in T.near[l][i]:
+                if j != i:
+                    assert col[i] != col[j], (l, i, j)
+            lower = {col[j] for j in T.near[l][i] if j < i}
+            assert col[i] not in lower and all(c in lower for c in range(col[i]))
+        # the elimination order is colour-major, index-minor
+        order = T.order[l]
+        keys = [(col[i], i) for i in order]
+        assert keys == sorted(keys) and sorted(order) == list(range(1 << l))
+
+
+def test_mutation_weak_admissibility_test_is_caught(monkeypatch):
+    """Planted mistake: admissibility against the larger radius only.  The
+    block tree still tiles the matrix, but an interaction pair then violates
+    the condition recomputed from its points."""
+    from oracle import tree as OT
+    X = np.random.default_rng(11).random((1000, 3)) * np.array([1.0, 3.0, 0.5])
+
+    def weak(self, l, i, j):
+        if i == j:
+            return False
+        d = float(np.linalg.norm(self.center[l][i] - self.center[l][j]))
+        return d > 0.0 and self.eta * d >= max(self.radius[l][i], self.radius[l][j])
+
+    monkeypatch.setattr(OT.Tree, "admissible", weak)
+    T = OT.Tree(X, 32, 1.0)
+    with pytest.raises(AssertionError):
+        test_block_tree_tiles_the_matrix_once((X, T))
