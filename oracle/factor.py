@@ -102,8 +102,13 @@ def _rotate(i, W, R_i, S, F, nbS, nbF):
             blk[:, :R_i] = blk[:, :R_i] @ W
 
 
-def inertia(H, sigma: float, stats: dict | None = None) -> int:
-    """nu(A~ - sigma I) = #{lambda(A~) < sigma} by the generalized H^2-LDL."""
+def inertia(H, sigma: float, stats: dict | None = None, on_level=None) -> int:
+    """nu(A~ - sigma I) = #{lambda(A~) < sigma} by the generalized H^2-LDL.
+
+    on_level, if given, is called after the eliminations of every level l and
+    before its merge as on_level(l, nu, S, F, m, R): the negative pivots
+    counted so far and the blocks that hold the remaining (skeleton) system,
+    for checks of the inertia bookkeeping; it must not modify them."""
     T, L = H.tree, H.tree.L
     m = list(H.m[L])
     r0 = list(H.r[L])
@@ -176,6 +181,8 @@ def inertia(H, sigma: float, stats: dict | None = None) -> int:
             stats["t"].append(tl)
             stats["R"].append(list(R))
             stats["m"].append(list(m))
+        if on_level is not None:
+            on_level(l, nu, S, F, list(m), list(R))
         if l == 0:
             break
         # ---- merge to level l-1

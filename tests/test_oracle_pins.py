@@ -451,3 +451,107 @@ def test_mutation_weak_admissibility_test_is_caught(monkeypatch):
     T = OT.Tree(X, 32, 1.0)
     with pytest.raises(AssertionError):
         test_block_tree_tiles_the_matrix_once((X, T))
+
+
+# ------------------------------------------------- Haynsworth, level by level
+def _trailing_dense(H, l, S, F, m, R, couplings=True):
+    """The remaining system after the eliminations of level l, assembled densely
+    from the oracle's blocks and the construction's couplings and transfer
+    matrices: near blocks and carried fill-in on the skeleton parts, and for
+    every other pair the coupling of the level at which its ancestors are
+    admissible, brought down to level l through the skeleton columns of the
+    transfer matrices."""
+    T = H.tree
+    N = 1 << l
+    s = [m[c] - R[c] for c in range(N)]
+    t = [s[c] - H.r[l][c] for c in range(N)]
+    off = np.concatenate([[0], np.cumsum(s)]).astype(int)
+
+    def down(c, lp):
+        """Old-skeleton coordinates of c (level l) from the skeleton coordinates
+        of its ancestor at level lp."""
+        M = np.eye(H.r[l][c])
+        for lv in range(l - 1, lp - 1, -1):
+            a, ch = c >> (l - lv), c >> (l - lv - 1)
+            E = H.Q[lv][a]
+            Es = E[:, E.shape[1] - H.r[lv][a]:]
+            r1 = H.r[lv + 1][2 * a]
+            rows = slice(0, r1) if ch == 2 * a else slice(r1, r1 + H.r[lv + 1][2 * a + 1])
+            M = M @ Es[rows, :]
+        return M
+
+    D = np.zeros((off[-1], off[-1]))
+    for c in range(N):
+        for d in range(N):
+            if d in T.near_set[l][c]:
+                blk = S[(c, d)][R[c]:, R[d]:]
+            else:
+                blk = np.zeros((s[c], s[d]))
+                if (c, d) in F:
+                    blk = blk + F[(c, d)][R[c]:, R[d]:]
+                for lp in range(l, 0, -1):
+                    p, q = c >> (l - lp), d >> (l - lp)
+                    if couplings and q in T.far[lp][p]:
+                        blk[t[c]:, t[d]:] += down(c, lp) @ H.C[lp][(p, q)] @ down(d, lp).T
+                        break
+            D[off[c]:off[c + 1], off[d]:off[d + 1]] = blk
+    return D
+
+
+@pytest.mark.parametrize("eta", [1.0, 0.7])
+def test_haynsworth_after_every_level(eta):
+    """Sylvester/Haynsworth bookkeeping of the oracle's elimination: after every
+    level, the negative pivots counted so far plus the negative eigenvalues of
+    the remaining system (assembled independently, above) equal the count of
+    the whole matrix A~ - sigma I (LAPACK), at shifts farther than the window
+    from every eigenvalue of A~."""
+    H, ev, sig = _haynsworth_case(eta)
+    for s0 in sig:
+        want = int(np.sum(ev < s0))
+        seen = []
+
+        def check(l, nu, S, F, m, R):
+            D = _trailing_dense(H, l, S, F, m, R)
+            rest = int(np.sum(np.linalg.eigvalsh(0.5 * (D + D.T)) < 0.0)) if D.size else 0
+            seen.append((l, nu, rest))
+            assert nu + rest == want, (s0, l, nu, rest, want)
+
+        assert OF.inertia(H, s0, on_level=check) == want
+        # levels with pivots counted and a system left (three at eta = 1)
+        assert sum(1 for _, nu, rest in seen if nu > 0 and rest > 0) >= (2 if eta == 1.0 else 1), seen
+
+
+def _haynsworth_case(eta):
+    """n = 1024, eps = 1e-6 (ranks low enough that three levels eliminate),
+    shifts midway in gaps wider than twice the truncation's 10 eps normA."""
+    n, leaf, eps = 1024, 32, 1e-6
+    H = H2(W.cube_points(n, 5), Kernel(0, 1e3), leaf, eta, eps)
+    ev = np.linalg.eigvalsh(H.dense())
+    w = 10 * eps * H.normA
+    sig = []
+    for q in (0.1, 0.35, 0.6, 0.9):
+        k = int(q * n)
+        while k + 1 < n and ev[k + 1] - ev[k] <= 2 * w:
+            k += 1
+        if k + 1 < n:
+            sig.append(0.5 * (ev[k] + ev[k + 1]))
+    assert len(sig) >= 3
+    return H, ev, sig
+
+
+def test_haynsworth_check_sees_a_missing_coupling():
+    """The same bookkeeping with the ancestors' couplings left out of the
+    remaining system must fail at some level (the check is not vacuous)."""
+    H, ev, sig = _haynsworth_case(1.0)
+    s0 = sig[0]
+    want = int(np.sum(ev < s0))
+    bad = []
+
+    def check(l, nu, S, F, m, R):
+        D = _trailing_dense(H, l, S, F, m, R, couplings=False)
+        rest = int(np.sum(np.linalg.eigvalsh(0.5 * (D + D.T)) < 0.0)) if D.size else 0
+        if nu + rest != want:
+            bad.append(l)
+
+    OF.inertia(H, s0, on_level=check)
+    assert bad
