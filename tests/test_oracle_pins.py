@@ -555,3 +555,34 @@ def test_haynsworth_check_sees_a_missing_coupling():
 
     OF.inertia(H, s0, on_level=check)
     assert bad
+
+
+def test_rank_statistics_bookkeeping():
+    """The oracle's per-level statistics (directions t kept by recompression,
+    pivot sizes R, cluster dimensions m) obey what the elimination fixes:
+    every coordinate is eliminated exactly once (the pivot sizes of all levels
+    add up to n), a cluster's pivot block is its redundant part m - r0 less the
+    t new skeleton directions, and a parent's dimension is its children's
+    skeleton parts, t + r0 each."""
+    n, leaf, eps = 1024, 32, 1e-6
+    H = H2(W.cube_points(n, 5), Kernel(0, 1e3), leaf, 1.0, eps)
+    st = {}
+    OF.inertia(H, float(np.median(np.linalg.eigvalsh(H.dense()))) + 1e-3, st)
+    L = H.tree.L
+    total = 0
+    for j, (tl, Rl, ml) in enumerate(zip(st["t"], st["R"], st["m"])):
+        l = L - j
+        r0 = H.r[l] if l > 0 else [0]
+        for i in range(1 << l):
+            assert tl[i] >= 0 and Rl[i] >= 0
+            r = r0[i] if l > 0 else 0
+            assert Rl[i] == ml[i] - r - tl[i] or l == 0, (l, i)
+        if j > 0:
+            tc, mc = st["t"][j - 1], st["m"][j - 1]
+            rc = H.r[l + 1]
+            for p in range(1 << l):
+                assert ml[p] == sum(tc[c] + rc[c] for c in (2 * p, 2 * p + 1)), (l, p)
+        total += sum(Rl)
+        if l == 0:
+            assert Rl[0] == ml[0]
+    assert total == n
