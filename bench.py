@@ -323,10 +323,20 @@ def cpu_baseline(n_sample: int = 4096, shifts: int = 4, n_target: int = 262144) 
         inertia(H, float(s))
     dt = (time.perf_counter() - t0) / shifts
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": (1.0 / dt) * (n_sample / n_target),
         "unit": "evals/s",
         "cores": int(threads),
+        "cpu_model": cpu_model,
         "kind": "oracle",
         "sample": ("%d shifts of the oracle at n=%d (same kernel, leaf 256, eta 1, eps 1e-8), %.2f s per "
                    "shift, scaled linearly by n=%d/%d (the paper's O(n) per factorization; measured cost grows "
