@@ -92,6 +92,9 @@ def test_null_handles(mod):
     assert L.h2_norm(None, C.byref(x)) == mod.H2_EINVAL
     assert L.h2_tree_perm(None, None) == mod.H2_EINVAL
     assert L.h2_profile_enable(None, 1) == mod.H2_EINVAL
+    assert L.h2_profile_bytes(None, 0, C.byref(x)) == mod.H2_EINVAL
+    assert L.h2_profile_read(None, 0, None, None, None) == mod.H2_EINVAL
+    assert L.h2_release_workspace(None) == mod.H2_EINVAL
     L.h2_free(None)   # no-op
 
 
