@@ -21,10 +21,23 @@ Plain, slow and written for a reader holding the paper (Apriansyah & Yokota,
   * ``dense``   brute-force checkers: dense inertia, cyclic Jacobi eigensolver,
                 closed-form 1-D Laplacian spectrum.
 
-Pins (all in ``tests/test_oracle_*.py``, marked "not gpu"): the closed-form
-spectrum 2-2cos(j*pi/(n+1)) of the 1-D second-difference matrix, for every
-shift, through the full hierarchical path with and without fill-in; dense
-inertia of the assembled H^2 matrix and of the exact kernel matrix; the
-Jacobi eigensolver; per-level Sylvester/Haynsworth additivity.  Factor values
-(individual pivots, ranks) are "parity unpinned": they depend on truncation.
+Pins (all in ``tests/test_oracle_pins.py``, marked "not gpu"):
+  * the closed-form spectrum 2-2cos(j*pi/(n+1)) of the 1-D second-difference
+    matrix, for every shift, through the full hierarchical path with and
+    without fill-in, and through bisection at large n;
+  * dense inertia of the assembled H^2 matrix and of the exact kernel matrix,
+    k-th eigenvalues against LAPACK at loose and tight tolerance, and every
+    eigenvalue of the circle matrix within half the paper's tolerance (Sec. 5.1);
+  * the construction bound ||A - A~||_2 <= 10 eps ||A|| (n = 1024 and 8192),
+    the row ID's Frobenius stopping rule and the block-row budget;
+  * the tree: partition, depth and median split, the block tree tiling every
+    entry once, a valid greedy colouring;
+  * Sylvester/Haynsworth additivity after every level of the factorization;
+  * the Jacobi eigensolver, the rank-revealing QR and Gershgorin bounds;
+  * planted mistakes (a sampled far field, a dropped recompression, a wrong
+    Schur sign, a transposed transfer matrix, a wrong admissibility test, a
+    missing coupling) that one of the above must catch.
+Individual factor values (pivots, ranks) depend on truncation: they are
+"parity unpinned" one by one; their per-level sums are checked against the
+bookkeeping of the factorization itself.
 """
