@@ -29,6 +29,7 @@
 #include "host.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "records.hpp"
 
 using namespace h2;
 
@@ -244,8 +245,9 @@ struct h2_matrix_s {
   Arena sf[2], lvl, mrg, small, rs;
   Arena tab[2];   // block offset / leading-dimension tables of the blocks in sf[0] / sf[1]
   Arena stab;     // offset / leading-dimension tables of the current level's fill-in Gram slots
-  // slicing cache and statistics
-  std::vector<std::pair<double, int64_t>> cache;
+  // slicing cache (FP64 inertia records, sorted by shift, runs of equal counts
+  // compacted) and statistics
+  std::vector<h2::Record> cache;
   bool have_gersh = false;
   double mixed_rel = 0.0;
   std::vector<std::vector<int64_t>> lstats;   // per level, per shift of the last factorization: sum t, sum m, max m, sum R
@@ -1120,15 +1122,15 @@ h2_status run_inertia(h2_matrix A, const double* sigma, int64_t ns, bool f32, in
       A->mrg.release();
       A->rs.release();
       for (auto& a : A->tab) a.release();
-  A->stab.release();
       A->stab.release();
       A->arena_shifts = 0;
       continue;
     }
     for (int k = 0; k < S; ++k) {
       if (nu[s0 + k] < 0) anybad = true;
-      else if (!f32) A->cache.push_back({sigma[s0 + k], nu[s0 + k]});
+      else if (!f32) h2::record_insert(A->cache, sigma[s0 + k], nu[s0 + k]);
     }
+    if (!f32) h2::record_compact(A->cache);
     int32_t& cnt = f32 ? A->st.evals_f32 : A->st.evals_f64;
     cnt = (int32_t)std::min<int64_t>(INT32_MAX, (int64_t)cnt + S);
     s0 += S;
@@ -1328,22 +1330,10 @@ h2_status h2_kth_eig(h2_matrix A, const int64_t* k, int64_t nk, double tol, cons
       else lo[j] = mu;
     }
   };
-  auto has64 = [&](double mu) {
-    for (const auto& rec : A->cache)
-      if (rec.first == mu) return true;
-    return false;
-  };
+  auto has64 = [&](double mu) { return h2::record_has(A->cache, mu); };
   // the bracket of j from FP64 counts alone: the largest shift below k
   // eigenvalues, then the smallest shift above it with at least k
-  auto rebuild = [&](int64_t j) {
-    double L = a0, H = b0;
-    for (const auto& rec : A->cache)
-      if (rec.second < k[j] && rec.first > L && rec.first < b0) L = rec.first;
-    for (const auto& rec : A->cache)
-      if (rec.second >= k[j] && rec.first > L && rec.first < H) H = rec.first;
-    lo[j] = L;
-    hi[j] = H;
-  };
+  auto rebuild = [&](int64_t j) { h2::record_bracket(A->cache, k[j], a0, b0, &lo[j], &hi[j]); };
   for (auto& rec : A->cache) narrow(rec.first, rec.second, false);
   const char* pe = std::getenv("H2EIG_PROGRESS");
   const bool progress = pe && pe[0] == '1';

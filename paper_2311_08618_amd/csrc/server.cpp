@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/h2eig.h"
+#include "records.hpp"
 
 namespace h2 {
 void set_last_error(const std::string& msg);
@@ -61,7 +62,7 @@ struct Resident {
   int64_t held = 0;         // budget held: per_shift times the shifts it can factor together now
   std::deque<int64_t> queue;
   std::vector<int64_t> active;
-  std::vector<std::pair<double, int64_t>> records;   // (mu, nu), sorted by mu
+  std::vector<h2::Record> records;   // (mu, nu), sorted by mu, runs of equal nu compacted
   std::thread worker;
 };
 
@@ -88,25 +89,8 @@ h2_status fail(h2_status s, const char* msg) {
   return s;
 }
 
-void add_record(Resident& R, double mu, int64_t nu) {
-  auto it = std::lower_bound(R.records.begin(), R.records.end(), std::make_pair(mu, (int64_t)INT64_MIN));
-  if (it != R.records.end() && it->first == mu) return;
-  R.records.insert(it, {mu, nu});
-}
-
-// the starting bracket of a query for lambda_k from the matrix's records: the
-// record of largest mu with nu < k and the next record with nu >= k, found by
-// binary search (counts grow with mu) and each end checked on its own
-void seed_bracket(const Resident& R, Query& x) {
-  x.lo = R.a0;
-  x.hi = R.b0;
-  const auto& v = R.records;
-  const size_t p = std::partition_point(v.begin(), v.end(), [&](const std::pair<double, int64_t>& r) {
-                     return r.second < x.k;
-                   }) - v.begin();
-  if (p > 0 && v[p - 1].second < x.k && v[p - 1].first > x.lo && v[p - 1].first < x.hi) x.lo = v[p - 1].first;
-  if (p < v.size() && v[p].second >= x.k && v[p].first > x.lo && v[p].first < x.hi) x.hi = v[p].first;
-}
+// the starting bracket of a query for lambda_k from the matrix's records
+void seed_bracket(const Resident& R, Query& x) { h2::record_bracket(R.records, x.k, R.a0, R.b0, &x.lo, &x.hi); }
 
 // narrow [lo, hi] of every in-flight query of the matrix by the record (mu, nu)
 void narrow(h2_server S, Resident& R, double mu, int64_t nu) {
@@ -234,9 +218,10 @@ void worker_loop(h2_server S, Resident* R) {
     R->active.swap(keep);
     for (size_t j = 0; j < mus.size(); ++j) {
       if (sts[j] != H2_OK) continue;
-      add_record(*R, mus[j], nus[j]);
+      h2::record_insert(R->records, mus[j], nus[j]);
       narrow(S, *R, mus[j], nus[j]);
     }
+    h2::record_compact(R->records);
     complete(S, *R);
     // nothing in flight: give the share back when the queue is empty, or
     // when another matrix waits for budget (then step aside briefly so that

@@ -1,7 +1,7 @@
-"""Host-side logic of the measurement and tuning tools (no device work):
-the autotuner's mapping of profiler symbols and capacities to table entries,
-and the bench's use of a committed counter record only while it matches the
-kernel, the workload and the kernel source."""
+"""Host-side logic (no device work): the autotuner's mapping of profiler
+symbols and capacities to table entries, the bench's use of a committed counter
+record only while it matches the kernel, the workload and the kernel source,
+the merge of separate query runs, and the inertia-record cache of the library."""
 import hashlib
 import os
 import re
@@ -131,3 +131,20 @@ def test_query_merge_rejects_mixed_workloads(tmp_path):
     pb.write_text(json.dumps(b))
     with pytest.raises(ValueError):
         bench.merge_queries([str(pa), str(pb)])
+
+
+def test_inertia_record_cache(tmp_path):
+    """The record cache shared by h2_kth_eig and the serving loop
+    (csrc/records.hpp): a C++ harness compares brackets from the compacted list
+    with brackets from every record ever inserted (Sec. 4.2's inertia reuse)."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not found")
+    here = os.path.dirname(os.path.abspath(__file__))
+    exe = str(tmp_path / "records_check")
+    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-Wextra", "-Werror", "-o", exe,
+                    os.path.join(here, "records_check.cpp")], check=True)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout + out.stderr
