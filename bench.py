@@ -372,7 +372,7 @@ def main():
                     help="only run a plain device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the batch of shifts is one GPU's share); "
+        print("bench.py: the library runs on one GPU only (the batch of shifts is one GPU's share); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.copy_calib:
@@ -384,7 +384,7 @@ def main():
     if args.queries_merge:
         merge_queries(args.queries_merge)
         return
-    os.environ["H2EIG_PROGRESS"] = "1"       # the build reports each level (large builds run for minutes)
+    os.environ["H2EIG_PROGRESS"] = "1"       # h2_build reports each level (large constructions run for minutes)
     if args.queries:
         queries_bench(args)
         return

@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Bars (from the method's accuracy statement and the build's targets):
+Bars (from the method's accuracy statement and the construction tolerance):
   * inertia: equal to the oracle's for every shift whose window
     [sigma - w, sigma + w], w = 1e3 * eps * normA, holds no eigenvalue change of
     the oracle (nu_or(sigma - w) == nu_or(sigma + w)); otherwise
