@@ -98,8 +98,10 @@ h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern,
  *            or non-finite pivot (its nu is then -1).
  * Returns H2_ENUMERIC if any shift failed (the others are still valid).
  * Every count obtained joins the handle's record cache of (sigma, nu) pairs,
- * kept for the handle's lifetime (16 bytes per shift), from which h2_kth_eig
- * narrows its brackets before factoring anything (Sec. 4.2).
+ * kept sorted by sigma for the handle's lifetime, from which h2_kth_eig
+ * narrows its brackets before factoring anything (Sec. 4.2).  Of a run of
+ * records with equal counts only the first and the last can end a bracket, so
+ * only those are kept: at most two records (16 bytes each) per distinct count.
  */
 h2_status h2_inertia(h2_matrix A, const double* sigma, int64_t nshift,
                      int64_t* nu, int32_t* status);
