@@ -352,7 +352,8 @@ h2_status h2s_submit(h2_server S, int32_t id, int64_t k, double tol, int64_t* ti
  * the call that reports it done (or failed) forgets it. */
 h2_status h2s_poll(h2_server S, int64_t ticket, double* lambda, int32_t* done);
 /* Block until the query has finished (H2_EINVAL if the server stops first);
- * forgets the ticket as h2s_poll does. */
+ * forgets the ticket as h2s_poll does.  If another h2s_poll or h2s_wait reads
+ * the ticket first, this call returns H2_EINVAL. */
 h2_status h2s_wait(h2_server S, int64_t ticket, double* lambda);
 /* Latency percentiles (submission to completion, ms) of the finished queries,
  * and the numbers of finished and submitted queries. */

@@ -360,7 +360,13 @@ h2_status h2s_wait(h2_server S, int64_t ticket, double* lambda) {
   std::unique_lock<std::mutex> lk(S->mu);
   auto it = S->q.find(ticket);
   if (it == S->q.end()) return fail(H2_EINVAL, "unknown ticket");
-  S->cv_done.wait(lk, [&] { return it->second.state >= 2 || S->stop; });
+  // looked up again at every wake: another h2s_poll or h2s_wait on the same
+  // ticket may have read, and so forgotten, it meanwhile
+  S->cv_done.wait(lk, [&] {
+    it = S->q.find(ticket);
+    return it == S->q.end() || it->second.state >= 2 || S->stop;
+  });
+  if (it == S->q.end()) return fail(H2_EINVAL, "ticket read by another call");
   if (it->second.state == 3) {
     const h2_status st = it->second.status;
     S->q.erase(it);

@@ -133,6 +133,51 @@ def test_serve_shared_memory_budget(lib):
         S.close()
 
 
+def test_serve_two_readers_of_one_ticket(lib):
+    """h2s_wait in a thread and h2s_poll in the caller on the same ticket:
+    exactly one of them reports the eigenvalue (closed form), the other finds
+    the ticket already read (H2_EINVAL), and neither blocks."""
+    import threading
+    print("case serve two readers of one ticket, tridiag n=1024", flush=True)
+    n, tol = 1024, 1e-9
+    T = lib.H2Matrix(W.line_points(n), W.K_TRIDIAG_1D, 2.0, 32, 1.0, 1e-12, p0=1.0)
+    exact = tridiag_eigs(n)
+    S = lib.H2Server(max_slots=2)
+    try:
+        m = S.add(T)
+        for k in (1, 300, n):
+            t = S.submit(m, k, tol)
+            got = []
+
+            def reader(t=t, got=got):
+                try:
+                    got.append(("wait", S.wait(t)))
+                except lib.H2EigError:
+                    got.append(("wait", None))
+
+            th = threading.Thread(target=reader)
+            th.start()
+            t0 = time.time()
+            while True:
+                try:
+                    lam = S.poll(t)
+                except lib.H2EigError:
+                    got.append(("poll", None))
+                    break
+                if lam is not None:
+                    got.append(("poll", lam))
+                    break
+                assert time.time() - t0 < 60
+                time.sleep(0.001)
+            th.join(60)
+            assert not th.is_alive()
+            vals = [v for _, v in got if v is not None]
+            assert len(got) == 2 and len(vals) == 1, got
+            assert abs(vals[0] - exact[k - 1]) <= tol / 2 + 10 * 1e-12 * T.norm(), (k, vals)
+    finally:
+        S.close()
+
+
 def _free_device_bytes():
     """hipMemGetInfo of the current device, through the HIP runtime the library
     already initialised in this process."""
