@@ -47,26 +47,49 @@ WORKLOADS = {
 }
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2311_08618_amd", "csrc", "kernels.hip")
+# besides the GEMM section of KERNEL_SOURCE, what decides the GEMM's launches
+GEMM_SOURCES = [os.path.join(ROOT, "paper_2311_08618_amd", "csrc", "desc.hpp"),
+                os.path.join(ROOT, "paper_2311_08618_amd", "tuning", "gemm_tuning.json")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_gemm_nt_cube_laplace_n262144.md")
 
 
-def kernel_source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def gemm_source_hash(kernel_text=None, other_texts=None) -> str:
+    """First 16 hex digits of the sha256 of the code that decides the batched
+    GEMM's memory traffic: the GEMM section of kernels.hip (tile scan, k_gemm*
+    kernels, the transposed copy-back) and its launchers, the descriptor header
+    and the launch-parameter table.  Texts may be passed in (e.g. read from an
+    older commit); ValueError when the section markers are missing."""
+    if kernel_text is None:
+        with open(KERNEL_SOURCE) as f:
+            kernel_text = f.read()
+    if other_texts is None:
+        other_texts = []
+        for p in GEMM_SOURCES:
+            with open(p) as f:
+                other_texts.append(f.read())
+
+    def cut(a, b):
+        i = kernel_text.index(a)
+        return kernel_text[i:kernel_text.index(b, i)]
+
+    h = hashlib.sha256()
+    for t in [cut("GEMM (FP64 MFMA)", "matrix sums"), cut("void launch_variant(", "void launch_copyback(")] + other_texts:
+        h.update(t.encode())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str, n: int, S: int):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None
-    when it covers another kernel or workload, or the kernel source changed
-    since the counters were taken."""
+    when it covers another kernel or workload, or the GEMM's code changed since
+    the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     txt = open(TRAFFIC_FILE).read()
     fields = dict(re.findall(r"^- (\w+): (.+)$", txt, flags=re.M))
     try:
         if (fields["kernel"].strip() != kernel or int(fields["n"]) != n or int(fields["shifts_per_step"]) != S
-                or fields["kernels_hip_sha256_16"].strip() != kernel_source_hash()):
+                or fields["gemm_source_sha256_16"].strip() != gemm_source_hash()):
             return None
         return float(fields["hbm_bytes_per_launch"])
     except (KeyError, ValueError):

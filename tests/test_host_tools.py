@@ -41,18 +41,34 @@ def test_bucket_boundaries(autotune):
 def test_traffic_record_validity(tmp_path, monkeypatch):
     import bench
     src = tmp_path / "kernels.hip"
-    src.write_text("// kernel source\n")
-    h = hashlib.sha256(src.read_bytes()).hexdigest()[:16]
+    src.write_text("// head\n// GEMM (FP64 MFMA)\ngemm kernels\n// matrix sums\nother kernels\n"
+                   "void launch_variant(gemm launchers)\nvoid launch_copyback(other launchers)\n")
+    desc, tune = tmp_path / "desc.hpp", tmp_path / "tuning.json"
+    desc.write_text("struct GItem;\n")
+    tune.write_text("{}\n")
+    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(src))
+    monkeypatch.setattr(bench, "GEMM_SOURCES", [str(desc), str(tune)])
+    h = bench.gemm_source_hash()
     rec = tmp_path / "traffic.md"
     rec.write_text("# counters\n\n- kernel: h2::k_gemm<false, true>\n- n: 262144\n- shifts_per_step: 2\n"
-                   "- kernels_hip_sha256_16: %s\n- hbm_bytes_per_launch: 1.5e+09\n" % h)
-    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(src))
+                   "- gemm_source_sha256_16: %s\n- hbm_bytes_per_launch: 1.5e+09\n" % h)
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(rec))
     assert bench.measured_traffic("h2::k_gemm<false, true>", 262144, 2) == 1.5e9
     assert bench.measured_traffic("h2::k_gemm<true, false>", 262144, 2) is None
     assert bench.measured_traffic("h2::k_gemm<false, true>", 131072, 2) is None
     assert bench.measured_traffic("h2::k_gemm<false, true>", 262144, 1) is None
-    src.write_text("// changed kernel source\n")
+    # a change outside the GEMM section keeps the record; inside it, in its
+    # launchers, the descriptors or the table, drops it
+    src.write_text(src.read_text().replace("other kernels", "changed recompression kernels"))
+    assert bench.measured_traffic("h2::k_gemm<false, true>", 262144, 2) == 1.5e9
+    for path, a, b in [(src, "gemm kernels", "gemm kernels changed"), (src, "gemm launchers", "new launchers"),
+                       (desc, "GItem", "GItem2"), (tune, "{}", "{\"a\": 1}")]:
+        old = path.read_text()
+        path.write_text(old.replace(a, b))
+        assert bench.measured_traffic("h2::k_gemm<false, true>", 262144, 2) is None, (path, a)
+        path.write_text(old)
+    assert bench.measured_traffic("h2::k_gemm<false, true>", 262144, 2) == 1.5e9
+    src.write_text("// no markers\n")
     assert bench.measured_traffic("h2::k_gemm<false, true>", 262144, 2) is None
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.md"))
     assert bench.measured_traffic("h2::k_gemm<false, true>", 262144, 2) is None
@@ -60,14 +76,13 @@ def test_traffic_record_validity(tmp_path, monkeypatch):
 
 def test_committed_traffic_record_matches_committed_kernels():
     """The committed counter record is used only while it was taken on the
-    committed kernel source (otherwise the bench reports traffic as null)."""
+    committed GEMM code (otherwise the bench reports traffic as null)."""
     import bench
     if not os.path.exists(bench.TRAFFIC_FILE):
         pytest.skip("no counter record")
     txt = open(bench.TRAFFIC_FILE).read()
-    h = hashlib.sha256(open(bench.KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
-    if h not in txt:
-        pytest.skip("counter record predates the current kernels.hip: traffic is reported as null")
+    if bench.gemm_source_hash() not in txt:
+        pytest.skip("counter record predates the current GEMM code: traffic is reported as null")
     fields = dict(re.findall(r"^- (\w+): (.+)$", txt, flags=re.M))
     kernel, n, S = fields["kernel"].strip(), int(fields["n"]), int(fields["shifts_per_step"])
     assert kernel.startswith("h2::k_gemm")

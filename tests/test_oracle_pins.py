@@ -177,6 +177,65 @@ def test_paper_circle_accuracy():
         assert abs(l - ev[kk - 1]) < tol / 2, (kk, l, ev[kk - 1])
 
 
+def _gram_pchol_directions(X, tol):
+    """A Gram-based rank rule for the recompression (the GPU's, with negative
+    rounding in the remaining diagonal counted as zero): the pivoted Cholesky
+    of the FP64 Gram X X^T (largest remaining diagonal first), stopping once
+    the remaining diagonal sums to <= tol^2; the kept directions are the
+    Cholesky columns."""
+    G = X @ X.T
+    m = G.shape[0]
+    perm = np.arange(m)
+    L = np.zeros((m, m))
+    t = 0
+    for k in range(m):
+        d = np.diag(G)[k:]
+        if not float(np.sum(np.maximum(d, 0.0))) > tol * tol:
+            break
+        j = k + int(np.argmax(d))
+        if j != k:
+            G[[k, j], :] = G[[j, k], :]
+            G[:, [k, j]] = G[:, [j, k]]
+            L[[k, j], :] = L[[j, k], :]
+            perm[[k, j]] = perm[[j, k]]
+        if not G[k, k] > 0.0:
+            break
+        L[k, k] = math.sqrt(G[k, k])
+        L[k + 1:, k] = G[k + 1:, k] / L[k, k]
+        G[k + 1:, k + 1:] -= np.outer(L[k + 1:, k], L[k + 1:, k])
+        t = k + 1
+    At = np.zeros((m, t))
+    At[perm, :] = L[:, :t]
+    return t, At
+
+
+def test_gram_rank_rule_meets_circle_bound(monkeypatch):
+    """Sec. 5.1's circle setting with the recompression's column-pivoted QR
+    replaced by the pivoted Cholesky of the FP64 Gram: every sampled eigenvalue
+    still lies within eps_ev / 2 of LAPACK's, and the rule keeps at least the
+    oracle's directions.  Squaring the singular values in the rank decision
+    therefore does not by itself cost this accuracy."""
+    n = 512
+    X = W.circle_points(n)
+    k = Kernel(3, 1.0 / 1e-3, 1e-3)
+    tol = 1e-8
+    eps = 1e-2 * tol / estimate_norm(X, k)
+    H = H2(X, k, 32, 1.0, eps)
+    ev = np.linalg.eigvalsh(k.dense(X))
+    sigma = float(ev[n // 2]) + 1e-6
+    st_qr = {}
+    OF.inertia(H, sigma, st_qr)
+    monkeypatch.setattr(OF, "rrqr_directions", _gram_pchol_directions)
+    st_g = {}
+    OF.inertia(H, sigma, st_g)
+    kept_g, kept_qr = [sum(t) for t in st_g["t"]], [sum(t) for t in st_qr["t"]]
+    assert len(kept_g) == len(kept_qr) and all(a >= b for a, b in zip(kept_g, kept_qr)), (kept_g, kept_qr)
+    ks = [1, 49, n // 4, 305, n // 2, n]
+    lam = kth_eigs(H, ks, tol, ab=(0.0, 2048.0 * 2))
+    for kk, l in zip(ks, lam):
+        assert abs(l - ev[kk - 1]) < tol / 2, (kk, l, ev[kk - 1])
+
+
 def test_gershgorin_contains_spectrum():
     X = W.cube_points(300, 2)
     k = Kernel(1, 1e3)
