@@ -3,9 +3,11 @@ symbols and capacities to table entries, the bench's use of a committed counter
 record only while it matches the kernel, the workload and the kernel source,
 the merge of separate query runs, and the inertia-record cache of the library."""
 import hashlib
+import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 
@@ -163,3 +165,73 @@ def test_inertia_record_cache(tmp_path):
                     os.path.join(here, "records_check.cpp")], check=True)
     out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout + out.stderr
+
+
+def _tree_cases():
+    from paper_2311_08618_amd import workloads as W
+    rng = np.random.default_rng(11)
+    grid = np.array([[x, y] for x in range(12) for y in range(9)], dtype=np.float64) * 0.5
+    return [
+        ("cube-300-leaf32", W.cube_points(300, 1), 32, 1.0),
+        ("cube-2000-leaf64-eta0.7", W.cube_points(2000, 0), 64, 0.7),
+        ("circle-512-leaf32", W.circle_points(512), 32, 1.0),
+        ("line-700-leaf64", W.line_points(700), 64, 1.0),
+        ("cylinders-1024-leaf64", W.cylinder_points(1024, 0), 64, 1.0),
+        ("cube-1000-weak", W.cube_points(1000, 2), 64, math.inf),
+        ("grid-ties-108-leaf4", grid, 4, 1.0),
+        ("duplicates-96-leaf8", np.repeat(rng.random((24, 3)), 4, axis=0), 8, 1.0),
+        ("single-point", np.zeros((1, 3)), 2, 1.0),
+        ("ragged-37-leaf5", rng.random((37, 2)), 5, 1.0),
+    ]
+
+
+@pytest.fixture(scope="module")
+def tree_exe(tmp_path_factory):
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    lib = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2311_08618_amd",
+                       "libh2eig.so")
+    if gxx is None:
+        pytest.skip("g++ not found")
+    assert os.path.exists(lib), "libh2eig.so is not built (run __graft_entry__.build())"
+    here = os.path.dirname(os.path.abspath(__file__))
+    exe = str(tmp_path_factory.mktemp("tree") / "tree_check")
+    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+                    "-I/opt/rocm/include", "-o", exe, os.path.join(here, "tree_check.cpp"),
+                    "-L" + os.path.dirname(lib), "-l:libh2eig.so", "-Wl,-rpath," + os.path.dirname(lib)],
+                   check=True)
+    return exe
+
+
+@pytest.mark.parametrize("case", _tree_cases(), ids=lambda c: c[0])
+def test_library_tree_equals_oracle(tree_exe, case):
+    """The library's cluster tree, block tree and colouring (host code, no GPU)
+    equal the oracle's index for index: median split of the longest axis,
+    strong admissibility (R1), near and interaction lists, greedy colouring
+    (Secs. 3.1 and 3.4), and the leaf-order permutation."""
+    import subprocess
+    from oracle.tree import Tree
+    name, X, leaf, eta = case
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X.reshape(-1, 1)
+    n, dim = X.shape
+    inp = "%d %d %d %r\n" % (n, dim, leaf, eta) + " ".join("%.17g" % v for v in X.ravel()) + "\n"
+    out = subprocess.run([tree_exe], input=inp, capture_output=True, text=True, timeout=120, check=True).stdout
+    T = Tree(X, leaf, eta)
+    got = {}
+    for line in out.splitlines():
+        tok = line.split()
+        if tok[0] == "L":
+            got["L"] = int(tok[1])
+        else:
+            got[(tok[0], int(tok[1]), int(tok[2]))] = [int(v) for v in tok[3:]]
+    assert got["L"] == T.L
+    for l in range(T.L + 1):
+        assert got[("colour", l, -1)] == list(T.colour[l]), (name, l)
+        for i in range(1 << l):
+            assert got[("idx", l, i)] == [int(v) for v in T.idx[l][i]], (name, l, i)
+            assert got[("near", l, i)] == list(T.near[l][i]), (name, l, i)
+            assert got[("far", l, i)] == list(T.far[l][i]), (name, l, i)
+    assert got[("perm", -1, -1)] == [int(v) for v in T.perm()]
