@@ -168,20 +168,21 @@ def test_inertia_record_cache(tmp_path):
 
 
 def _tree_cases():
+    """(name, points, leaf, eta, kernel (kind, diag, p0, p1))"""
     from paper_2311_08618_amd import workloads as W
     rng = np.random.default_rng(11)
     grid = np.array([[x, y] for x in range(12) for y in range(9)], dtype=np.float64) * 0.5
     return [
-        ("cube-300-leaf32", W.cube_points(300, 1), 32, 1.0),
-        ("cube-2000-leaf64-eta0.7", W.cube_points(2000, 0), 64, 0.7),
-        ("circle-512-leaf32", W.circle_points(512), 32, 1.0),
-        ("line-700-leaf64", W.line_points(700), 64, 1.0),
-        ("cylinders-1024-leaf64", W.cylinder_points(1024, 0), 64, 1.0),
-        ("cube-1000-weak", W.cube_points(1000, 2), 64, math.inf),
-        ("grid-ties-108-leaf4", grid, 4, 1.0),
-        ("duplicates-96-leaf8", np.repeat(rng.random((24, 3)), 4, axis=0), 8, 1.0),
-        ("single-point", np.zeros((1, 3)), 2, 1.0),
-        ("ragged-37-leaf5", rng.random((37, 2)), 5, 1.0),
+        ("cube-300-leaf32", W.cube_points(300, 1), 32, 1.0, (W.K_LAPLACE, 1e3, 0.0, 0.0)),
+        ("cube-2000-leaf64-eta0.7", W.cube_points(2000, 0), 64, 0.7, (W.K_YUKAWA, 1e3, 0.0, 0.0)),
+        ("circle-512-leaf32", W.circle_points(512), 32, 1.0, (W.K_REG_LAPLACE, 1e3, 1e-3, 0.0)),
+        ("line-700-leaf64", W.line_points(700), 64, 1.0, (W.K_TRIDIAG_1D, 2.0, 1.0, 0.0)),
+        ("cylinders-1024-leaf64", W.cylinder_points(1024, 0), 64, 1.0, (W.K_GAUSS_DAMPED, 10.0, 0.01, 0.01)),
+        ("cube-1000-weak", W.cube_points(1000, 2), 64, math.inf, (W.K_LAPLACE, 1e3, 0.0, 0.0)),
+        ("grid-ties-108-leaf4", grid, 4, 1.0, (W.K_YUKAWA, 5.0, 0.0, 0.0)),
+        ("duplicates-96-leaf8", np.repeat(rng.random((24, 3)), 4, axis=0), 8, 1.0, (W.K_REG_LAPLACE, 50.0, 0.1, 0.0)),
+        ("single-point", np.zeros((1, 3)), 2, 1.0, (W.K_LAPLACE, 1e3, 0.0, 0.0)),
+        ("ragged-37-leaf5", rng.random((37, 2)), 5, 1.0, (W.K_GAUSS_DAMPED, 3.0, 0.5, 0.1)),
     ]
 
 
@@ -206,25 +207,34 @@ def tree_exe(tmp_path_factory):
 
 @pytest.mark.parametrize("case", _tree_cases(), ids=lambda c: c[0])
 def test_library_tree_equals_oracle(tree_exe, case):
-    """The library's cluster tree, block tree and colouring (host code, no GPU)
-    equal the oracle's index for index: median split of the longest axis,
-    strong admissibility (R1), near and interaction lists, greedy colouring
-    (Secs. 3.1 and 3.4), and the leaf-order permutation."""
+    """The library's host code, without a GPU, against the oracle: its cluster
+    tree, block tree and colouring equal the oracle's index for index (median
+    split of the longest axis, strong admissibility, near and interaction
+    lists, greedy colouring; Secs. 3.1 and 3.4) with the leaf-order
+    permutation; its normA (the scale of every truncation tolerance) equals the
+    oracle's to summation order; its kernel entries to a few ulps."""
     import subprocess
+    from oracle.build import estimate_norm
+    from oracle.kernels import Kernel
     from oracle.tree import Tree
-    name, X, leaf, eta = case
+    name, X, leaf, eta, (kind, diag, p0, p1) = case
     X = np.asarray(X, dtype=np.float64)
     if X.ndim == 1:
         X = X.reshape(-1, 1)
     n, dim = X.shape
-    inp = "%d %d %d %r\n" % (n, dim, leaf, eta) + " ".join("%.17g" % v for v in X.ravel()) + "\n"
+    inp = ("%d %d %d %r %d %r %r %r\n" % (n, dim, leaf, eta, kind, diag, p0, p1)
+           + " ".join("%.17g" % v for v in X.ravel()) + "\n")
     out = subprocess.run([tree_exe], input=inp, capture_output=True, text=True, timeout=120, check=True).stdout
     T = Tree(X, leaf, eta)
-    got = {}
+    got, kb = {}, []
     for line in out.splitlines():
         tok = line.split()
         if tok[0] == "L":
             got["L"] = int(tok[1])
+        elif tok[0] == "norm":
+            got["norm"] = float(tok[1])
+        elif tok[0] == "kblock":
+            kb.append([float(v) for v in tok[2:]])
         else:
             got[(tok[0], int(tok[1]), int(tok[2]))] = [int(v) for v in tok[3:]]
     assert got["L"] == T.L
@@ -235,3 +245,19 @@ def test_library_tree_equals_oracle(tree_exe, case):
             assert got[("near", l, i)] == list(T.near[l][i]), (name, l, i)
             assert got[("far", l, i)] == list(T.far[l][i]), (name, l, i)
     assert got[("perm", -1, -1)] == [int(v) for v in T.perm()]
+    k = Kernel(kind, diag, p0, p1)
+    assert abs(got["norm"] - estimate_norm(X, k)) <= 1e-12 * abs(estimate_norm(X, k)), (got["norm"],)
+    m = min(n, 24)
+    ids = np.arange(m)
+    want = k.block(X, ids, ids)
+    # a few ulps, times the kernel's condition number |d log f / d log r| at
+    # that distance (the two sides may round r differently by an ulp)
+    d = X[:m, None, :] - X[None, :m, :]
+    r = np.sqrt(np.sum(d * d, axis=2))
+    h = 1e-6
+    with np.errstate(divide="ignore", invalid="ignore"):
+        cond = np.abs((k.f(r * (1 + h)) - k.f(r * (1 - h))) / (2 * h * k.f(r)))
+    cond = np.where(np.isfinite(cond), cond, 0.0)
+    tol = 8e-16 * (2.0 + cond) * np.abs(want)
+    got_kb = np.array(kb)
+    assert got_kb.shape == want.shape and np.all(np.abs(got_kb - want) <= tol), name
