@@ -261,3 +261,38 @@ def test_library_tree_equals_oracle(tree_exe, case):
     tol = 8e-16 * (2.0 + cond) * np.abs(want)
     got_kb = np.array(kb)
     assert got_kb.shape == want.shape and np.all(np.abs(got_kb - want) <= tol), name
+
+
+def test_host_code_under_sanitizers(tree_exe, tmp_path):
+    """The host code shared by the harnesses, built with the address and
+    undefined-behaviour sanitizers (any report is fatal) and, separately, with
+    the thread sanitizer: the record cache and the library's host.cpp (tree,
+    threaded norm estimate, kernel entries) run clean and print what the plain
+    build prints.  Host code only; no device code is built here."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not found")
+    here = os.path.dirname(os.path.abspath(__file__))
+    libdir = os.path.join(os.path.dirname(here), "paper_2311_08618_amd")
+    common = ["-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
+    link = ["-L" + libdir, "-l:libh2eig.so", "-Wl,-rpath," + libdir, "-pthread"]
+    san = {"asan": ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"],
+           "tsan": ["-fsanitize=thread"]}
+    from paper_2311_08618_amd import workloads as W
+    X = W.cube_points(2000, 1)
+    inp = "2000 3 64 0.7 %d 1000.0 0.0 0.0\n" % W.K_YUKAWA + " ".join("%.17g" % v for v in X.ravel()) + "\n"
+    plain = subprocess.run([tree_exe], input=inp, capture_output=True, text=True, timeout=120, check=True).stdout
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", TSAN_OPTIONS="halt_on_error=1")
+    for name, flags in san.items():
+        exe = str(tmp_path / ("tree_" + name))
+        subprocess.run([gxx] + common + flags + ["-o", exe, os.path.join(here, "tree_check.cpp"),
+                                                 os.path.join(libdir, "csrc", "host.cpp")] + link, check=True)
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True, timeout=300, env=env)
+        assert out.returncode == 0 and "Sanitizer" not in out.stderr, (name, out.stderr[-2000:])
+        assert out.stdout == plain, name
+    exe = str(tmp_path / "records_asan")
+    subprocess.run([gxx] + common + san["asan"] + ["-o", exe, os.path.join(here, "records_check.cpp")], check=True)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout + out.stderr[-2000:]
