@@ -263,12 +263,13 @@ def test_library_tree_equals_oracle(tree_exe, case):
     assert got_kb.shape == want.shape and np.all(np.abs(got_kb - want) <= tol), name
 
 
-def test_host_code_under_sanitizers(tree_exe, tmp_path):
+def test_host_code_under_sanitizers(tree_exe, plan_exe, tmp_path):
     """The host code shared by the harnesses, built with the address and
     undefined-behaviour sanitizers (any report is fatal) and, separately, with
-    the thread sanitizer: the record cache and the library's host.cpp (tree,
-    threaded norm estimate, kernel entries) run clean and print what the plain
-    build prints.  Host code only; no device code is built here."""
+    the thread sanitizer: the record cache, the library's host.cpp (tree,
+    threaded norm estimate, kernel entries) and plan.cpp (the static schedule)
+    run clean and print what the plain build prints.  Host code only; no device
+    code is built here."""
     import shutil
     import subprocess
     gxx = shutil.which("g++")
@@ -285,14 +286,98 @@ def test_host_code_under_sanitizers(tree_exe, tmp_path):
     inp = "2000 3 64 0.7 %d 1000.0 0.0 0.0\n" % W.K_YUKAWA + " ".join("%.17g" % v for v in X.ravel()) + "\n"
     plain = subprocess.run([tree_exe], input=inp, capture_output=True, text=True, timeout=120, check=True).stdout
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", TSAN_OPTIONS="halt_on_error=1")
-    for name, flags in san.items():
-        exe = str(tmp_path / ("tree_" + name))
-        subprocess.run([gxx] + common + flags + ["-o", exe, os.path.join(here, "tree_check.cpp"),
-                                                 os.path.join(libdir, "csrc", "host.cpp")] + link, check=True)
-        out = subprocess.run([exe], input=inp, capture_output=True, text=True, timeout=300, env=env)
-        assert out.returncode == 0 and "Sanitizer" not in out.stderr, (name, out.stderr[-2000:])
-        assert out.stdout == plain, name
+    plan_inp = inp.split("\n", 1)
+    plan_inp = " ".join(plan_inp[0].split()[:4]) + "\n" + plan_inp[1]
+    plain_plan = subprocess.run([plan_exe], input=plan_inp, capture_output=True, text=True, timeout=120,
+                                check=True).stdout
+    # the library sources as instrumented objects, compiled side by side; plan.cpp
+    # runs on one thread, so the thread sanitizer covers the tree harness only
+    objs = {("host.cpp", "asan"), ("plan.cpp", "asan"), ("host.cpp", "tsan")}
+    procs = {}
+    for src, name in objs:
+        obj = str(tmp_path / ("%s_%s.o" % (src[:-4], name)))
+        procs[(src, name)] = (obj, subprocess.Popen([gxx] + common + san[name] + ["-c", "-o", obj,
+                                                                                   os.path.join(libdir, "csrc", src)]))
+    for key, (obj, pr) in procs.items():
+        assert pr.wait(timeout=600) == 0, key
+    runs = [("tree", "asan", ["host.cpp"], inp, plain), ("plan", "asan", ["plan.cpp", "host.cpp"], plan_inp, plain_plan),
+            ("tree", "tsan", ["host.cpp"], inp, plain)]
+    for harness, name, srcs, text, want in runs:
+        exe = str(tmp_path / (harness + "_" + name))
+        subprocess.run([gxx] + common + san[name] + ["-o", exe, os.path.join(here, harness + "_check.cpp")]
+                       + [procs[(f, name)][0] for f in srcs] + link, check=True)
+        out = subprocess.run([exe], input=text, capture_output=True, text=True, timeout=300, env=env)
+        assert out.returncode == 0 and "Sanitizer" not in out.stderr, (name, harness, out.stderr[-2000:])
+        assert out.stdout == want, (name, harness)
     exe = str(tmp_path / "records_asan")
     subprocess.run([gxx] + common + san["asan"] + ["-o", exe, os.path.join(here, "records_check.cpp")], check=True)
     out = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
     assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout + out.stderr[-2000:]
+
+
+@pytest.fixture(scope="module")
+def plan_exe(tree_exe, tmp_path_factory):
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    here = os.path.dirname(os.path.abspath(__file__))
+    libdir = os.path.join(os.path.dirname(here), "paper_2311_08618_amd")
+    exe = str(tmp_path_factory.mktemp("plan") / "plan_check")
+    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+                    "-I/opt/rocm/include", "-o", exe, os.path.join(here, "plan_check.cpp"),
+                    "-L" + libdir, "-l:libh2eig.so", "-Wl,-rpath," + libdir], check=True)
+    return exe
+
+
+@pytest.mark.parametrize("n,leaf,eta,seed", [(2048, 128, 1.0, 0), (1000, 64, 1.5, 3)])
+def test_library_schedule_carries_the_oracles_fill_in(plan_exe, n, leaf, eta, seed):
+    """The library's static schedule (host code, no GPU) against the oracle's
+    factorization (Secs. 3.3-3.4): the near-pair rows are the tree's near lists,
+    the colour classes partition each level into pairwise non-near clusters in
+    the oracle's colouring, and the fill-in blocks the schedule carries into
+    each level are exactly the pairs on which the oracle's elimination of the
+    level below left fill-in that its merge carries up (parents not near)."""
+    import subprocess
+    from oracle import factor as OF
+    from oracle.build import H2
+    from oracle.kernels import Kernel
+    from paper_2311_08618_amd import workloads as W
+    X = W.cube_points(n, seed)
+    inp = "%d 3 %d %r\n" % (n, leaf, eta) + " ".join("%.17g" % v for v in X.ravel()) + "\n"
+    out = subprocess.run([plan_exe], input=inp, capture_output=True, text=True, timeout=120, check=True).stdout
+    got = {}
+    for line in out.splitlines():
+        tok = line.split()
+        if tok[0] != "L":
+            got[(tok[0], int(tok[1]), int(tok[2]))] = [int(v) for v in tok[3:]]
+    H = H2(X, Kernel(W.K_LAPLACE, 1e3), leaf, eta, 1e-6)
+    T = H.tree
+    fkeys, allR = {}, {}
+
+    def hook(l, nu, S, F, m, R):
+        fkeys[l] = set(F.keys())
+        allR[l] = list(R)
+
+    OF.inertia(H, 1000.0, on_level=hook)
+    for l in range(T.L + 1):
+        N = 1 << l
+        for i in range(N):
+            assert got[("near", l, i)] == list(T.near[l][i]), (l, i)
+        classes = [got[("class", l, c)] for c in range(max(T.colour[l]) + 1)]
+        assert sorted(i for cl in classes for i in cl) == list(range(N))
+        for c, cl in enumerate(classes):
+            assert cl == [i for i in range(N) if T.colour[l][i] == c], (l, c)
+            assert all(b not in T.near_set[l][a] for a in cl for b in cl if a != b), (l, c)
+        if l == T.L:
+            assert all(got[("carried", l, i)] == [] for i in range(N))
+            continue
+        # the oracle creates fill-in only behind clusters with a pivot block
+        # (R > 0); the schedule lays it out for every cluster
+        carried = {(min(c >> 1, d >> 1), max(c >> 1, d >> 1)) for (c, d) in fkeys[l + 1]
+                   if (d >> 1) not in T.near_set[l][c >> 1]}
+        sched = {(i, j) for i in range(N) for j in got[("carried", l, i)]}
+        if all(r > 0 for r in allR[l + 1]):
+            assert sched == carried, (l, sorted(sched ^ carried)[:10])
+        else:
+            assert carried <= sched, l
+    assert any(got[("carried", l, i)] for l in range(T.L) for i in range(1 << l))   # fill-in is carried somewhere
