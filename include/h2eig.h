@@ -214,6 +214,20 @@ h2_status h2_get_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_
  * H2_EDEVICE. */
 h2_status h2_release_workspace(h2_matrix A);
 
+/* Device-memory allocator of the library, process-wide (the handle owns HBM
+ * through this hook; a framework points it at its own caching allocator).
+ * Every device allocation made after the call (resident H^2 data, plans,
+ * factorization workspace, construction scratch) calls alloc(bytes, ctx),
+ * which returns device memory of the current device aligned to at least 256
+ * bytes, or NULL (the call that needed it then fails with H2_ENOMEM).  Each
+ * block is returned by release(ptr, ctx) of the allocator that made it, after
+ * the device has finished all work queued so far (as hipFree), even if the
+ * hook has changed since.  alloc = release = NULL restores hipMalloc/hipFree
+ * for new blocks.  The callbacks may be called from any thread that uses the
+ * library (the serving loop's workers included) and must be thread-safe.
+ * H2_EINVAL if exactly one of alloc and release is NULL. */
+h2_status h2_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* ctx);
+
 /* Cap on the shifts factored together in one launch (0 = automatic, from the
  * free device memory at each call); larger batches are split.  H2_EINVAL for
  * max_shifts < 0. */

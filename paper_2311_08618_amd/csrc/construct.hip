@@ -16,6 +16,7 @@
 #include <string>
 
 #include "construct.hpp"
+#include "devmem.hpp"
 
 #pragma clang fp contract(off)
 
@@ -356,7 +357,7 @@ struct HipFail : std::runtime_error {
 template <class T>
 T* dev_copy(const std::vector<T>& v, hipStream_t st) {
   T* p = nullptr;
-  FCHK(hipMalloc(&p, std::max<size_t>(1, v.size()) * sizeof(T)));
+  FCHK(h2::dev_malloc(&p, std::max<size_t>(1, v.size()) * sizeof(T)));
   if (!v.empty()) FCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
   return p;
 }
@@ -379,9 +380,9 @@ void far_points_upload(FarIdPoints& P, const double* X, const int64_t* perm, int
 }
 
 void far_points_free(FarIdPoints& P) {
-  if (P.px) (void)hipFree(P.px);
-  if (P.py) (void)hipFree(P.py);
-  if (P.pz) (void)hipFree(P.pz);
+  if (P.px) (void)h2::dev_free(P.px);
+  if (P.py) (void)h2::dev_free(P.py);
+  if (P.pz) (void)h2::dev_free(P.pz);
   P = FarIdPoints{};
 }
 
@@ -453,17 +454,17 @@ void far_field_ids(const FarIdPoints& P, int kind, double p0, double p1, const F
     FarItem* dit = dev_copy(items, st);
     double *Gh, *Gl, *Lh, *Ll, *Lo, *dh, *dl;
     int *stp, *piv, *rk, *bad;
-    FCHK(hipMalloc(&Gh, go * 8));
-    FCHK(hipMalloc(&Gl, go * 8));
-    FCHK(hipMalloc(&Lh, go * 8));
-    FCHK(hipMalloc(&Ll, go * 8));
-    FCHK(hipMalloc(&Lo, go * 8));
-    FCHK(hipMalloc(&dh, std::max<int64_t>(1, ro) * 8));
-    FCHK(hipMalloc(&dl, std::max<int64_t>(1, ro) * 8));
-    FCHK(hipMalloc(&stp, std::max<int64_t>(1, ro) * 4));
-    FCHK(hipMalloc(&piv, std::max<int64_t>(1, ro) * 4));
-    FCHK(hipMalloc(&rk, nb * 4));
-    FCHK(hipMalloc(&bad, 4));
+    FCHK(h2::dev_malloc(&Gh, go * 8));
+    FCHK(h2::dev_malloc(&Gl, go * 8));
+    FCHK(h2::dev_malloc(&Lh, go * 8));
+    FCHK(h2::dev_malloc(&Ll, go * 8));
+    FCHK(h2::dev_malloc(&Lo, go * 8));
+    FCHK(h2::dev_malloc(&dh, std::max<int64_t>(1, ro) * 8));
+    FCHK(h2::dev_malloc(&dl, std::max<int64_t>(1, ro) * 8));
+    FCHK(h2::dev_malloc(&stp, std::max<int64_t>(1, ro) * 4));
+    FCHK(h2::dev_malloc(&piv, std::max<int64_t>(1, ro) * 4));
+    FCHK(h2::dev_malloc(&rk, nb * 4));
+    FCHK(h2::dev_malloc(&bad, 4));
     FCHK(hipMemsetAsync(bad, 0, 4, st));
     for (size_t i0 = 0; i0 < items.size(); i0 += 1u << 30) {
       const unsigned ni = (unsigned)std::min<size_t>(items.size() - i0, 1u << 30);
@@ -491,7 +492,7 @@ void far_field_ids(const FarIdPoints& P, int kind, double p0, double p1, const F
     for (void* p : {(void*)dm, (void*)dt2, (void*)dro, (void*)dgo, (void*)dfp, (void*)df0, (void*)df1, (void*)drx, (void*)dry,
                     (void*)drz, (void*)dit, (void*)Gh, (void*)Gl, (void*)Lh, (void*)Ll, (void*)Lo, (void*)dh,
                     (void*)dl, (void*)stp, (void*)piv, (void*)rk, (void*)bad})
-      FCHK(hipFree(p));
+      FCHK(h2::dev_free(p));
     if (badh) throw std::invalid_argument("kernel is not finite between a cluster and its far field");
     for (int b = 0; b < nb; ++b) {
       const int i = todo[t0 + b];
@@ -566,12 +567,12 @@ void kernel_matvec_gpu(const double* X, int64_t n, int dim, int kind, double dia
     double** p[3];
     ~Guard() {
       for (double** q : p)
-        if (*q) (void)hipFree(*q);
+        if (*q) (void)h2::dev_free(*q);
     }
   } guard{{&dX, &dx, &dy}};
-  FCHK(hipMalloc(&dX, std::max<int64_t>(1, n * dim) * 8));
-  FCHK(hipMalloc(&dx, std::max<int64_t>(1, n) * 8));
-  FCHK(hipMalloc(&dy, std::max<int64_t>(1, n) * 8));
+  FCHK(h2::dev_malloc(&dX, std::max<int64_t>(1, n * dim) * 8));
+  FCHK(h2::dev_malloc(&dx, std::max<int64_t>(1, n) * 8));
+  FCHK(h2::dev_malloc(&dy, std::max<int64_t>(1, n) * 8));
   FCHK(hipMemcpyAsync(dX, X, n * dim * 8, hipMemcpyHostToDevice, st));
   FCHK(hipMemcpyAsync(dx, x, n * 8, hipMemcpyHostToDevice, st));
   launch_kernel_matvec(dX, n, dim, kind, diag, p0, p1, dx, dy, st);

@@ -22,10 +22,12 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/h2eig.h"
 #include "construct.hpp"
+#include "devmem.hpp"
 #include "host.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -77,12 +79,12 @@ struct Arena {
     if (bytes <= cap) return;
     if (p) {
       HIPCHK(hipStreamSynchronize(st));
-      HIPCHK(hipFree(p));
+      HIPCHK(h2::dev_free(p));
       p = nullptr;
       cap = 0;
     }
     size_t want = bytes + bytes / 32 + 4096;
-    if (hipMalloc(&p, want) != hipSuccess) {
+    if (h2::dev_malloc(&p, want) != hipSuccess) {
       (void)hipGetLastError();
       p = nullptr;
       throw NoMem{"device allocation of " + std::to_string(want) + " bytes failed"};
@@ -91,7 +93,7 @@ struct Arena {
     if (poison_on()) poison(st);
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) (void)h2::dev_free(p);
     p = nullptr;
     cap = 0;
   }
@@ -214,7 +216,7 @@ struct Profiler {
   void release() {
     for (auto e : pool) (void)hipEventDestroy(e);
     pool.clear();
-    if (d_fc) (void)hipFree(d_fc);
+    if (d_fc) (void)h2::dev_free(d_fc);
     d_fc = nullptr;
   }
 };
@@ -365,7 +367,7 @@ void upload_plan(h2_matrix A) {
   A->leaf_m0 = b.put(m0);
   A->leaf_blkdiag = b.put(bdm);
   A->max_list = g_max_list;
-  HIPCHK(hipMalloc(&A->d_plan, b.h.size()));
+  HIPCHK(h2::dev_malloc(&A->d_plan, b.h.size()));
   HIPCHK(hipMemcpy(A->d_plan, b.h.data(), b.h.size(), hipMemcpyHostToDevice));
   A->resident += (int64_t)b.h.size();
 }
@@ -379,7 +381,7 @@ void build_near_blocks(h2_matrix A) {
   int N = lf.N, nblk = lf.nblk();
   hipStream_t st = A->stream;
   size_t bsz = (size_t)cap * cap;
-  HIPCHK(hipMalloc(&A->d_bres, std::max<size_t>(1, (size_t)nblk * bsz * sizeof(double))));
+  HIPCHK(h2::dev_malloc(&A->d_bres, std::max<size_t>(1, (size_t)nblk * bsz * sizeof(double))));
   A->resident += (int64_t)nblk * bsz * 8;
   // points in leaf order, starts, sizes, bases
   std::vector<double> Xl((size_t)T.n * T.dim);
@@ -401,11 +403,11 @@ void build_near_blocks(h2_matrix A) {
   double *dX = nullptr, *dQ = nullptr;
   int64_t* dstart = nullptr;
   int *dm = nullptr, *dbad = nullptr;
-  HIPCHK(hipMalloc(&dX, std::max<size_t>(8, Xl.size() * 8)));
-  HIPCHK(hipMalloc(&dQ, Q.size() * 8));
-  HIPCHK(hipMalloc(&dstart, N * 8));
-  HIPCHK(hipMalloc(&dm, N * 4));
-  HIPCHK(hipMalloc(&dbad, 4));
+  HIPCHK(h2::dev_malloc(&dX, std::max<size_t>(8, Xl.size() * 8)));
+  HIPCHK(h2::dev_malloc(&dQ, Q.size() * 8));
+  HIPCHK(h2::dev_malloc(&dstart, N * 8));
+  HIPCHK(h2::dev_malloc(&dm, N * 4));
+  HIPCHK(h2::dev_malloc(&dbad, 4));
   HIPCHK(hipMemcpy(dX, Xl.data(), Xl.size() * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(dQ, Q.data(), Q.size() * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(dstart, start.data(), N * 8, hipMemcpyHostToDevice));
@@ -414,8 +416,8 @@ void build_near_blocks(h2_matrix A) {
   // chunked: kernel blocks -> HAT ; TMP = Q_i^T HAT ; BRES = TMP Q_j
   int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nblk, (int64_t)(2LL << 30) / (int64_t)(bsz * 8)));
   double *dA = nullptr, *dT = nullptr;
-  HIPCHK(hipMalloc(&dA, (size_t)chunk * bsz * 8));
-  HIPCHK(hipMalloc(&dT, (size_t)chunk * bsz * 8));
+  HIPCHK(h2::dev_malloc(&dA, (size_t)chunk * bsz * 8));
+  HIPCHK(h2::dev_malloc(&dT, (size_t)chunk * bsz * 8));
   std::vector<int> bi(nblk), bj(nblk);
   for (int i = 0; i < N; ++i)
     for (int k = lf.near_ptr[i]; k < lf.near_ptr[i + 1]; ++k) {
@@ -423,8 +425,8 @@ void build_near_blocks(h2_matrix A) {
       bj[k] = lf.near_idx[k];
     }
   int *dbi = nullptr, *dbj = nullptr;
-  HIPCHK(hipMalloc(&dbi, std::max(1, nblk) * 4));
-  HIPCHK(hipMalloc(&dbj, std::max(1, nblk) * 4));
+  HIPCHK(h2::dev_malloc(&dbi, std::max(1, nblk) * 4));
+  HIPCHK(h2::dev_malloc(&dbj, std::max(1, nblk) * 4));
   HIPCHK(hipMemcpy(dbi, bi.data(), nblk * 4, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(dbj, bj.data(), nblk * 4, hipMemcpyHostToDevice));
   int zero_int = 0;
@@ -448,10 +450,10 @@ void build_near_blocks(h2_matrix A) {
     }
     GItem *di1, *di2;
     GTerm *dt1, *dt2;
-    HIPCHK(hipMalloc(&di1, g1.items.size() * sizeof(GItem)));
-    HIPCHK(hipMalloc(&di2, g2.items.size() * sizeof(GItem)));
-    HIPCHK(hipMalloc(&dt1, g1.terms.size() * sizeof(GTerm)));
-    HIPCHK(hipMalloc(&dt2, g2.terms.size() * sizeof(GTerm)));
+    HIPCHK(h2::dev_malloc(&di1, g1.items.size() * sizeof(GItem)));
+    HIPCHK(h2::dev_malloc(&di2, g2.items.size() * sizeof(GItem)));
+    HIPCHK(h2::dev_malloc(&dt1, g1.terms.size() * sizeof(GTerm)));
+    HIPCHK(h2::dev_malloc(&dt2, g2.terms.size() * sizeof(GTerm)));
     HIPCHK(hipMemcpy(di1, g1.items.data(), g1.items.size() * sizeof(GItem), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(di2, g2.items.data(), g2.items.size() * sizeof(GItem), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dt1, g1.terms.data(), g1.terms.size() * sizeof(GTerm), hipMemcpyHostToDevice));
@@ -463,27 +465,27 @@ void build_near_blocks(h2_matrix A) {
     bt.p[B_TMP] = dT;
     bt.p[B_BRES] = A->d_bres;
     int* dpre = nullptr;
-    HIPCHK(hipMalloc(&dpre, (size_t)(nb + 1) * sizeof(int)));
+    HIPCHK(h2::dev_malloc(&dpre, (size_t)(nb + 1) * sizeof(int)));
     launch_gemm(GEMM_TN, di1, nb, dt1, bt, sz, cap, cap, 1, dpre, st);
     launch_gemm(GEMM_NN, di2, nb, dt2, bt, sz, cap, cap, 1, dpre, st);
     HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipFree(dpre));
-    HIPCHK(hipFree(di1));
-    HIPCHK(hipFree(di2));
-    HIPCHK(hipFree(dt1));
-    HIPCHK(hipFree(dt2));
+    HIPCHK(h2::dev_free(dpre));
+    HIPCHK(h2::dev_free(di1));
+    HIPCHK(h2::dev_free(di2));
+    HIPCHK(h2::dev_free(dt1));
+    HIPCHK(h2::dev_free(dt2));
   }
   int bad = 0;
   HIPCHK(hipMemcpy(&bad, dbad, 4, hipMemcpyDeviceToHost));
-  HIPCHK(hipFree(dA));
-  HIPCHK(hipFree(dT));
-  HIPCHK(hipFree(dX));
-  HIPCHK(hipFree(dQ));
-  HIPCHK(hipFree(dstart));
-  HIPCHK(hipFree(dm));
-  HIPCHK(hipFree(dbad));
-  HIPCHK(hipFree(dbi));
-  HIPCHK(hipFree(dbj));
+  HIPCHK(h2::dev_free(dA));
+  HIPCHK(h2::dev_free(dT));
+  HIPCHK(h2::dev_free(dX));
+  HIPCHK(h2::dev_free(dQ));
+  HIPCHK(h2::dev_free(dstart));
+  HIPCHK(h2::dev_free(dm));
+  HIPCHK(h2::dev_free(dbad));
+  HIPCHK(h2::dev_free(dbi));
+  HIPCHK(h2::dev_free(dbj));
   if (bad) throw std::invalid_argument("kernel is not finite for a pair of distinct points (coincident points?)");
 }
 
@@ -506,7 +508,7 @@ void upload_resident(h2_matrix A) {
           for (int r = 0; r < ri; ++r) h[(size_t)slot * rm * rm + r + (size_t)c * rm] = pr.second[r + (size_t)c * ri];
       }
     }
-    HIPCHK(hipMalloc(&A->d_cpl[l], h.size() * 8));
+    HIPCHK(h2::dev_malloc(&A->d_cpl[l], h.size() * 8));
     HIPCHK(hipMemcpy(A->d_cpl[l], h.data(), h.size() * 8, hipMemcpyHostToDevice));
     A->resident += (int64_t)h.size() * 8;
     // transfer matrices of the parents (level l-1), stored with level l-1
@@ -519,7 +521,7 @@ void upload_resident(h2_matrix A) {
       for (int c = 0; c < d; ++c)
         for (int r = 0; r < d; ++r) e[(size_t)p * em * em + r + (size_t)c * em] = Q[r + (size_t)c * d];
     }
-    HIPCHK(hipMalloc(&A->d_emat[l - 1], e.size() * 8));
+    HIPCHK(h2::dev_malloc(&A->d_emat[l - 1], e.size() * 8));
     HIPCHK(hipMemcpy(A->d_emat[l - 1], e.data(), e.size() * 8, hipMemcpyHostToDevice));
     A->emat_ld[l - 1] = em;
     A->resident += (int64_t)e.size() * 8;
@@ -1061,12 +1063,12 @@ void ensure_gershgorin(h2_matrix A) {
     double** a;
     double** b;
     ~Guard() {
-      if (*a) (void)hipFree(*a);
-      if (*b) (void)hipFree(*b);
+      if (*a) (void)h2::dev_free(*a);
+      if (*b) (void)h2::dev_free(*b);
     }
   } guard{&dX, &drad};
-  HIPCHK(hipMalloc(&dX, (size_t)n * T.dim * 8));
-  HIPCHK(hipMalloc(&drad, (size_t)n * 8));
+  HIPCHK(h2::dev_malloc(&dX, (size_t)n * T.dim * 8));
+  HIPCHK(h2::dev_malloc(&drad, (size_t)n * 8));
   HIPCHK(hipMemcpyAsync(dX, T.X.data(), (size_t)n * T.dim * 8, hipMemcpyHostToDevice, st));
   launch_row_abs_sum(dX, n, T.dim, A->kern.kind, A->kern.p0, A->kern.p1, drad, st);
   HIPCHK(hipGetLastError());
@@ -1147,6 +1149,55 @@ h2_status run_inertia(h2_matrix A, const double* sigma, int64_t ns, bool f32, in
 // error message of the calling thread, shared with the serving loop
 namespace h2 {
 void set_last_error(const std::string& msg) { g_err = msg; }
+
+// ------------------------------------------------------- device allocations
+namespace {
+struct AllocHook {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*release)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+AllocHook g_hook;                                     // the allocator for new blocks
+std::atomic<bool> g_hook_used{false};                 // a hook was ever installed
+std::unordered_map<void*, AllocHook> g_hook_blocks;   // blocks from a hook, by address
+}  // namespace
+
+hipError_t dev_malloc_bytes(void** p, size_t bytes) {
+  AllocHook h;
+  {
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    h = g_hook;
+  }
+  if (!h.alloc) return hipMalloc(p, bytes);
+  *p = nullptr;
+  if (bytes == 0) return hipSuccess;
+  void* q = h.alloc(bytes, h.ctx);
+  if (!q) return hipErrorOutOfMemory;
+  std::lock_guard<std::mutex> g(g_alloc_mu);
+  g_hook_blocks[q] = h;
+  *p = q;
+  return hipSuccess;
+}
+
+hipError_t dev_free(void* p) {
+  if (!p) return hipSuccess;
+  AllocHook h;
+  bool hooked = false;
+  if (g_hook_used.load()) {
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    auto it = g_hook_blocks.find(p);
+    if (it != g_hook_blocks.end()) {
+      h = it->second;
+      g_hook_blocks.erase(it);
+      hooked = true;
+    }
+  }
+  if (!hooked) return hipFree(p);
+  const hipError_t e = hipDeviceSynchronize();   // as hipFree: no queued kernel may still use the block
+  h.release(p, h.ctx);
+  return e;
+}
 }  // namespace h2
 
 // =================================================================== C ABI
@@ -1216,7 +1267,7 @@ h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern,
     A->leafcap = 0;
     for (int i = 0; i < (1 << L); ++i) A->leafcap = std::max<int>(A->leafcap, (int)A->T.size[L][i]);
     A->leafcap = round_cap(A->leafcap);
-    HIPCHK(hipMalloc(&A->d_more, (MORE_SLOTS + 4) * sizeof(int)));
+    HIPCHK(h2::dev_malloc(&A->d_more, (MORE_SLOTS + 4) * sizeof(int)));
     A->d_tau2.assign(L + 1, nullptr);
     A->d_tau2_f32.assign(L + 1, nullptr);
     const double tau32 = std::max(eps, EPS_F32) * A->normA;
@@ -1227,9 +1278,9 @@ h2_status h2_build(const double* points, int64_t n, int32_t dim, h2_kernel kern,
         t2[i] = A->tau * A->tau * share;
         t32[i] = tau32 * tau32 * share;
       }
-      HIPCHK(hipMalloc(&A->d_tau2[l], t2.size() * sizeof(double)));
+      HIPCHK(h2::dev_malloc(&A->d_tau2[l], t2.size() * sizeof(double)));
       HIPCHK(hipMemcpy(A->d_tau2[l], t2.data(), t2.size() * sizeof(double), hipMemcpyHostToDevice));
-      HIPCHK(hipMalloc(&A->d_tau2_f32[l], t32.size() * sizeof(double)));
+      HIPCHK(h2::dev_malloc(&A->d_tau2_f32[l], t32.size() * sizeof(double)));
       HIPCHK(hipMemcpy(A->d_tau2_f32[l], t32.data(), t32.size() * sizeof(double), hipMemcpyHostToDevice));
     }
     HIPCHK(hipHostMalloc(&A->h_more, 4 * sizeof(int)));
@@ -1523,6 +1574,16 @@ h2_status h2_level_dims(h2_matrix A, int32_t nlev, int32_t* cap) {
   return H2_OK;
 }
 
+h2_status h2_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* ctx) {
+  if ((alloc == nullptr) != (release == nullptr)) return fail(H2_EINVAL, "alloc and release must both be set or both be NULL");
+  std::lock_guard<std::mutex> g(h2::g_alloc_mu);
+  h2::g_hook.alloc = alloc;
+  h2::g_hook.release = release;
+  h2::g_hook.ctx = alloc ? ctx : nullptr;
+  if (alloc) h2::g_hook_used.store(true);
+  return H2_OK;
+}
+
 h2_status h2_set_max_shifts(h2_matrix A, int32_t max_shifts) {
   if (!A) return fail(H2_EINVAL, "NULL handle");
   if (max_shifts < 0) return fail(H2_EINVAL, "max_shifts must be >= 0");
@@ -1635,7 +1696,7 @@ h2_status h2_profile_enable(h2_matrix A, int32_t enable) {
   try {
     HIPCHK(hipSetDevice(A->device));
     if (enable && !A->prof.d_fc) {
-      HIPCHK(hipMalloc(&A->prof.d_fc, 2 * PROF_N * sizeof(unsigned long long)));
+      HIPCHK(h2::dev_malloc(&A->prof.d_fc, 2 * PROF_N * sizeof(unsigned long long)));
       HIPCHK(hipMemset(A->prof.d_fc, 0, 2 * PROF_N * sizeof(unsigned long long)));
     }
   } catch (HipError& e) {
@@ -1677,6 +1738,7 @@ h2_status h2_profile_level_ms(h2_matrix A, int32_t cls, int32_t level, double* m
 
 void h2_free(h2_matrix A) {
   if (!A) return;
+  (void)hipSetDevice(A->device);
   if (A->stream) (void)hipStreamSynchronize(A->stream);
   for (auto& a : A->sf) a.release();
   A->lvl.release();
@@ -1685,18 +1747,18 @@ void h2_free(h2_matrix A) {
   A->rs.release();
   for (auto& a : A->tab) a.release();
   A->stab.release();
-  if (A->d_bres) (void)hipFree(A->d_bres);
+  if (A->d_bres) (void)h2::dev_free(A->d_bres);
   for (auto p : A->d_cpl)
-    if (p) (void)hipFree(p);
+    if (p) (void)h2::dev_free(p);
   for (auto p : A->d_emat)
-    if (p) (void)hipFree(p);
-  if (A->d_plan) (void)hipFree(A->d_plan);
+    if (p) (void)h2::dev_free(p);
+  if (A->d_plan) (void)h2::dev_free(A->d_plan);
   A->prof.release();
-  if (A->d_more) (void)hipFree(A->d_more);
+  if (A->d_more) (void)h2::dev_free(A->d_more);
   for (double* p : A->d_tau2)
-    if (p) (void)hipFree(p);
+    if (p) (void)h2::dev_free(p);
   for (double* p : A->d_tau2_f32)
-    if (p) (void)hipFree(p);
+    if (p) (void)h2::dev_free(p);
   if (A->h_more) (void)hipHostFree(A->h_more);
   if (A->own_stream) (void)hipStreamDestroy(A->own_stream);
   delete A;

@@ -44,6 +44,11 @@ class _Stats(C.Structure):
                 ("evals_f32", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
+# device allocator hook of h2_set_allocator: alloc(bytes, ctx) -> address, release(address, ctx)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise ImportError("libh2eig.so is not built (run __graft_entry__.build())")
@@ -110,6 +115,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.h2_get_gemm_tuning.argtypes = [C.c_int32, C.c_int32, C.c_int32, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
     lib.h2_set_max_shifts.restype = C.c_int
     lib.h2_set_max_shifts.argtypes = [C.c_void_p, C.c_int32]
+    lib.h2_set_allocator.restype = C.c_int
+    lib.h2_set_allocator.argtypes = [ALLOC_FN, RELEASE_FN, C.c_void_p]
     lib.h2_free.restype = None
     lib.h2_free.argtypes = [C.c_void_p]
     lib.h2s_create.restype = C.c_int
@@ -141,7 +148,7 @@ _lib = load_library()
 EXPORTED = ["h2_build", "h2_inertia", "h2_inertia_f32", "h2_set_mixed", "h2_kth_eig", "h2_norm", "h2_stats", "h2_set_stream", "h2_tree_perm",
             "h2_basis_ranks", "h2_level_stats", "h2_count", "h2_eigs_in", "h2_gap", "h2_matvec", "h2_kernel_matvec", "h2_kernel_matvec_noalloc",
             "h2_profile_enable", "h2_profile_classes", "h2_profile_class_name", "h2_profile_read", "h2_profile_bytes",
-            "h2_profile_level_ms", "h2_interval", "h2_capacity", "h2_set_max_shifts", "h2_level_dims",
+            "h2_profile_level_ms", "h2_interval", "h2_capacity", "h2_set_max_shifts", "h2_set_allocator", "h2_level_dims",
             "h2_set_gemm_tuning", "h2_get_gemm_tuning", "h2_free", "h2_last_error",
             "h2s_create", "h2s_latency", "h2_release_workspace", "h2s_add", "h2s_submit", "h2s_poll", "h2s_wait", "h2s_stats", "h2s_destroy"]
 
@@ -149,6 +156,35 @@ EXPORTED = ["h2_build", "h2_inertia", "h2_inertia_f32", "h2_set_mixed", "h2_kth_
 def _check(st: int):
     if st != H2_OK:
         raise H2EigError(st, _lib.h2_last_error().decode())
+
+
+# every pair of callbacks ever installed: a block keeps the allocator that made
+# it, so the wrappers must outlive the hook
+_allocators = []
+
+
+def set_allocator(alloc=None, release=None):
+    """Route the library's device allocations made from now on through
+    alloc(nbytes) -> device address (int; 0 or an exception: out of memory) and
+    release(address) (h2_set_allocator); both None restores hipMalloc/hipFree."""
+    if (alloc is None) != (release is None):
+        raise ValueError("alloc and release must both be given or both be None")
+    if alloc is None:
+        _check(_lib.h2_set_allocator(ALLOC_FN(), RELEASE_FN(), None))
+        return
+
+    def _alloc(nbytes, ctx):
+        try:
+            return int(alloc(int(nbytes)) or 0)
+        except Exception:
+            return 0
+
+    def _release(ptr, ctx):
+        release(int(ptr))
+
+    pair = (ALLOC_FN(_alloc), RELEASE_FN(_release))
+    _allocators.append(pair)
+    _check(_lib.h2_set_allocator(pair[0], pair[1], None))
 
 
 def set_gemm_tuning(layout: int, f32: int, bucket: int, grid: int, group_m: int, tile: int = 0):

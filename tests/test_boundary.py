@@ -166,3 +166,18 @@ def test_gemm_tuning_table(mod):
     finally:
         mod.set_gemm_tuning(1, 0, 3, g0, gm0, t0)
     assert mod.get_gemm_tuning(1, 0, 3) == (g0, gm0, t0)
+
+
+def test_allocator_hook_arguments(mod):
+    """h2_set_allocator: both callbacks or neither (no device work is done)."""
+    L = mod._lib
+    rel = mod.RELEASE_FN(lambda p, ctx: None)
+    al = mod.ALLOC_FN(lambda n, ctx: 0)
+    assert L.h2_set_allocator(mod.ALLOC_FN(), rel, None) == mod.H2_EINVAL
+    assert L.h2_set_allocator(al, mod.RELEASE_FN(), None) == mod.H2_EINVAL
+    assert L.h2_set_allocator(al, rel, None) == mod.H2_OK
+    assert L.h2_set_allocator(mod.ALLOC_FN(), mod.RELEASE_FN(), None) == mod.H2_OK
+    with pytest.raises(ValueError):
+        mod.set_allocator(lambda n: 0, None)
+    mod.set_allocator(lambda n: 0, lambda p: None)
+    mod.set_allocator()
