@@ -443,9 +443,9 @@ void build_near_blocks(h2_matrix A) {
       int i = bi[b0 + k], j = bj[b0 + k];
       Ref q{B_V, i, 0, 0, 0, 0}, a{B_HAT, k, 0, 0, 0, 0}, t{B_TMP, k, 0, 0, 0, 0}, o{B_BRES, b0 + k, 0, 0, 0, 0};
       Ref none{-1, 0, 0, 0, 0, 0};
-      GItem it1{t, none, msz[i], msz[j], 0, 0, 1.0, 0.0, -1};
+      GItem it1{t, none, msz[i], msz[j], 0, 0, 1.0, 0.0, -1, 0, 0};
       g1.add(it1, {GTerm{q, a, msz[i], -1, 0}});
-      GItem it2{o, none, msz[i], msz[j], 0, 0, 1.0, 0.0, -1};
+      GItem it2{o, none, msz[i], msz[j], 0, 0, 1.0, 0.0, -1, 0, 0};
       g2.add(it2, {GTerm{t, Ref{B_V, j, 0, 0, 0, 0}, msz[j], -1, 0}});
     }
     GItem *di1, *di2;

@@ -381,3 +381,21 @@ def test_library_schedule_carries_the_oracles_fill_in(plan_exe, n, leaf, eta, se
         else:
             assert carried <= sched, l
     assert any(got[("carried", l, i)] for l in range(T.L) for i in range(1 << l))   # fill-in is carried somewhere
+
+
+def test_host_sources_compile_without_warnings():
+    """The library's host C++ (tree and bases, schedule, level engine and C ABI,
+    serving loop) is clean under g++ -Wall -Wextra."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not found")
+    csrc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2311_08618_amd", "csrc")
+    procs = [(f, subprocess.Popen([gxx, "-std=c++17", "-fsyntax-only", "-Wall", "-Wextra", "-Werror",
+                                   "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", os.path.join(csrc, f)],
+                                  stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True))
+             for f in ("host.cpp", "plan.cpp", "engine.cpp", "server.cpp")]
+    for f, pr in procs:
+        out, err = pr.communicate(timeout=300)
+        assert pr.returncode == 0, (f, err[-3000:])
