@@ -1,8 +1,9 @@
 """Host-side logic (no device work): the autotuner's mapping of profiler
 symbols and capacities to table entries, the bench's use of a committed counter
-record only while it matches the kernel, the workload and the kernel source,
-the merge of separate query runs, and the inertia-record cache of the library."""
-import hashlib
+record only while it matches the GEMM's code and the workload, the merge of
+separate query runs, and the library's own host code against the oracle (the
+inertia-record cache, the cluster tree, the norm and kernel entries, the static
+schedule), also under sanitizers."""
 import math
 import os
 import re
