@@ -64,9 +64,10 @@ def test_argument_errors(lib):
 
 
 def test_tridiag_closed_form_large(lib):
-    # the largest size whose far fields the host builds exactly in seconds (the
-    # second-difference far field is one boundary point, which a strided sample
-    # of an ancestor's interaction cluster can miss)
+    # the second difference is exactly representable (its far field is one
+    # boundary point per block row), so the closed form fixes every count at
+    # any size; large pivot blocks are covered by the parity file's
+    # large-block cases
     n, leaf = 1 << 14, 64
     print("case tridiag n=%d leaf=%d" % (n, leaf), flush=True)
     A = lib.H2Matrix(W.line_points(n), W.K_TRIDIAG_1D, 2.0, leaf, 1.0, 1e-12, p0=1.0)
