@@ -264,12 +264,12 @@ def test_library_tree_equals_oracle(tree_exe, case):
     assert got_kb.shape == want.shape and np.all(np.abs(got_kb - want) <= tol), name
 
 
-def test_host_code_under_sanitizers(tree_exe, plan_exe, tmp_path):
+def test_host_code_under_sanitizers(tree_exe, plan_exe, matvec_exe, tmp_path):
     """The host code shared by the harnesses, built with the address and
     undefined-behaviour sanitizers (any report is fatal) and, separately, with
     the thread sanitizer: the record cache, the library's host.cpp (tree,
-    threaded norm estimate, kernel entries) and plan.cpp (the static schedule)
-    run clean and print what the plain build prints.  Host code only; no device
+    threaded norm estimate, kernel entries, threaded H^2 matvec) and plan.cpp
+    (the static schedule) run clean and print what the plain build prints.  Host code only; no device
     code is built here."""
     import shutil
     import subprocess
@@ -301,8 +301,12 @@ def test_host_code_under_sanitizers(tree_exe, plan_exe, tmp_path):
                                                                                    os.path.join(libdir, "csrc", src)]))
     for key, (obj, pr) in procs.items():
         assert pr.wait(timeout=600) == 0, key
+    mv_inp = _matvec_input(300, 32, W.K_LAPLACE, 1e-6, 2)[0]
+    plain_mv = subprocess.run([matvec_exe], input=mv_inp, capture_output=True, text=True, timeout=120,
+                              check=True).stdout
     runs = [("tree", "asan", ["host.cpp"], inp, plain), ("plan", "asan", ["plan.cpp", "host.cpp"], plan_inp, plain_plan),
-            ("tree", "tsan", ["host.cpp"], inp, plain)]
+            ("matvec", "asan", ["host.cpp"], mv_inp, plain_mv), ("tree", "tsan", ["host.cpp"], inp, plain),
+            ("matvec", "tsan", ["host.cpp"], mv_inp, plain_mv)]
     for harness, name, srcs, text, want in runs:
         exe = str(tmp_path / (harness + "_" + name))
         subprocess.run([gxx] + common + san[name] + ["-o", exe, os.path.join(here, harness + "_check.cpp")]
@@ -400,3 +404,64 @@ def test_host_sources_compile_without_warnings():
     for f, pr in procs:
         out, err = pr.communicate(timeout=300)
         assert pr.returncode == 0, (f, err[-3000:])
+
+
+def _matvec_input(n, leaf, kind, eps, seed):
+    """Input of tests/matvec_check.cpp for the oracle's H^2 matrix of n cube
+    points: (text, oracle H2, kernel, points, x)."""
+    from oracle.build import H2
+    from oracle.kernels import Kernel
+    from paper_2311_08618_amd import workloads as W
+    X = W.cube_points(n, seed)
+    k = Kernel(kind, 1e3)
+    H = H2(X, k, leaf, 1.0, eps)
+    L = H.tree.L
+    parts = ["%d 3 %d %r %d %r 0 0\n" % (n, leaf, 1.0, kind, 1e3), " ".join("%.17g" % v for v in X.ravel()), "\n"]
+    for l in range(1, L + 1):
+        for i in range(1 << l):
+            Q = np.asarray(H.Q[l][i])
+            m, r = H.m[l][i], H.r[l][i]
+            assert Q.shape == (m, m)
+            parts.append("%d %d\n" % (m, r))
+            parts.append(" ".join("%.17g" % v for v in Q.ravel(order="F")) + "\n")
+            cpl = [(j, np.asarray(H.C[l][(i, j)])) for j in H.tree.far[l][i]]
+            parts.append("%d\n" % len(cpl))
+            for j, C in cpl:
+                parts.append("%d %d " % (j, H.r[l][j]) + " ".join("%.17g" % v for v in C.ravel(order="F")) + "\n")
+    x = np.random.default_rng(seed + 1).standard_normal(n)
+    parts.append(" ".join("%.17g" % v for v in x) + "\n")
+    return "".join(parts), H, k, X, x
+
+
+@pytest.fixture(scope="module")
+def matvec_exe(tree_exe, tmp_path_factory):
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    here = os.path.dirname(os.path.abspath(__file__))
+    libdir = os.path.join(os.path.dirname(here), "paper_2311_08618_amd")
+    exe = str(tmp_path_factory.mktemp("matvec") / "matvec_check")
+    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+                    "-I/opt/rocm/include", "-o", exe, os.path.join(here, "matvec_check.cpp"),
+                    "-L" + libdir, "-l:libh2eig.so", "-Wl,-rpath," + libdir], check=True)
+    return exe
+
+
+@pytest.mark.parametrize("n,leaf,kind,eps,seed", [(1024, 64, 0, 1e-6, 0), (700, 32, 1, 1e-9, 4)])
+def test_library_host_matvec_equals_oracle_dense(matvec_exe, n, leaf, kind, eps, seed):
+    """The library's host H^2 matvec (the diagnostic behind h2_matvec, with
+    which the GPU tests measure ||A - A~||) applied to the oracle's bases,
+    transfer matrices and couplings equals the oracle's densely assembled A~
+    times x to rounding: both read the nested bases of Sec. 3.1 the same way
+    (skeleton columns last, transfer matrices on the children's skeletons,
+    couplings between skeletons), and the library adds the exact near field."""
+    import subprocess
+    text, H, k, X, x = _matvec_input(n, leaf, kind, eps, seed)
+    out = subprocess.run([matvec_exe], input=text, capture_output=True, text=True, timeout=300, check=True).stdout
+    y = np.array([float(v) for v in out.split()])
+    want = H.dense() @ x
+    assert y.shape == want.shape
+    assert np.linalg.norm(y - want) <= 1e-13 * np.linalg.norm(want), np.linalg.norm(y - want) / np.linalg.norm(want)
+    # and it is the H^2 matrix, not the exact one: the difference is the construction error
+    exact = k.dense(X) @ x
+    assert 0.0 < np.linalg.norm(y - exact) <= 10 * eps * H.normA * np.linalg.norm(x)
