@@ -355,11 +355,21 @@ def cpu_baseline(n_sample: int = 4096, shifts: int = 4, n_target: int = 262144) 
                     break
     except OSError:
         pass
+    # the host's FP64 matrix-multiply rate through the same BLAS (best of 3,
+    # 2048^3): context for the oracle's rate, whose block work runs on it
+    M = np.random.default_rng(0).standard_normal((2048, 2048))
+    best = math.inf
+    for _ in range(3):
+        t1 = time.perf_counter()
+        M @ M
+        best = min(best, time.perf_counter() - t1)
     return {
         "value": (1.0 / dt) * (n_sample / n_target),
         "unit": "evals/s",
         "cores": int(threads),
+        "nproc": os.cpu_count(),
         "cpu_model": cpu_model,
+        "host_dgemm_gflops": round(2.0 * 2048 ** 3 / best / 1e9, 1),
         "kind": "oracle",
         "sample": ("%d shifts of the oracle at n=%d (same kernel, leaf 256, eta 1, eps 1e-8), %.2f s per "
                    "shift, scaled linearly by n=%d/%d (the paper's O(n) per factorization; measured cost grows "
