@@ -88,3 +88,30 @@ def test_construction_error_full_size(lib, n, kind, eps):
     err = _power_error(A, 8)
     assert err <= 10 * eps * A.norm(), err / (eps * A.norm())
     A.close()
+
+
+@pytest.mark.xfail(strict=False, reason="open question: whether the GPU construction meets 10*eps*normA at the "
+                   "circle setting's eps (about 5e-14 of normA), where the factorization misses the Sec. 5.1 "
+                   "bound; a pass (XPASS) places that miss in the factorization, a failure in the construction")
+def test_construction_error_circle_tight_eps(lib):
+    """Sec. 5.1's circle setting (n = 512, leaf 32, 1/(r + 1e-3), A_ii = 1e3,
+    eps_H2 = 1e-10 absolute): ||A - A~||_2 of the GPU-built matrix, exactly,
+    from A~ applied to every unit vector (the host H^2 matvec) against the
+    dense kernel matrix; the oracle's construction at the same eps meets
+    10 * eps * normA (its own pin in tests/test_oracle_pins.py covers the rule)."""
+    n = 512
+    print("case construction error circle n=%d tight eps" % n, flush=True)
+    X = W.circle_points(n)
+    k = Kernel(W.K_REG_LAPLACE, 1e3, 1e-3)
+    A0 = lib.H2Matrix(X, W.K_REG_LAPLACE, 1e3, 32, 1.0, 1e-8, p0=1e-3)
+    eps = 1e-2 * 1e-8 / A0.norm()
+    A0.close()
+    A = lib.H2Matrix(X, W.K_REG_LAPLACE, 1e3, 32, 1.0, eps, p0=1e-3)
+    At = np.column_stack([A.matvec(e) for e in np.eye(n)])
+    err = float(np.linalg.norm(k.dense(X) - At, 2))
+    bound = 10 * eps * A.norm()
+    H = H2(X, k, 32, 1.0, eps)
+    err_oracle = float(np.linalg.norm(k.dense(X) - H.dense(), 2))
+    print("  ||A - A~||_2: gpu %.3e, oracle %.3e, bound %.3e" % (err, err_oracle, bound), flush=True)
+    A.close()
+    assert err <= bound, (err, err_oracle, bound)
