@@ -214,8 +214,9 @@ h2_status h2_get_gemm_tuning(int32_t layout, int32_t f32, int32_t bucket, int32_
  * H2_EDEVICE. */
 h2_status h2_release_workspace(h2_matrix A);
 
-/* Device-memory allocator of the library, process-wide (the handle owns HBM
- * through this hook; a framework points it at its own caching allocator).
+/* Device-memory allocator of the library, process-wide (plumbing: no passage
+ * of the paper defines it; the handle owns HBM through this hook, and a
+ * framework points it at its own caching allocator).
  * Every device allocation made after the call (resident H^2 data, plans,
  * factorization workspace, construction scratch) calls alloc(bytes, ctx),
  * which returns device memory of the current device aligned to at least 256
